@@ -1,0 +1,360 @@
+"""Pins for the FP64 CPU oracle, independent of the oracle's own formulas.
+
+Each test checks the oracle against something the mathematics fixes: a closed
+form derived from geometry or orbital mechanics, an exact invariance, the
+relation between the acceleration and the gradient of the potential energy,
+or a finite-difference derivative of the oracle's own forward map. A dropped
+term, a wrong sign or exponent, a swapped index or a wrong adjoint weight in
+the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2511_02655_amd import inputs
+
+
+def _rand_system(n, seed, spread=1.0, vscale=0.0):
+    g = np.random.Generator(np.random.PCG64(seed))
+    pos = g.uniform(-spread, spread, (3, n))
+    vel = g.normal(0.0, vscale, (3, n)) if vscale else np.zeros((3, n))
+    mass = g.uniform(0.5, 1.5, n)
+    return pos, vel, mass
+
+
+# ---------------------------------------------------------------- forces / potential
+
+@pytest.mark.parametrize("n", [3, 7, 64, 257])
+def test_ring_closed_form(oracle, n):
+    """Regular n-gon: by symmetry the acceleration is purely radial (inward) with
+    magnitude G m sum_k 2R sin^2(pi k/n) / (4R^2 sin^2(pi k/n) + eps^2)^{3/2}, since
+    the chord to the k-th neighbour is 2R sin(pi k/n) and its radial projection is
+    R(1 - cos(2 pi k/n)) = 2R sin^2(pi k/n); phi = -G m sum_k (4R^2 sin^2 + eps^2)^{-1/2}."""
+    R, m, G, eps = 1.3, 0.7, 1.7, 0.05
+    s = inputs.ring(n, R=R, m=m, phase=0.37)
+    shift = np.array([[0.25], [-1.5], [3.0]])
+    acc, pot = oracle.forces(s.pos + shift, s.mass, G=G, eps=eps)
+    k = np.arange(1, n)
+    sn2 = np.sin(np.pi * k / n) ** 2
+    a_rad = G * m * np.sum(2 * R * sn2 / (4 * R * R * sn2 + eps * eps) ** 1.5)
+    phi = -G * m * np.sum(1.0 / np.sqrt(4 * R * R * sn2 + eps * eps))
+    rhat = s.pos / R
+    radial = np.sum(acc * rhat, axis=0)
+    tang = np.stack([-rhat[1], rhat[0], np.zeros(n)])
+    np.testing.assert_allclose(radial, -a_rad, rtol=1e-12)
+    assert np.max(np.abs(np.sum(acc * tang, axis=0))) < 1e-12 * a_rad
+    assert np.max(np.abs(acc[2])) == 0.0
+    np.testing.assert_allclose(pot, phi, rtol=1e-13)
+
+
+def test_two_body_and_energy(oracle):
+    """Two bodies: a_1 = G m_2 d / (|d|^2+eps^2)^{3/2}, a_2 = -(m_1/m_2) a_1 (action-reaction),
+    E = 1/2 m1 v1^2 + 1/2 m2 v2^2 - G m1 m2 / sqrt(|d|^2 + eps^2)."""
+    G, eps = 2.5, 0.3
+    pos = np.array([[0.1, 1.2], [-0.4, 0.3], [0.5, -0.2]])
+    vel = np.array([[0.3, -0.1], [0.0, 0.2], [-0.7, 0.4]])
+    mass = np.array([0.8, 1.9])
+    d = pos[:, 1] - pos[:, 0]
+    s = d @ d + eps * eps
+    acc, pot = oracle.forces(pos, mass, G=G, eps=eps)
+    np.testing.assert_allclose(acc[:, 0], G * mass[1] * d / s ** 1.5, rtol=1e-14)
+    np.testing.assert_allclose(acc[:, 1], -G * mass[0] * d / s ** 1.5, rtol=1e-14)
+    np.testing.assert_allclose(pot, [-G * mass[1] / math.sqrt(s), -G * mass[0] / math.sqrt(s)], rtol=1e-14)
+    em = oracle.energy_momentum(pos, vel, mass, G=G, eps=eps)
+    ke = 0.5 * mass[0] * vel[:, 0] @ vel[:, 0] + 0.5 * mass[1] * vel[:, 1] @ vel[:, 1]
+    np.testing.assert_allclose(em[0], ke, rtol=1e-14)
+    np.testing.assert_allclose(em[1], -G * mass[0] * mass[1] / math.sqrt(s), rtol=1e-14)
+    np.testing.assert_allclose(em[2:], vel @ mass, rtol=1e-14)
+
+
+def test_acceleration_is_minus_gradient_of_potential_energy(oracle):
+    """m_k a_k = -dU/dx_k with U = PE = 1/2 sum m phi (central differences of the
+    oracle's own potential energy). Ties a and phi together: a wrong exponent or
+    sign in either fails."""
+    pos, vel, mass = _rand_system(6, 11)
+    G, eps, h = 1.3, 0.2, 1e-5
+    acc, _ = oracle.forces(pos, mass, G=G, eps=eps)
+    grad = np.zeros_like(pos)
+    for c in range(3):
+        for k in range(pos.shape[1]):
+            p = pos.copy(); p[c, k] += h
+            up = oracle.energy_momentum(p, vel, mass, G=G, eps=eps)[1]
+            p[c, k] -= 2 * h
+            um = oracle.energy_momentum(p, vel, mass, G=G, eps=eps)[1]
+            grad[c, k] = (up - um) / (2 * h)
+    np.testing.assert_allclose(mass * acc, -grad, rtol=1e-7, atol=1e-9)
+
+
+def test_newton_third_law(oracle):
+    """sum_i m_i a_i = 0 (every pair force appears with both signs)."""
+    pos, _, mass = _rand_system(500, 12)
+    acc, _ = oracle.forces(pos, mass, eps=1e-2)
+    total = (acc * mass).sum(axis=1)
+    scale = np.abs(acc * mass).sum()
+    assert np.max(np.abs(total)) < 1e-13 * scale
+
+
+def test_scaling_laws(oracle):
+    """a(c x, c eps) = a(x, eps)/c^2, phi(c x, c eps) = phi/c; a(s m) = s a; a(G) linear in G."""
+    pos, _, mass = _rand_system(40, 13)
+    a0, p0 = oracle.forces(pos, mass, G=1.0, eps=0.05)
+    c = 3.7
+    a1, p1 = oracle.forces(c * pos, mass, G=1.0, eps=0.05 * c)
+    np.testing.assert_allclose(a1, a0 / c ** 2, rtol=1e-12)
+    np.testing.assert_allclose(p1, p0 / c, rtol=1e-12)
+    a2, p2 = oracle.forces(pos, 2.5 * mass, G=1.0, eps=0.05)
+    np.testing.assert_allclose(a2, 2.5 * a0, rtol=1e-13)
+    a3, p3 = oracle.forces(pos, mass, G=0.3, eps=0.05)
+    np.testing.assert_allclose(a3, 0.3 * a0, rtol=1e-13)
+
+
+def test_rotation_translation_permutation(oracle):
+    """a(Q x + t) = Q a(x); permuting particles permutes the output."""
+    pos, _, mass = _rand_system(30, 14)
+    a0, p0 = oracle.forces(pos, mass, eps=0.05)
+    th = 0.7
+    Q = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1.0]])
+    Q = Q @ np.array([[1, 0, 0], [0, math.cos(0.3), -math.sin(0.3)], [0, math.sin(0.3), math.cos(0.3)]])
+    a1, p1 = oracle.forces(Q @ pos + np.array([[1.0], [-2.0], [0.5]]), mass, eps=0.05)
+    np.testing.assert_allclose(a1, Q @ a0, rtol=1e-11, atol=1e-12 * np.abs(a0).max())
+    np.testing.assert_allclose(p1, p0, rtol=1e-12)
+    perm = np.random.Generator(np.random.PCG64(3)).permutation(30)
+    a2, p2 = oracle.forces(pos[:, perm], mass[perm], eps=0.05)
+    np.testing.assert_allclose(a2, a0[:, perm], rtol=1e-12, atol=1e-13 * np.abs(a0).max())
+
+
+def test_far_field_monopole(oracle):
+    """A light probe at distance D from a compact cluster of mass M feels
+    G M / D^2 towards the cluster's centre of mass, up to O((size/D)^2)."""
+    g = np.random.Generator(np.random.PCG64(15))
+    n = 200
+    cl = g.uniform(-0.01, 0.01, (3, n))
+    m = g.uniform(0.5, 1.5, n) / n
+    cl -= (cl * m).sum(axis=1, keepdims=True) / m.sum()
+    D = 10.0
+    probe = np.array([[D * 0.6], [D * 0.8], [0.0]])
+    pos = np.concatenate([cl, probe], axis=1)
+    mass = np.concatenate([m, [1e-9]])
+    acc, pot = oracle.forces(pos, mass, eps=1e-6)
+    M = m.sum()
+    expect = -M * probe[:, 0] / D ** 3
+    assert np.linalg.norm(acc[:, -1] - expect) < 1e-5 * np.linalg.norm(expect)
+    np.testing.assert_allclose(pot[-1], -M / D, rtol=1e-6)
+
+
+def test_high_precision_brute_force(oracle):
+    """Rounding check on a tiny system: the oracle agrees with a 40-digit evaluation."""
+    import mpmath
+    mpmath.mp.dps = 40
+    pos, _, mass = _rand_system(5, 16)
+    acc, pot = oracle.forces(pos, mass, G=1.0, eps=0.1)
+    for i in range(5):
+        a = [mpmath.mpf(0)] * 3
+        ph = mpmath.mpf(0)
+        for j in range(5):
+            if j == i:
+                continue
+            d = [mpmath.mpf(pos[c, j]) - mpmath.mpf(pos[c, i]) for c in range(3)]
+            s = d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + mpmath.mpf(0.1) ** 2
+            for c in range(3):
+                a[c] += mpmath.mpf(mass[j]) * d[c] / s ** 1.5
+            ph -= mpmath.mpf(mass[j]) / mpmath.sqrt(s)
+        for c in range(3):
+            assert abs(float(a[c]) - acc[c, i]) <= 1e-14 * max(1.0, abs(float(a[c])))
+        assert abs(float(ph) - pot[i]) <= 1e-14 * abs(float(ph))
+
+
+def test_empty_and_single(oracle):
+    acc, pot = oracle.forces(np.zeros((3, 1)), np.ones(1), eps=0.1)
+    assert np.all(acc == 0) and np.all(pot == 0)
+    acc, pot = oracle.forces(np.zeros((3, 0)), np.zeros(0), eps=0.1)
+    assert acc.shape == (3, 0)
+
+
+# ---------------------------------------------------------------- integrator
+
+def _kepler_relative(a, e, GM, t):
+    """Relative position of a Kepler orbit started at pericentre (x along +x, motion +y)."""
+    n_mean = math.sqrt(GM / a ** 3)
+    Mn = n_mean * t
+    E = Mn
+    for _ in range(60):
+        E = E - (E - e * math.sin(E) - Mn) / (1 - e * math.cos(E))
+    return np.array([a * (math.cos(E) - e), a * math.sqrt(1 - e * e) * math.sin(E), 0.0])
+
+
+def test_kdk_kepler_second_order(oracle):
+    """Eccentric Kepler orbit (e = 0.5, eps ~ 0): the KDK relative position after a fixed
+    time converges to the solution of Kepler's equation with order 2 (error ratio 4 on
+    halving dt)."""
+    m1, m2, a, e = 0.6, 0.4, 1.0, 0.5
+    T = 1.7
+    errs = []
+    for dt in [2e-3, 1e-3, 5e-4]:
+        s = inputs.kepler_pair(m1, m2, a, e)
+        steps = int(round(T / dt))
+        x, v, _, _ = oracle.kdk(s.pos, s.vel, s.mass, dt, steps, eps=1e-7)
+        rel = x[:, 1] - x[:, 0]
+        errs.append(np.linalg.norm(rel - _kepler_relative(a, e, 1.0, steps * dt)))
+    assert errs[1] < 1e-4
+    for r in (errs[0] / errs[1], errs[1] / errs[2]):
+        assert 3.8 < r < 4.2, errs
+
+
+def test_kdk_softened_circular_orbit(oracle):
+    """Two bodies on a circular orbit of separation D under the softened force have
+    angular speed w^2 = G M / (D^2 + eps^2)^{3/2} exactly; the KDK phase error is O(dt^2)."""
+    m1, m2, D, eps, G = 0.7, 0.3, 1.0, 0.3, 1.0
+    M = m1 + m2
+    w = math.sqrt(G * M / (D * D + eps * eps) ** 1.5)
+    pos = np.array([[-m2 / M * D, m1 / M * D], [0, 0], [0, 0.0]])
+    vel = np.array([[0, 0], [-m2 / M * D * w, m1 / M * D * w], [0, 0.0]])
+    mass = np.array([m1, m2])
+    T = 2.0
+    errs = []
+    for dt in [4e-3, 2e-3]:
+        steps = int(round(T / dt))
+        x, _, _, _ = oracle.kdk(pos, vel, mass, dt, steps, G=G, eps=eps)
+        rel = x[:, 1] - x[:, 0]
+        expect = D * np.array([math.cos(w * T), math.sin(w * T), 0.0])
+        errs.append(np.linalg.norm(rel - expect))
+    assert errs[1] < 1e-5
+    assert 3.8 < errs[0] / errs[1] < 4.2
+
+
+def test_kdk_time_reversal_and_conservation(oracle):
+    """KDK is time-reversible: K steps, flip v, K steps returns to the start.
+    Linear and angular momentum are conserved to rounding; the energy error is
+    second order in dt and does not grow secularly."""
+    pos, vel, mass = _rand_system(50, 17, vscale=0.3)
+    eps, dt, K = 0.05, 2e-3, 40
+    x, v, _, energy = oracle.kdk(pos, vel, mass, dt, K, eps=eps, want_energy=True)
+    xb, vb, _, _ = oracle.kdk(x, -v, mass, dt, K, eps=eps)
+    np.testing.assert_allclose(xb, pos, atol=1e-12)
+    np.testing.assert_allclose(-vb, vel, atol=1e-11)
+    P0 = vel @ mass
+    P1 = v @ mass
+    scale = np.abs(vel * mass).sum()
+    assert np.max(np.abs(P1 - P0)) < 1e-14 * scale
+    np.testing.assert_allclose(energy[:, 2:], np.tile(energy[0, 2:], (K + 1, 1)), atol=1e-14 * scale)
+    L0 = np.cross(pos.T, (vel * mass).T).sum(axis=0)
+    L1 = np.cross(x.T, (v * mass).T).sum(axis=0)
+    assert np.max(np.abs(L1 - L0)) < 1e-13 * np.abs(np.cross(pos.T, (vel * mass).T)).sum()
+    E = energy[:, 0] + energy[:, 1]
+    d1 = np.max(np.abs(E - E[0]))
+    _, _, _, energy2 = oracle.kdk(pos, vel, mass, dt / 2, 2 * K, eps=eps, want_energy=True)
+    E2 = energy2[:, 0] + energy2[:, 1]
+    d2 = np.max(np.abs(E2 - E2[0]))
+    assert 3.0 < d1 / d2 < 5.0
+
+
+def test_kdk_traj_matches_steps(oracle):
+    """traj[k] is the state after k steps (restart consistency)."""
+    pos, vel, mass = _rand_system(20, 18, vscale=0.2)
+    x, v, traj, _ = oracle.kdk(pos, vel, mass, 1e-3, 6, eps=0.05, want_traj=True)
+    x3, v3, _, _ = oracle.kdk(pos, vel, mass, 1e-3, 3, eps=0.05)
+    np.testing.assert_array_equal(traj[3], x3)
+    np.testing.assert_array_equal(traj[0], pos)
+    np.testing.assert_array_equal(traj[6], x)
+
+
+def test_plummer_energy_statistics(oracle):
+    """Plummer sphere (G = M = a = 1): potential energy close to -3 pi / 32 and virial
+    ratio 2 KE / |PE| close to 1 (statistical; truncation at 10 a and softening shift
+    both by about a percent)."""
+    s = inputs.plummer(8192, 21)
+    em = oracle.energy_momentum(s.pos, s.vel, s.mass, eps=1e-3)
+    assert abs(em[1] / (-3 * math.pi / 32) - 1) < 0.04
+    assert abs(2 * em[0] / abs(em[1]) - 1) < 0.06
+    assert np.max(np.abs(em[2:])) < 1e-14
+
+
+# ---------------------------------------------------------------- adjoint
+
+def test_force_vjp_matches_finite_differences(oracle):
+    """gx = d/dx (sum lam . a), gm = d/dm (sum lam . a), checked along random directions
+    by central differences of the oracle's forward forces (no use of the VJP formula)."""
+    g = np.random.Generator(np.random.PCG64(31))
+    pos, _, mass = _rand_system(12, 32)
+    G, eps = 1.4, 0.15
+    lam = g.normal(size=(3, 12))
+    gx, gm = oracle.force_vjp(pos, mass, lam, G=G, eps=eps)
+
+    def f(p, m):
+        a, _ = oracle.forces(p, m, G=G, eps=eps)
+        return float(np.sum(lam * a))
+
+    for trial in range(4):
+        dx = g.normal(size=(3, 12))
+        dm = g.normal(size=12)
+        h = 1e-6
+        fd_x = (f(pos + h * dx, mass) - f(pos - h * dx, mass)) / (2 * h)
+        fd_m = (f(pos, mass + h * dm) - f(pos, mass - h * dm)) / (2 * h)
+        assert abs(fd_x - np.sum(gx * dx)) < 1e-7 * max(1.0, abs(fd_x))
+        assert abs(fd_m - np.sum(gm * dm)) < 1e-7 * max(1.0, abs(fd_m))
+
+
+def test_force_vjp_full_jacobian(oracle):
+    """Full Jacobian of a (tiny n) by finite differences, transposed onto lam."""
+    g = np.random.Generator(np.random.PCG64(33))
+    pos, _, mass = _rand_system(4, 34)
+    lam = g.normal(size=(3, 4))
+    gx, gm = oracle.force_vjp(pos, mass, lam, eps=0.2)
+    h = 1e-6
+    J = np.zeros((12, 16))
+    for c in range(3):
+        for k in range(4):
+            p = pos.copy(); p[c, k] += h
+            ap, _ = oracle.forces(p, mass, eps=0.2)
+            p[c, k] -= 2 * h
+            am, _ = oracle.forces(p, mass, eps=0.2)
+            J[:, c * 4 + k] = ((ap - am) / (2 * h)).ravel()
+    for k in range(4):
+        m = mass.copy(); m[k] += h
+        ap, _ = oracle.forces(pos, m, eps=0.2)
+        m[k] -= 2 * h
+        am, _ = oracle.forces(pos, m, eps=0.2)
+        J[:, 12 + k] = ((ap - am) / (2 * h)).ravel()
+    jt = J.T @ lam.ravel()
+    np.testing.assert_allclose(gx.ravel(), jt[:12], rtol=1e-6, atol=1e-8)
+    np.testing.assert_allclose(gm, jt[12:], rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 7])
+def test_rollout_adjoint_matches_finite_differences(oracle, steps):
+    """Gradient of L = <cx, x_K> + <cv, v_K> w.r.t. x0, v0, m from the discrete adjoint
+    equals central differences of the oracle's own rollout along random directions."""
+    g = np.random.Generator(np.random.PCG64(40 + steps))
+    pos, vel, mass = _rand_system(8, 41, vscale=0.3)
+    G, eps, dt = 1.0, 0.1, 0.02
+    cx = g.normal(size=(3, 8))
+    cv = g.normal(size=(3, 8))
+    gx, gv, gm = oracle.rollout_adjoint(pos, vel, mass, dt, steps, cx, cv, G=G, eps=eps)
+
+    def L(p, v, m):
+        x, vv, _, _ = oracle.kdk(p, v, m, dt, steps, G=G, eps=eps)
+        return float(np.sum(cx * x) + np.sum(cv * vv))
+
+    h = 1e-6
+    for _ in range(3):
+        dx, dv, dm = g.normal(size=(3, 8)), g.normal(size=(3, 8)), g.normal(size=8)
+        for (args_p, args_m, grad, d) in [
+            ((pos + h * dx, vel, mass), (pos - h * dx, vel, mass), gx, dx),
+            ((pos, vel + h * dv, mass), (pos, vel - h * dv, mass), gv, dv),
+            ((pos, vel, mass + h * dm), (pos, vel, mass - h * dm), gm, dm),
+        ]:
+            fd = (L(*args_p) - L(*args_m)) / (2 * h)
+            assert abs(fd - np.sum(grad * d)) < 1e-7 * max(1.0, abs(fd)), (fd, np.sum(grad * d))
+
+
+def test_msd_loss_and_gradient(oracle):
+    g = np.random.Generator(np.random.PCG64(50))
+    x = g.normal(size=(3, 9))
+    y = g.normal(size=(3, 9))
+    val, grad = oracle.loss_msd(x, y)
+    assert abs(val - np.sum((x - y) ** 2) / 9) < 1e-14
+    d = g.normal(size=(3, 9))
+    h = 1e-6
+    fd = (oracle.loss_msd(x + h * d, y)[0] - oracle.loss_msd(x - h * d, y)[0]) / (2 * h)
+    assert abs(fd - np.sum(grad * d)) < 1e-8
