@@ -1,0 +1,191 @@
+/*
+ * nbody.h - C ABI of libnbody.so, the MI355X (gfx950) all-pairs N-body hot path.
+ *
+ * What is computed (per system; systems never interact):
+ *   The paper's N-body miniapp evaluates the force between every pair of
+ *   particles, N_p^2 pair interactions per evaluation (Sec. IV-B), moves the
+ *   particles with a Verlet half-step integrator (Sec. II-A) and reduces the
+ *   total energy over all particles inside the force pass (Sec. V, with and
+ *   without that reduction). This library keeps that structure with
+ *   Plummer-softened gravity as the pair law in place of Eq. (1):
+ *       d_ij  = x_j - x_i,   s_ij = |d_ij|^2 + eps^2
+ *       a_i   =  G sum_{j != i} m_j d_ij s_ij^{-3/2}
+ *       phi_i = -G sum_{j != i} m_j s_ij^{-1/2}
+ *   and reads the Verlet half-step scheme as kick-drift-kick leapfrog with
+ *   force reuse. Energy/momentum per system: KE = 1/2 sum m|v|^2,
+ *   PE = 1/2 sum m phi, P = sum m v (all reduced in FP64, deterministically,
+ *   without atomics).
+ *
+ * Conventions (all entry points):
+ *   - Array pointers are DEVICE pointers owned by the caller, unless a comment
+ *     says HOST. Positions, velocities, accelerations and their gradients are
+ *     SoA planes of doubles, [3][n] (all x, then all y, then all z).
+ *   - The library allocates no device memory. Scratch space comes from the
+ *     caller's workspace (nbody_config.workspace), whose size
+ *     nbody_workspace_size() returns.
+ *   - Calls are asynchronous on nbody_config.stream (a hipStream_t; NULL = the
+ *     null stream). Host arguments (offsets, the config itself) may be reused
+ *     as soon as the call returns.
+ *   - Every call returns an nbody_status. Argument errors are detected on the
+ *     host before any HIP call and leave device memory untouched; a failed
+ *     launch returns NBODY_ERR_DEVICE. nbody_last_error() describes the last
+ *     failure of the calling thread. Device faults surface at the caller's
+ *     next synchronisation.
+ *   - n == 0 is valid and does nothing.
+ *   - Results are deterministic: the same inputs, configuration and tile
+ *     table give bitwise-equal outputs (fixed summation orders, no atomics in
+ *     any arithmetic).
+ *   - Outputs must not alias inputs except where a parameter is documented as
+ *     in/out.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBODY_ABI_VERSION 1
+
+typedef enum {
+  NBODY_OK = 0,
+  NBODY_ERR_INVALID_ARG = 1, /* bad pointer, size, softening, step, offsets ... */
+  NBODY_ERR_DEVICE = 2,      /* a HIP call failed (message in nbody_last_error) */
+  NBODY_ERR_UNSUPPORTED = 3, /* valid request this build cannot serve */
+  NBODY_ERR_WORKSPACE = 4    /* workspace missing or smaller than required */
+} nbody_status;
+
+/* Arithmetic of the pair interactions. State, position/velocity updates and
+ * every reduction are FP64 in all modes.
+ *   NBODY_FP64       pair math in double.
+ *   NBODY_FP32       pair math in float; per-particle float accumulators.
+ *   NBODY_FP32_COMP  pair math in float; per-particle accumulation compensated:
+ *                    a float (hi, lo) pair per component, the partial sum of
+ *                    each staged j-tile folded into it with an error-free
+ *                    TwoSum; the result is (double)hi + (double)lo. */
+typedef enum { NBODY_FP64 = 0, NBODY_FP32 = 1, NBODY_FP32_COMP = 2 } nbody_precision;
+
+/* config.flags */
+#define NBODY_FLAG_LOOP_SYSTEMS 1u /* batched calls: one plain launch per system
+                                      instead of one persistent launch (baseline) */
+
+typedef struct {
+  int32_t abi_version;     /* must equal NBODY_ABI_VERSION */
+  int32_t precision;       /* nbody_precision */
+  double G;                /* gravitational constant, finite */
+  double eps;              /* Plummer softening length; eps > 0, and eps >= 1e-10 for
+                              the FP32 modes (eps^2 must be a normal float) */
+  int64_t n_systems;       /* >= 1 */
+  const int64_t *offsets;  /* HOST, n_systems + 1 entries: offsets[0] = 0,
+                              non-decreasing, offsets[n_systems] = n. System s owns
+                              particles offsets[s] .. offsets[s+1]-1. May be NULL
+                              only when n_systems == 1. */
+  void *workspace;         /* DEVICE scratch, caller-owned, 256-byte aligned */
+  size_t workspace_bytes;  /* >= nbody_workspace_size(...) for the call */
+  void *stream;            /* hipStream_t (NULL = null stream) */
+  uint32_t flags;          /* NBODY_FLAG_* */
+  uint32_t reserved;       /* must be 0 */
+} nbody_config;
+
+/* Bytes of workspace any call below needs for n particles (in cfg's systems),
+ * a rollout/backward of `steps` steps with checkpoints every `ckpt_every`
+ * steps (pass 0, 0 when no rollout/backward is planned). The size depends on
+ * cfg->precision, cfg->n_systems/offsets and the tile table.
+ * Returns NBODY_OK and writes *bytes. */
+int nbody_workspace_size(const nbody_config *cfg, int64_t n, int64_t steps, int64_t ckpt_every,
+                         size_t *bytes);
+
+/* All-pairs acceleration and, optionally, potential of every particle
+ * (the force pass of Sec. IV-B; pot != NULL adds the fused per-particle
+ * potential that the Sec. V energy reduction needs, pot == NULL is the
+ * variant without it).
+ *   pos  [3][n] double, mass [n] double (any finite values; mass may be 0)
+ *   acc  [3][n] double, out
+ *   pot  [n] double, out, nullable */
+int nbody_forces(const nbody_config *cfg, int64_t n, const double *pos, const double *mass,
+                 double *acc, double *pot);
+
+/* One kick-drift-kick step of size dt with force reuse (the Verlet
+ * half-step update of Sec. II-A):
+ *   v += dt/2 a;  x += dt v;  a = a(x);  v += dt/2 a
+ *   pos, vel [3][n] in/out; acc [3][n] in: a(x_n), out: a(x_{n+1}). */
+int nbody_step(const nbody_config *cfg, int64_t n, double dt, double *pos, double *vel,
+               const double *mass, double *acc);
+
+/* `steps` KDK steps (steps >= 0), state in place.
+ *   acc   in: a(x_0) (e.g. from nbody_forces), out: a(x_steps)
+ *   ckpt  nullable, [steps/ckpt_every + 1][6][n] doubles: (x planes, v planes)
+ *         at steps 0, ckpt_every, 2 ckpt_every, ... (ckpt_every >= 1 when given;
+ *         ignored when NULL)
+ *   energy_trace nullable, [steps + 1][n_systems][5] doubles: (KE, PE, Px, Py, Pz)
+ *         of every system at every integer step (costs the potential in every
+ *         force pass). */
+int nbody_rollout(const nbody_config *cfg, int64_t n, double dt, int64_t steps, int64_t ckpt_every,
+                  double *pos, double *vel, const double *mass, double *acc, double *ckpt,
+                  double *energy_trace);
+
+/* Energy and linear momentum of every system (the energy reduction of Sec. V).
+ *   pot  nullable: the per-particle potential from nbody_forces; when NULL it is
+ *        computed here with one force pass at cfg->precision.
+ *   out  [n_systems][5] double: KE, PE, Px, Py, Pz. */
+int nbody_energy_momentum(const nbody_config *cfg, int64_t n, const double *pos, const double *vel,
+                          const double *mass, const double *pot, double *out);
+
+/* Reverse-mode gradient of a function of the final state of a rollout made by
+ * nbody_rollout(cfg, n, dt, steps, ckpt_every, ...) with the same cfg:
+ * the exact adjoint of the discrete KDK map (discretise, then differentiate).
+ *   ckpt        [steps/ckpt_every + 1][6][n] checkpoints written by that rollout
+ *   gpos_final, gvel_final [3][n]: dL/dx_steps, dL/dv_steps
+ *   gpos0, gvel0 [3][n] out: dL/dx_0, dL/dv_0;  gmass [n] out: dL/dm.
+ * Positions between checkpoints are recomputed (bitwise equal to the forward
+ * pass). Each step costs one adjoint pair pass
+ *   gx_k += G sum_j T(d_kj)(m_k l_j - m_j l_k),  gm_k += -G sum_j s^{-3/2} d_kj . l_j,
+ *   T(d) = s^{-3/2} I - 3 s^{-5/2} d d^T,  l = w * (velocity cotangent)
+ * at cfg->precision, plus one recomputed force pass. */
+int nbody_rollout_backward(const nbody_config *cfg, int64_t n, double dt, int64_t steps,
+                           int64_t ckpt_every, const double *mass, const double *ckpt,
+                           const double *gpos_final, const double *gvel_final, double *gpos0,
+                           double *gvel0, double *gmass);
+
+/* ---- tile table (written by the autotuner; built-in defaults otherwise) ---- */
+
+typedef enum {
+  NBODY_KERNEL_FORCE = 0,   /* single-system force pass */
+  NBODY_KERNEL_ADJOINT = 1, /* single-system adjoint pass */
+  NBODY_KERNEL_FORCE_BATCHED = 2,
+  NBODY_KERNEL_ADJOINT_BATCHED = 3
+} nbody_kernel;
+
+typedef struct {
+  int32_t kernel;    /* nbody_kernel */
+  int32_t precision; /* nbody_precision */
+  int64_t n_min;     /* entry applies when n_min <= n <= n_max (n: particles of the
+                        system for single-system kernels, largest system for batched) */
+  int64_t n_max;
+  int32_t variant;   /* index into nbody_tile_variants() for (kernel, precision) */
+  int32_t j_split;   /* single-system: number of j-ranges (>= 1, results summed in a
+                        fixed order); batched: j-chunk length of one work unit */
+} nbody_tile_entry;
+
+/* Replace the tile table (copied; count 0 restores the built-in defaults). */
+int nbody_set_tile_table(const nbody_tile_entry *entries, int64_t count);
+
+/* Number of compiled tile variants for (kernel, precision); writes up to `cap`
+ * descriptions "bs=256,i=2,tj=256" (NUL-separated) into `buf` when non-NULL. */
+int nbody_tile_variants(int32_t kernel, int32_t precision, char *buf, size_t cap);
+
+/* The (variant, j_split) the library would use for a call of size n. */
+int nbody_tile_lookup(int32_t kernel, int32_t precision, int64_t n, int32_t *variant,
+                      int32_t *j_split);
+
+/* ---- diagnostics ---- */
+const char *nbody_last_error(void); /* thread-local, valid until the next call on this thread */
+int nbody_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

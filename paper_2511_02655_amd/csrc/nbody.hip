@@ -1,0 +1,985 @@
+// libnbody.so: host side of the C ABI declared in include/nbody.h.
+//
+// Argument validation (host only, before any HIP call), workspace planning,
+// tile-table lookup, kernel launches, and the rollout / reverse-rollout drivers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nbody.h"
+#include "nbody_kernels.hpp"
+
+using namespace nbody;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(NBODY_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK(what)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess) return fail(NBODY_ERR_DEVICE, "launch of %s failed: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(expr)              \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != NBODY_OK) return rc_; \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ tile variants
+
+using ForceFn = void (*)(dim3, hipStream_t, const void* jarr, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
+                         int64_t jchunk, double eps2, const ForceOut&);
+using ForceBatchedFn = void (*)(dim3, hipStream_t, const void* jarr, const WorkUnit* units, int32_t n_units,
+                                int32_t* counter, double eps2, const ForceOut&);
+using AdjFn = void (*)(dim3, hipStream_t, const void* jadj, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
+                       int64_t jchunk, double eps2, const AdjOut&);
+using AdjBatchedFn = void (*)(dim3, hipStream_t, const void* jadj, const WorkUnit* units, int32_t n_units,
+                              int32_t* counter, double eps2, const AdjOut&);
+
+template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
+void launch_force(dim3 g, hipStream_t st, const void* jarr, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
+                  int64_t jchunk, double eps2, const ForceOut& o) {
+  hipLaunchKernelGGL((force_kernel<T, BS, I, TJ, POT, COMP>), g, dim3(BS), 0, st,
+                     (const typename Vec4<T>::type*)jarr, i0, i1, j0, j1, jchunk, (T)eps2, o);
+}
+template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
+void launch_force_batched(dim3 g, hipStream_t st, const void* jarr, const WorkUnit* units, int32_t n_units,
+                          int32_t* counter, double eps2, const ForceOut& o) {
+  hipLaunchKernelGGL((force_batched_kernel<T, BS, I, TJ, POT, COMP>), g, dim3(BS), 0, st,
+                     (const typename Vec4<T>::type*)jarr, units, n_units, counter, (T)eps2, o);
+}
+template <typename T, int BS, int I, int TJ, bool COMP>
+void launch_adj(dim3 g, hipStream_t st, const void* jadj, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
+                int64_t jchunk, double eps2, const AdjOut& o) {
+  hipLaunchKernelGGL((adjoint_kernel<T, BS, I, TJ, COMP>), g, dim3(BS), 0, st,
+                     (const typename Vec4<T>::type*)jadj, i0, i1, j0, j1, jchunk, (T)eps2, o);
+}
+template <typename T, int BS, int I, int TJ, bool COMP>
+void launch_adj_batched(dim3 g, hipStream_t st, const void* jadj, const WorkUnit* units, int32_t n_units,
+                        int32_t* counter, double eps2, const AdjOut& o) {
+  hipLaunchKernelGGL((adjoint_batched_kernel<T, BS, I, TJ, COMP>), g, dim3(BS), 0, st,
+                     (const typename Vec4<T>::type*)jadj, units, n_units, counter, (T)eps2, o);
+}
+
+// Kernel pointers for occupancy queries of the persistent kernels.
+template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
+const void* force_batched_ptr() { return (const void*)&force_batched_kernel<T, BS, I, TJ, POT, COMP>; }
+template <typename T, int BS, int I, int TJ, bool COMP>
+const void* adj_batched_ptr() { return (const void*)&adjoint_batched_kernel<T, BS, I, TJ, COMP>; }
+
+struct ForceVariant {
+  int bs, i, tj;
+  ForceFn fn[2][2];               // [pot][comp]
+  ForceBatchedFn bfn[2][2];
+  const void* (*bptr[2][2])();
+};
+struct AdjVariant {
+  int bs, i, tj;
+  AdjFn fn[2];                    // [comp]
+  AdjBatchedFn bfn[2];
+  const void* (*bptr[2])();
+};
+
+#define FV32(BS, I, TJ)                                                                                    \
+  ForceVariant {                                                                                           \
+    BS, I, TJ,                                                                                             \
+        {{launch_force<float, BS, I, TJ, false, false>, launch_force<float, BS, I, TJ, false, true>},     \
+         {launch_force<float, BS, I, TJ, true, false>, launch_force<float, BS, I, TJ, true, true>}},      \
+        {{launch_force_batched<float, BS, I, TJ, false, false>, launch_force_batched<float, BS, I, TJ, false, true>}, \
+         {launch_force_batched<float, BS, I, TJ, true, false>, launch_force_batched<float, BS, I, TJ, true, true>}},  \
+        {{force_batched_ptr<float, BS, I, TJ, false, false>, force_batched_ptr<float, BS, I, TJ, false, true>},       \
+         {force_batched_ptr<float, BS, I, TJ, true, false>, force_batched_ptr<float, BS, I, TJ, true, true>}}         \
+  }
+#define FV64(BS, I, TJ)                                                                                    \
+  ForceVariant {                                                                                           \
+    BS, I, TJ,                                                                                             \
+        {{launch_force<double, BS, I, TJ, false, false>, nullptr},                                         \
+         {launch_force<double, BS, I, TJ, true, false>, nullptr}},                                         \
+        {{launch_force_batched<double, BS, I, TJ, false, false>, nullptr},                                 \
+         {launch_force_batched<double, BS, I, TJ, true, false>, nullptr}},                                 \
+        {{force_batched_ptr<double, BS, I, TJ, false, false>, nullptr},                                    \
+         {force_batched_ptr<double, BS, I, TJ, true, false>, nullptr}}                                     \
+  }
+#define AV32(BS, I, TJ)                                                                                    \
+  AdjVariant {                                                                                             \
+    BS, I, TJ, {launch_adj<float, BS, I, TJ, false>, launch_adj<float, BS, I, TJ, true>},                 \
+        {launch_adj_batched<float, BS, I, TJ, false>, launch_adj_batched<float, BS, I, TJ, true>},       \
+        {adj_batched_ptr<float, BS, I, TJ, false>, adj_batched_ptr<float, BS, I, TJ, true>}              \
+  }
+#define AV64(BS, I, TJ)                                                                                    \
+  AdjVariant {                                                                                             \
+    BS, I, TJ, {launch_adj<double, BS, I, TJ, false>, nullptr},                                            \
+        {launch_adj_batched<double, BS, I, TJ, false>, nullptr},                                           \
+        {adj_batched_ptr<double, BS, I, TJ, false>, nullptr}                                               \
+  }
+
+const ForceVariant kForce32[] = {FV32(256, 1, 256), FV32(512, 1, 512), FV32(256, 2, 256), FV32(128, 1, 256),
+                                 FV32(64, 1, 128)};
+const ForceVariant kForce64[] = {FV64(256, 1, 256), FV64(128, 1, 128), FV64(64, 1, 128)};
+const AdjVariant kAdj32[] = {AV32(256, 1, 256), AV32(128, 1, 128), AV32(64, 1, 128)};
+const AdjVariant kAdj64[] = {AV64(256, 1, 256), AV64(128, 1, 128), AV64(64, 1, 64)};
+
+constexpr int kNumForce32 = sizeof(kForce32) / sizeof(kForce32[0]);
+constexpr int kNumForce64 = sizeof(kForce64) / sizeof(kForce64[0]);
+constexpr int kNumAdj32 = sizeof(kAdj32) / sizeof(kAdj32[0]);
+constexpr int kNumAdj64 = sizeof(kAdj64) / sizeof(kAdj64[0]);
+
+bool is_fp64(int prec) { return prec == NBODY_FP64; }
+
+int num_variants(int kernel, int prec) {
+  bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
+  if (f) return is_fp64(prec) ? kNumForce64 : kNumForce32;
+  return is_fp64(prec) ? kNumAdj64 : kNumAdj32;
+}
+
+void variant_shape(int kernel, int prec, int v, int& bs, int& i, int& tj) {
+  bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
+  if (f) {
+    const ForceVariant& fv = is_fp64(prec) ? kForce64[v] : kForce32[v];
+    bs = fv.bs; i = fv.i; tj = fv.tj;
+  } else {
+    const AdjVariant& av = is_fp64(prec) ? kAdj64[v] : kAdj32[v];
+    bs = av.bs; i = av.i; tj = av.tj;
+  }
+}
+
+// ------------------------------------------------------------------ tile table
+
+std::mutex g_table_mu;
+std::vector<nbody_tile_entry> g_table;
+
+struct Tile {
+  int variant;
+  int bs, i, tj;
+  int64_t j_split;  // single: number of j-ranges; batched: j-chunk length
+};
+
+int g_num_cu = 0;
+int num_cu() {
+  if (g_num_cu == 0) {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      g_num_cu = cu;
+    else
+      g_num_cu = 256;
+  }
+  return g_num_cu;
+}
+
+// Built-in defaults: one lane per i-particle; the j-range is split until the grid
+// holds about 8 blocks per CU; batched j-chunks of 1024.
+Tile default_tile(int kernel, int prec, int64_t n) {
+  Tile t{};
+  bool batched = kernel == NBODY_KERNEL_FORCE_BATCHED || kernel == NBODY_KERNEL_ADJOINT_BATCHED;
+  t.variant = 0;
+  if (n <= 4096) t.variant = (kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED)
+                                 ? (is_fp64(prec) ? 1 : 3) : 1;
+  variant_shape(kernel, prec, t.variant, t.bs, t.i, t.tj);
+  if (batched) {
+    t.j_split = 1024;
+  } else {
+    int64_t nblk = cdiv(std::max<int64_t>(n, 1), (int64_t)t.bs * t.i);
+    int64_t want = (int64_t)num_cu() * 8;
+    int64_t S = std::max<int64_t>(1, cdiv(want, nblk));
+    S = std::min<int64_t>(S, std::max<int64_t>(1, n / (4 * t.tj)));
+    S = std::min<int64_t>(S, 64);
+    t.j_split = S;
+  }
+  return t;
+}
+
+Tile lookup_tile(int kernel, int prec, int64_t n) {
+  std::lock_guard<std::mutex> lk(g_table_mu);
+  for (const auto& e : g_table) {
+    if (e.kernel == kernel && e.precision == prec && n >= e.n_min && n <= e.n_max &&
+        e.variant >= 0 && e.variant < num_variants(kernel, prec) && e.j_split >= 1) {
+      Tile t{};
+      t.variant = e.variant;
+      variant_shape(kernel, prec, t.variant, t.bs, t.i, t.tj);
+      t.j_split = e.j_split;
+      bool batched = kernel == NBODY_KERNEL_FORCE_BATCHED || kernel == NBODY_KERNEL_ADJOINT_BATCHED;
+      if (batched) t.j_split = std::max<int64_t>(t.tj, cdiv(t.j_split, t.tj) * t.tj);
+      return t;
+    }
+  }
+  return default_tile(kernel, prec, n);
+}
+
+// Effective number of j-ranges and their length (a multiple of TJ).
+void split_geometry(const Tile& t, int64_t nj, int64_t& S, int64_t& jchunk) {
+  S = std::max<int64_t>(1, t.j_split);
+  int64_t ntiles = std::max<int64_t>(1, cdiv(nj, t.tj));
+  if (S > ntiles) S = ntiles;
+  jchunk = cdiv(ntiles, S) * t.tj;
+  S = std::max<int64_t>(1, cdiv(std::max<int64_t>(nj, 1), jchunk));
+}
+
+// ------------------------------------------------------------------ validation
+
+struct Systems {
+  int64_t S;
+  const int64_t* off;  // host
+  int64_t max_n;
+};
+
+int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys) {
+  if (!cfg) return fail(NBODY_ERR_INVALID_ARG, "cfg is NULL");
+  if (cfg->abi_version != NBODY_ABI_VERSION)
+    return fail(NBODY_ERR_INVALID_ARG, "abi_version %d does not match library ABI %d", cfg->abi_version,
+                NBODY_ABI_VERSION);
+  if (cfg->precision != NBODY_FP64 && cfg->precision != NBODY_FP32 && cfg->precision != NBODY_FP32_COMP)
+    return fail(NBODY_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
+  if (!std::isfinite(cfg->G)) return fail(NBODY_ERR_INVALID_ARG, "G must be finite");
+  if (!(cfg->eps > 0.0) || !std::isfinite(cfg->eps))
+    return fail(NBODY_ERR_INVALID_ARG, "eps must be finite and > 0 (got %g)", cfg->eps);
+  if (cfg->precision != NBODY_FP64 && cfg->eps < 1e-10)
+    return fail(NBODY_ERR_INVALID_ARG, "eps must be >= 1e-10 for the FP32 modes (got %g)", cfg->eps);
+  if (cfg->reserved != 0) return fail(NBODY_ERR_INVALID_ARG, "reserved must be 0");
+  if (cfg->flags & ~NBODY_FLAG_LOOP_SYSTEMS) return fail(NBODY_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
+  if (n < 0) return fail(NBODY_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)n);
+  if (n > ((int64_t)1 << 31)) return fail(NBODY_ERR_UNSUPPORTED, "n = %lld exceeds 2^31", (long long)n);
+  if (cfg->n_systems < 1) return fail(NBODY_ERR_INVALID_ARG, "n_systems must be >= 1");
+  sys.S = cfg->n_systems;
+  sys.off = cfg->offsets;
+  sys.max_n = n;
+  if (cfg->offsets) {
+    if (cfg->offsets[0] != 0) return fail(NBODY_ERR_INVALID_ARG, "offsets[0] must be 0");
+    int64_t mx = 0;
+    for (int64_t s = 0; s < cfg->n_systems; ++s) {
+      if (cfg->offsets[s + 1] < cfg->offsets[s])
+        return fail(NBODY_ERR_INVALID_ARG, "offsets must be non-decreasing (offsets[%lld] > offsets[%lld])",
+                    (long long)s, (long long)(s + 1));
+      mx = std::max(mx, cfg->offsets[s + 1] - cfg->offsets[s]);
+    }
+    if (cfg->offsets[cfg->n_systems] != n)
+      return fail(NBODY_ERR_INVALID_ARG, "offsets[n_systems] = %lld must equal n = %lld",
+                  (long long)cfg->offsets[cfg->n_systems], (long long)n);
+    sys.max_n = mx;
+  } else if (cfg->n_systems != 1) {
+    return fail(NBODY_ERR_INVALID_ARG, "offsets may be NULL only when n_systems == 1");
+  }
+  return NBODY_OK;
+}
+
+// ------------------------------------------------------------------ workspace plan
+
+struct Plan {
+  // batched metadata
+  size_t off_meta = 0, sz_meta = 0;
+  size_t off_sysoff = 0, off_nsplit = 0, off_units = 0, off_counter = 0;
+  int64_t n_units_force = 0, n_units_adj = 0;
+  // buffers
+  size_t off_jbuf = 0, sz_jbuf = 0;
+  size_t off_part = 0, sz_part = 0, part_planes = 0;
+  size_t off_epart = 0, sz_epart = 0;
+  size_t off_pot = 0, sz_pot = 0;
+  size_t off_accs = 0, sz_accs = 0;   // scratch acc [3][n]
+  size_t off_xw = 0, off_vw = 0, off_aw = 0, sz_state = 0;
+  size_t off_seg = 0, sz_seg = 0;
+  size_t total = 0;
+  int32_t e_chunks = 1;
+};
+
+struct UnitSet {
+  std::vector<WorkUnit> units;
+  std::vector<int32_t> nsplit;
+};
+
+// Work units of a batched pass: i-tiles of bs*i particles x j-chunks of jc particles
+// inside each system, sorted by decreasing cost (longest-processing-time order).
+void build_units(const Systems& sys, const Tile& t, UnitSet& us) {
+  us.units.clear();
+  us.nsplit.assign(sys.S, 0);
+  const int64_t ti = (int64_t)t.bs * t.i, jc = t.j_split;
+  for (int64_t s = 0; s < sys.S; ++s) {
+    const int64_t b = sys.off[s], e = sys.off[s + 1], ns = e - b;
+    if (ns == 0) continue;
+    const int64_t nsp = cdiv(ns, jc);
+    us.nsplit[s] = (int32_t)nsp;
+    for (int64_t ib = b; ib < e; ib += ti)
+      for (int64_t p = 0; p < nsp; ++p) {
+        WorkUnit w{};
+        w.ib = ib;
+        w.ie = std::min(ib + ti, e);
+        w.jb = b + p * jc;
+        w.je = std::min(w.jb + jc, e);
+        w.slot = (int32_t)p;
+        us.units.push_back(w);
+      }
+  }
+  std::stable_sort(us.units.begin(), us.units.end(), [](const WorkUnit& a, const WorkUnit& b) {
+    return (a.ie - a.ib) * (a.je - a.jb) > (b.ie - b.ib) * (b.je - b.jb);
+  });
+}
+
+int64_t max_nsplit(const UnitSet& us) {
+  int64_t m = 1;
+  for (auto v : us.nsplit) m = std::max<int64_t>(m, v);
+  return m;
+}
+
+enum Need : unsigned { NEED_FORCE = 1, NEED_ENERGY = 2, NEED_ROLLOUT = 4, NEED_BACKWARD = 8 };
+
+int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ckpt_every, unsigned need,
+              Plan& p, UnitSet* uf, UnitSet* ua) {
+  const int prec = cfg->precision;
+  const bool bat = sys.S > 1;
+  const bool loop = bat && (cfg->flags & NBODY_FLAG_LOOP_SYSTEMS);
+  const size_t dsz = sizeof(double);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  int64_t force_S = 1, adj_S = 1;
+  UnitSet local_f, local_a;
+  UnitSet& ufs = uf ? *uf : local_f;
+  UnitSet& uas = ua ? *ua : local_a;
+  if (bat && !loop) {
+    Tile tf = lookup_tile(NBODY_KERNEL_FORCE_BATCHED, prec, sys.max_n);
+    build_units(sys, tf, ufs);
+    force_S = max_nsplit(ufs);
+    p.n_units_force = (int64_t)ufs.units.size();
+    if (need & NEED_BACKWARD) {
+      Tile ta = lookup_tile(NBODY_KERNEL_ADJOINT_BATCHED, prec, sys.max_n);
+      build_units(sys, ta, uas);
+      adj_S = max_nsplit(uas);
+      p.n_units_adj = (int64_t)uas.units.size();
+    }
+    p.off_meta = off;
+    p.off_sysoff = take((sys.S + 1) * sizeof(int64_t));
+    p.off_nsplit = take(2 * sys.S * sizeof(int32_t));  // force then adjoint split counts
+    p.off_units = take((size_t)(p.n_units_force + p.n_units_adj) * sizeof(WorkUnit));
+    p.off_counter = take(2 * sizeof(int32_t));
+    p.sz_meta = off - p.off_meta;
+  } else if (loop) {
+    for (int64_t s = 0; s < sys.S; ++s) {
+      int64_t ns = sys.off[s + 1] - sys.off[s];
+      if (ns == 0) continue;
+      Tile tf = lookup_tile(NBODY_KERNEL_FORCE, prec, ns);
+      int64_t S, jc;
+      split_geometry(tf, ns, S, jc);
+      force_S = std::max(force_S, S);
+      if (need & NEED_BACKWARD) {
+        Tile ta = lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns);
+        split_geometry(ta, ns, S, jc);
+        adj_S = std::max(adj_S, S);
+      }
+    }
+  } else {
+    Tile tf = lookup_tile(NBODY_KERNEL_FORCE, prec, n);
+    int64_t jc;
+    split_geometry(tf, n, force_S, jc);
+    if (need & NEED_BACKWARD) {
+      Tile ta = lookup_tile(NBODY_KERNEL_ADJOINT, prec, n);
+      split_geometry(ta, n, adj_S, jc);
+    }
+  }
+  const size_t vec = is_fp64(prec) ? 32 : 16;
+  p.sz_jbuf = (size_t)n * vec * ((need & NEED_BACKWARD) ? 2 : 1);
+  p.off_jbuf = take(p.sz_jbuf);
+  // partial sums: the persistent batched kernels always write them (one slot per
+  // j-chunk); the single-system kernels only when the j-range is split.
+  const bool persistent = bat && !loop;
+  size_t part_planes = 0;
+  if (force_S > 1 || persistent) part_planes = std::max<size_t>(part_planes, (size_t)force_S * 4);
+  if ((need & NEED_BACKWARD) && (adj_S > 1 || persistent))
+    part_planes = std::max<size_t>(part_planes, (size_t)adj_S * 8);
+  p.part_planes = part_planes;
+  p.sz_part = part_planes * (size_t)n * dsz;
+  p.off_part = take(p.sz_part);
+  // energy partials: chunks per system
+  int64_t chunks = std::min<int64_t>(std::max<int64_t>(1, cdiv(sys.max_n, 256 * 4)), bat ? 16 : 1024);
+  p.e_chunks = (int32_t)chunks;
+  if (need & (NEED_ENERGY | NEED_ROLLOUT)) {
+    p.sz_epart = (size_t)sys.S * chunks * 5 * dsz;
+    p.off_epart = take(p.sz_epart);
+    p.sz_pot = (size_t)n * dsz;
+    p.off_pot = take(p.sz_pot);
+    p.sz_accs = (size_t)3 * n * dsz;
+    p.off_accs = take(p.sz_accs);
+  }
+  if (need & NEED_BACKWARD) {
+    p.sz_state = (size_t)3 * n * dsz;
+    p.off_xw = take(p.sz_state);
+    p.off_vw = take(p.sz_state);
+    p.off_aw = take(p.sz_state);
+    p.sz_seg = (size_t)(ckpt_every + 1) * 3 * n * dsz;
+    p.off_seg = take(p.sz_seg);
+  }
+  p.total = off;
+  return NBODY_OK;
+}
+
+struct Ctx {
+  const nbody_config* cfg;
+  Systems sys;
+  int64_t n;
+  hipStream_t st;
+  char* ws;
+  Plan plan;
+  UnitSet uf, ua;
+  bool bat, loop;
+};
+
+int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsigned need) {
+  TRY(check_cfg(cfg, n, c.sys));
+  c.cfg = cfg;
+  c.n = n;
+  c.st = (hipStream_t)cfg->stream;
+  c.bat = c.sys.S > 1;
+  c.loop = c.bat && (cfg->flags & NBODY_FLAG_LOOP_SYSTEMS);
+  TRY(make_plan(cfg, c.sys, n, ckpt_every, need, c.plan, &c.uf, &c.ua));
+  if (n == 0) return NBODY_OK;
+  if (!cfg->workspace) return fail(NBODY_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", c.plan.total);
+  if (((uintptr_t)cfg->workspace) % kAlign)
+    return fail(NBODY_ERR_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+  if (cfg->workspace_bytes < c.plan.total)
+    return fail(NBODY_ERR_WORKSPACE, "workspace too small: %zu bytes given, %zu needed", cfg->workspace_bytes,
+                c.plan.total);
+  c.ws = (char*)cfg->workspace;
+  return NBODY_OK;
+}
+
+// Host staging for the batched metadata (system offsets, split counts, work
+// units): pinned host memory, reused once the previous upload has completed.
+std::mutex g_stage_mu;
+void* g_stage = nullptr;
+size_t g_stage_bytes = 0;
+hipEvent_t g_stage_done = nullptr;
+
+int upload_meta(Ctx& c) {
+  if (!c.bat || c.loop) return NBODY_OK;
+  const int64_t S = c.sys.S;
+  const size_t b_off = (S + 1) * sizeof(int64_t);
+  const size_t b_ns = 2 * S * sizeof(int32_t);
+  const size_t b_units = (c.uf.units.size() + c.ua.units.size()) * sizeof(WorkUnit);
+  const size_t total = align_up(b_off) + align_up(b_ns) + align_up(b_units);
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  if (g_stage_done) HIP_TRY(hipEventSynchronize(g_stage_done));  // previous upload has read the staging
+  if (total > g_stage_bytes) {
+    if (g_stage) HIP_TRY(hipHostFree(g_stage));
+    g_stage = nullptr;
+    g_stage_bytes = 0;
+    HIP_TRY(hipHostMalloc(&g_stage, total, hipHostMallocDefault));
+    g_stage_bytes = total;
+  }
+  if (!g_stage_done) HIP_TRY(hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming));
+  char* h = (char*)g_stage;
+  int64_t* h_off = (int64_t*)h;
+  int32_t* h_ns = (int32_t*)(h + align_up(b_off));
+  WorkUnit* h_units = (WorkUnit*)(h + align_up(b_off) + align_up(b_ns));
+  std::memcpy(h_off, c.sys.off, b_off);
+  for (int64_t s = 0; s < S; ++s) {
+    h_ns[s] = c.uf.nsplit.empty() ? 0 : c.uf.nsplit[s];
+    h_ns[S + s] = c.ua.nsplit.empty() ? 0 : c.ua.nsplit[s];
+  }
+  if (!c.uf.units.empty()) std::memcpy(h_units, c.uf.units.data(), c.uf.units.size() * sizeof(WorkUnit));
+  if (!c.ua.units.empty())
+    std::memcpy(h_units + c.uf.units.size(), c.ua.units.data(), c.ua.units.size() * sizeof(WorkUnit));
+  HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_sysoff, h_off, b_off, hipMemcpyHostToDevice, c.st));
+  HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_nsplit, h_ns, b_ns, hipMemcpyHostToDevice, c.st));
+  if (b_units) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_units, h_units, b_units, hipMemcpyHostToDevice, c.st));
+  HIP_TRY(hipEventRecord(g_stage_done, c.st));
+  return NBODY_OK;
+}
+
+// Host-side guard: a pass about to write `planes` partial planes of n doubles must
+// find them inside the planned partial-sum region.
+int check_part(const Ctx& c, int64_t planes, const char* what) {
+  if ((size_t)planes > c.plan.part_planes)
+    return fail(NBODY_ERR_DEVICE, "internal: %s needs %lld partial planes, plan has %zu", what, (long long)planes,
+                c.plan.part_planes);
+  return NBODY_OK;
+}
+
+int check_jbuf(const Ctx& c, int vectors_per_particle, const char* what) {
+  const size_t vec = is_fp64(c.cfg->precision) ? 32 : 16;
+  if (c.plan.sz_jbuf < (size_t)c.n * vec * vectors_per_particle)
+    return fail(NBODY_ERR_DEVICE, "internal: %s j-array larger than the planned region", what);
+  return NBODY_OK;
+}
+
+inline dim3 grid1d(int64_t n, int bs = 256) { return dim3((unsigned)cdiv(std::max<int64_t>(n, 1), bs)); }
+
+// ------------------------------------------------------------------ passes
+
+int stage(Ctx& c, const double* pos, const double* mass) {
+  TRY(check_jbuf(c, 1, "stage_j"));
+  void* j = c.ws + c.plan.off_jbuf;
+  if (is_fp64(c.cfg->precision))
+    hipLaunchKernelGGL(stage_j<double>, grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (D4*)j);
+  else
+    hipLaunchKernelGGL(stage_j<float>, grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (float4*)j);
+  LAUNCH_CHECK("stage_j");
+  return NBODY_OK;
+}
+
+int kick_drift(Ctx& c, double dt, double* pos, double* vel, const double* acc, const double* mass) {
+  TRY(check_jbuf(c, 1, "kick_drift_stage"));
+  void* j = c.ws + c.plan.off_jbuf;
+  if (is_fp64(c.cfg->precision))
+    hipLaunchKernelGGL(kick_drift_stage<double>, grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel, acc,
+                       mass, (D4*)j);
+  else
+    hipLaunchKernelGGL(kick_drift_stage<float>, grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel, acc,
+                       mass, (float4*)j);
+  LAUNCH_CHECK("kick_drift_stage");
+  return NBODY_OK;
+}
+
+int persistent_grid(const void* kfn, int bs, int64_t units, unsigned& grid) {
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, bs, 0);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  int64_t g = std::min<int64_t>(units, (int64_t)num_cu() * per_cu);
+  grid = (unsigned)std::max<int64_t>(g, 1);
+  return NBODY_OK;
+}
+
+// Force pass on the staged j-array: acc = a, pot (nullable), vel += hh*acc when vel != NULL.
+int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
+  const int prec = c.cfg->precision;
+  const bool comp = prec == NBODY_FP32_COMP;
+  const int pot_on = pot != nullptr;
+  const double eps2 = c.cfg->eps * c.cfg->eps;
+  const void* jarr = c.ws + c.plan.off_jbuf;
+  double* part = (double*)(c.ws + c.plan.off_part);
+  const int64_t n = c.n;
+
+  auto single = [&](int64_t b, int64_t e) -> int {
+    const int64_t ns = e - b;
+    if (ns == 0) return NBODY_OK;
+    Tile t = lookup_tile(NBODY_KERNEL_FORCE, prec, ns);
+    int64_t S, jc;
+    split_geometry(t, ns, S, jc);
+    const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
+    ForceOut o{};
+    o.G = c.cfg->G;
+    o.n_plane = n;
+    dim3 g((unsigned)cdiv(ns, (int64_t)t.bs * t.i), (unsigned)S);
+    if (S == 1) {
+      o.acc = acc; o.pot = pot; o.vel = vel; o.hh = hh;
+    } else {
+      TRY(check_part(c, S * 4, "force_kernel"));
+      o.part = part;
+    }
+    fv.fn[pot_on][comp](g, c.st, jarr, b, e, b, e, jc, eps2, o);
+    LAUNCH_CHECK("force_kernel");
+    if (S > 1) {
+      // reduce only this system's particle range: offset pointers into the planes
+      hipLaunchKernelGGL(reduce_splits, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)S, part + b, c.cfg->G,
+                         acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, (int64_t)0,
+                         (const int64_t*)nullptr, (const int32_t*)nullptr);
+      LAUNCH_CHECK("reduce_splits");
+    }
+    return NBODY_OK;
+  };
+
+  if (!c.bat) return single(0, n);
+  if (c.loop) {
+    for (int64_t s = 0; s < c.sys.S; ++s) TRY(single(c.sys.off[s], c.sys.off[s + 1]));
+    return NBODY_OK;
+  }
+  // batched persistent launch
+  Tile t = lookup_tile(NBODY_KERNEL_FORCE_BATCHED, prec, c.sys.max_n);
+  const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
+  TRY(check_part(c, max_nsplit(c.uf) * 4, "force_batched_kernel"));
+  int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter);
+  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)2, 0);
+  LAUNCH_CHECK("fill_i32");
+  unsigned grid;
+  persistent_grid(fv.bptr[pot_on][comp](), t.bs, c.plan.n_units_force, grid);
+  ForceOut o{};
+  o.G = c.cfg->G;
+  o.n_plane = n;
+  o.part = part;
+  fv.bfn[pot_on][comp](dim3(grid), c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
+                       (int32_t)c.plan.n_units_force, counter, eps2, o);
+  LAUNCH_CHECK("force_batched_kernel");
+  hipLaunchKernelGGL(reduce_splits, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, c.cfg->G, acc, pot, vel, hh,
+                     c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit));
+  LAUNCH_CHECK("reduce_splits");
+  return NBODY_OK;
+}
+
+int energy_pass(Ctx& c, const double* vel, const double* mass, const double* pot, double* out) {
+  const int32_t chunks = c.plan.e_chunks;
+  double* ep = (double*)(c.ws + c.plan.off_epart);
+  const int64_t* dev_off = c.bat ? (const int64_t*)(c.ws + c.plan.off_sysoff) : nullptr;
+  if (c.bat && c.loop) {
+    // the looped baseline has no device offsets: reduce system by system
+    for (int64_t s = 0; s < c.sys.S; ++s) {
+      const int64_t b = c.sys.off[s], ns = c.sys.off[s + 1] - b;
+      // offset pointers; vel planes keep stride n, so pass a shifted view per plane
+      hipLaunchKernelGGL(energy_partial<256>, dim3(chunks, 1), dim3(256), 0, c.st, c.n, vel + b, mass + b, pot + b,
+                         (const int64_t*)nullptr, ns, chunks, ep + s * chunks * 5);
+      LAUNCH_CHECK("energy_partial");
+    }
+  } else {
+    hipLaunchKernelGGL(energy_partial<256>, dim3(chunks, (unsigned)c.sys.S), dim3(256), 0, c.st, c.n, vel, mass, pot,
+                       dev_off, c.n, chunks, ep);
+    LAUNCH_CHECK("energy_partial");
+  }
+  hipLaunchKernelGGL(energy_final<256>, dim3((unsigned)c.sys.S), dim3(256), 0, c.st, chunks, ep, out);
+  LAUNCH_CHECK("energy_final");
+  return NBODY_OK;
+}
+
+// Adjoint pass at positions pos with l = w * gvel (after gvel += h_drift * gpos):
+// gpos += G(...), gmass += -G M.
+int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, const double* gpos_in,
+                 double h_drift, double w, double* gpos, double* gmass) {
+  const int prec = c.cfg->precision;
+  const bool comp = prec == NBODY_FP32_COMP;
+  const double eps2 = c.cfg->eps * c.cfg->eps;
+  TRY(check_jbuf(c, 2, "adjoint_stage"));
+  void* jadj = c.ws + c.plan.off_jbuf;
+  double* part = (double*)(c.ws + c.plan.off_part);
+  const int64_t n = c.n;
+  if (is_fp64(prec))
+    hipLaunchKernelGGL(adjoint_stage<double>, grid1d(n), dim3(256), 0, c.st, n, pos, mass, gvel, gpos_in, h_drift, w,
+                       (D4*)jadj);
+  else
+    hipLaunchKernelGGL(adjoint_stage<float>, grid1d(n), dim3(256), 0, c.st, n, pos, mass, gvel, gpos_in, h_drift, w,
+                       (float4*)jadj);
+  LAUNCH_CHECK("adjoint_stage");
+
+  auto single = [&](int64_t b, int64_t e) -> int {
+    const int64_t ns = e - b;
+    if (ns == 0) return NBODY_OK;
+    Tile t = lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns);
+    int64_t S, jc;
+    split_geometry(t, ns, S, jc);
+    const AdjVariant& av = is_fp64(prec) ? kAdj64[t.variant] : kAdj32[t.variant];
+    AdjOut o{};
+    o.G = c.cfg->G;
+    o.n_plane = n;
+    dim3 g((unsigned)cdiv(ns, (int64_t)t.bs * t.i), (unsigned)S);
+    if (S == 1) {
+      o.gpos = gpos; o.gmass = gmass;
+    } else {
+      TRY(check_part(c, S * 8, "adjoint_kernel"));
+      o.part = part;
+    }
+    av.fn[comp](g, c.st, jadj, b, e, b, e, jc, eps2, o);
+    LAUNCH_CHECK("adjoint_kernel");
+    if (S > 1) {
+      if (is_fp64(prec))
+        hipLaunchKernelGGL(adjoint_reduce<double>, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)S, part + b,
+                           (const D4*)jadj + 2 * b, c.cfg->G, gpos + b, gmass + b, (int64_t)0,
+                           (const int64_t*)nullptr, (const int32_t*)nullptr);
+      else
+        hipLaunchKernelGGL(adjoint_reduce<float>, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)S, part + b,
+                           (const float4*)jadj + 2 * b, c.cfg->G, gpos + b, gmass + b, (int64_t)0,
+                           (const int64_t*)nullptr, (const int32_t*)nullptr);
+      LAUNCH_CHECK("adjoint_reduce");
+    }
+    return NBODY_OK;
+  };
+  if (!c.bat) return single(0, n);
+  if (c.loop) {
+    for (int64_t s = 0; s < c.sys.S; ++s) TRY(single(c.sys.off[s], c.sys.off[s + 1]));
+    return NBODY_OK;
+  }
+  Tile t = lookup_tile(NBODY_KERNEL_ADJOINT_BATCHED, prec, c.sys.max_n);
+  const AdjVariant& av = is_fp64(prec) ? kAdj64[t.variant] : kAdj32[t.variant];
+  TRY(check_part(c, max_nsplit(c.ua) * 8, "adjoint_batched_kernel"));
+  int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter) + 1;
+  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)1, 0);
+  LAUNCH_CHECK("fill_i32");
+  unsigned grid;
+  persistent_grid(av.bptr[comp](), t.bs, c.plan.n_units_adj, grid);
+  AdjOut o{};
+  o.G = c.cfg->G;
+  o.n_plane = n;
+  o.part = part;
+  av.bfn[comp](dim3(grid), c.st, jadj, (const WorkUnit*)(c.ws + c.plan.off_units) + c.plan.n_units_force,
+               (int32_t)c.plan.n_units_adj, counter, eps2, o);
+  LAUNCH_CHECK("adjoint_batched_kernel");
+  const int32_t* nsplit_adj = (const int32_t*)(c.ws + c.plan.off_nsplit) + c.sys.S;
+  if (is_fp64(prec))
+    hipLaunchKernelGGL(adjoint_reduce<double>, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, (const D4*)jadj,
+                       c.cfg->G, gpos, gmass, c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff), nsplit_adj);
+  else
+    hipLaunchKernelGGL(adjoint_reduce<float>, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part,
+                       (const float4*)jadj, c.cfg->G, gpos, gmass, c.sys.S,
+                       (const int64_t*)(c.ws + c.plan.off_sysoff), nsplit_adj);
+  LAUNCH_CHECK("adjoint_reduce");
+  return NBODY_OK;
+}
+
+int copy_d2d(Ctx& c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return NBODY_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.st));
+  return NBODY_OK;
+}
+
+int zero_f64(Ctx& c, double* p, int64_t count) {
+  if (count == 0) return NBODY_OK;
+  hipLaunchKernelGGL(fill_f64, grid1d(count), dim3(256), 0, c.st, p, count, 0.0);
+  LAUNCH_CHECK("fill_f64");
+  return NBODY_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+__attribute__((visibility("default"))) int nbody_abi_version(void) { return NBODY_ABI_VERSION; }
+
+__attribute__((visibility("default"))) const char* nbody_last_error(void) { return g_err.c_str(); }
+
+__attribute__((visibility("default"))) int nbody_workspace_size(const nbody_config* cfg, int64_t n, int64_t steps,
+                                                                int64_t ckpt_every, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(NBODY_ERR_INVALID_ARG, "bytes is NULL");
+  Systems sys;
+  TRY(check_cfg(cfg, n, sys));
+  if (steps < 0) return fail(NBODY_ERR_INVALID_ARG, "steps must be >= 0");
+  if (ckpt_every < 0) return fail(NBODY_ERR_INVALID_ARG, "ckpt_every must be >= 0");
+  Plan p;
+  unsigned need = NEED_FORCE | NEED_ENERGY | NEED_ROLLOUT;
+  if (steps > 0 && ckpt_every > 0) need |= NEED_BACKWARD;
+  TRY(make_plan(cfg, sys, n, std::max<int64_t>(ckpt_every, 1), need, p, nullptr, nullptr));
+  *bytes = p.total;
+  return NBODY_OK;
+}
+
+__attribute__((visibility("default"))) int nbody_forces(const nbody_config* cfg, int64_t n, const double* pos,
+                                                        const double* mass, double* acc, double* pot) {
+  g_err.clear();
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_FORCE));
+  if (n == 0) return NBODY_OK;
+  if (!pos || !mass || !acc) return fail(NBODY_ERR_INVALID_ARG, "pos, mass and acc must be non-NULL");
+  TRY(upload_meta(c));
+  TRY(stage(c, pos, mass));
+  return force_pass(c, acc, pot, nullptr, 0.0);
+}
+
+__attribute__((visibility("default"))) int nbody_step(const nbody_config* cfg, int64_t n, double dt, double* pos,
+                                                      double* vel, const double* mass, double* acc) {
+  g_err.clear();
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_FORCE));
+  if (!std::isfinite(dt)) return fail(NBODY_ERR_INVALID_ARG, "dt must be finite");
+  if (n == 0) return NBODY_OK;
+  if (!pos || !vel || !mass || !acc) return fail(NBODY_ERR_INVALID_ARG, "pos, vel, mass and acc must be non-NULL");
+  TRY(upload_meta(c));
+  TRY(kick_drift(c, dt, pos, vel, acc, mass));
+  return force_pass(c, acc, nullptr, vel, 0.5 * dt);
+}
+
+__attribute__((visibility("default"))) int nbody_rollout(const nbody_config* cfg, int64_t n, double dt, int64_t steps,
+                                                         int64_t ckpt_every, double* pos, double* vel,
+                                                         const double* mass, double* acc, double* ckpt,
+                                                         double* energy_trace) {
+  g_err.clear();
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_FORCE | NEED_ROLLOUT));
+  if (!std::isfinite(dt)) return fail(NBODY_ERR_INVALID_ARG, "dt must be finite");
+  if (steps < 0) return fail(NBODY_ERR_INVALID_ARG, "steps must be >= 0");
+  if (ckpt && ckpt_every < 1) return fail(NBODY_ERR_INVALID_ARG, "ckpt_every must be >= 1 when ckpt is given");
+  if (n == 0) return NBODY_OK;
+  if (!pos || !vel || !mass || !acc) return fail(NBODY_ERR_INVALID_ARG, "pos, vel, mass and acc must be non-NULL");
+  TRY(upload_meta(c));
+  const size_t plane3 = (size_t)3 * n * sizeof(double);
+  const int64_t S = c.sys.S;
+  double* pot = energy_trace ? (double*)(c.ws + c.plan.off_pot) : nullptr;
+  if (ckpt) {
+    TRY(copy_d2d(c, ckpt, pos, plane3));
+    TRY(copy_d2d(c, ckpt + 3 * n, vel, plane3));
+  }
+  if (energy_trace) {
+    // potential at x_0 (the caller's acc is left untouched)
+    TRY(stage(c, pos, mass));
+    TRY(force_pass(c, (double*)(c.ws + c.plan.off_accs), pot, nullptr, 0.0));
+    TRY(energy_pass(c, vel, mass, pot, energy_trace));
+  }
+  for (int64_t s = 0; s < steps; ++s) {
+    TRY(kick_drift(c, dt, pos, vel, acc, mass));
+    TRY(force_pass(c, acc, pot, vel, 0.5 * dt));
+    if (energy_trace) TRY(energy_pass(c, vel, mass, pot, energy_trace + (s + 1) * S * 5));
+    if (ckpt && (s + 1) % ckpt_every == 0) {
+      double* slot = ckpt + (size_t)((s + 1) / ckpt_every) * 6 * n;
+      TRY(copy_d2d(c, slot, pos, plane3));
+      TRY(copy_d2d(c, slot + 3 * n, vel, plane3));
+    }
+  }
+  return NBODY_OK;
+}
+
+__attribute__((visibility("default"))) int nbody_energy_momentum(const nbody_config* cfg, int64_t n,
+                                                                 const double* pos, const double* vel,
+                                                                 const double* mass, const double* pot,
+                                                                 double* out) {
+  g_err.clear();
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_ENERGY | (pot ? 0u : (unsigned)NEED_FORCE)));
+  if (!out) return fail(NBODY_ERR_INVALID_ARG, "out must be non-NULL");
+  if (n == 0) {
+    // every system is empty: zero energy and momentum
+    hipLaunchKernelGGL(fill_f64, grid1d(c.sys.S * 5), dim3(256), 0, (hipStream_t)cfg->stream, out, c.sys.S * 5, 0.0);
+    LAUNCH_CHECK("fill_f64");
+    return NBODY_OK;
+  }
+  if (!vel || !mass || (!pot && !pos)) return fail(NBODY_ERR_INVALID_ARG, "vel, mass and pos (or pot) must be non-NULL");
+  TRY(upload_meta(c));
+  const double* p = pot;
+  if (!p) {
+    double* pw = (double*)(c.ws + c.plan.off_pot);
+    TRY(stage(c, pos, mass));
+    TRY(force_pass(c, (double*)(c.ws + c.plan.off_accs), pw, nullptr, 0.0));
+    p = pw;
+  }
+  return energy_pass(c, vel, mass, p, out);
+}
+
+__attribute__((visibility("default"))) int nbody_rollout_backward(const nbody_config* cfg, int64_t n, double dt,
+                                                                  int64_t steps, int64_t ckpt_every,
+                                                                  const double* mass, const double* ckpt,
+                                                                  const double* gpos_final,
+                                                                  const double* gvel_final, double* gpos0,
+                                                                  double* gvel0, double* gmass) {
+  g_err.clear();
+  if (ckpt_every < 1) return fail(NBODY_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+  Ctx c;
+  TRY(prepare(c, cfg, n, ckpt_every, NEED_FORCE | NEED_BACKWARD));
+  if (!std::isfinite(dt)) return fail(NBODY_ERR_INVALID_ARG, "dt must be finite");
+  if (steps < 0) return fail(NBODY_ERR_INVALID_ARG, "steps must be >= 0");
+  if (n == 0) return NBODY_OK;
+  if (!mass || !ckpt || !gpos_final || !gvel_final || !gpos0 || !gvel0 || !gmass)
+    return fail(NBODY_ERR_INVALID_ARG, "mass, ckpt, gradients and outputs must be non-NULL");
+  TRY(upload_meta(c));
+  const size_t plane3 = (size_t)3 * n * sizeof(double);
+  const double h = dt;
+  double* xw = (double*)(c.ws + c.plan.off_xw);
+  double* vw = (double*)(c.ws + c.plan.off_vw);
+  double* aw = (double*)(c.ws + c.plan.off_aw);
+  double* seg = (double*)(c.ws + c.plan.off_seg);
+
+  TRY(copy_d2d(c, gpos0, gpos_final, plane3));
+  TRY(copy_d2d(c, gvel0, gvel_final, plane3));
+  TRY(zero_f64(c, gmass, n));
+  if (steps == 0) return NBODY_OK;
+
+  const int64_t nseg = cdiv(steps, ckpt_every);
+  for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+    const int64_t t0 = sg * ckpt_every;
+    const int64_t t1 = std::min(t0 + ckpt_every, steps);
+    const bool last = (sg == nseg - 1);
+    // recompute x_t0 .. x_t1 (x_t1 only needed by the last segment) into seg[0 .. t1-t0]
+    const double* ck = ckpt + (size_t)sg * 6 * n;
+    TRY(copy_d2d(c, xw, ck, plane3));
+    TRY(copy_d2d(c, vw, ck + 3 * n, plane3));
+    TRY(copy_d2d(c, seg, xw, plane3));
+    const int64_t t_end = last ? t1 : t1 - 1;  // last position to recompute
+    if (t_end > t0) {
+      TRY(stage(c, xw, mass));
+      TRY(force_pass(c, aw, nullptr, nullptr, 0.0));
+      for (int64_t t = t0; t < t_end; ++t) {
+        TRY(kick_drift(c, h, xw, vw, aw, mass));
+        TRY(copy_d2d(c, seg + (size_t)(t + 1 - t0) * 3 * n, xw, plane3));
+        if (t + 1 < t_end) TRY(force_pass(c, aw, nullptr, vw, 0.5 * h));
+      }
+    }
+    // reverse sweep over this segment
+    if (last) {
+      const double* xK = seg + (size_t)(steps - t0) * 3 * n;
+      TRY(adjoint_pass(c, xK, mass, gvel0, gpos0, 0.0, 0.5 * h, gpos0, gmass));
+    }
+    for (int64_t t = t1 - 1; t >= t0; --t) {
+      const double* xt = seg + (size_t)(t - t0) * 3 * n;
+      const double w = t > 0 ? h : 0.5 * h;
+      TRY(adjoint_pass(c, xt, mass, gvel0, gpos0, h, w, gpos0, gmass));
+    }
+  }
+  return NBODY_OK;
+}
+
+__attribute__((visibility("default"))) int nbody_set_tile_table(const nbody_tile_entry* entries, int64_t count) {
+  g_err.clear();
+  if (count < 0 || (count > 0 && !entries)) return fail(NBODY_ERR_INVALID_ARG, "bad tile table");
+  for (int64_t k = 0; k < count; ++k) {
+    const auto& e = entries[k];
+    if (e.kernel < 0 || e.kernel > 3) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad kernel", (long long)k);
+    if (e.precision < 0 || e.precision > 2) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad precision", (long long)k);
+    if (e.variant < 0 || e.variant >= num_variants(e.kernel, e.precision))
+      return fail(NBODY_ERR_INVALID_ARG, "entry %lld: variant %d out of range", (long long)k, e.variant);
+    if (e.j_split < 1 || e.n_min > e.n_max) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad range/j_split", (long long)k);
+  }
+  std::lock_guard<std::mutex> lk(g_table_mu);
+  g_table.assign(entries, entries + count);
+  return NBODY_OK;
+}
+
+__attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, int32_t precision, char* buf,
+                                                               size_t cap) {
+  g_err.clear();
+  if (kernel < 0 || kernel > 3 || precision < 0 || precision > 2) {
+    fail(NBODY_ERR_INVALID_ARG, "bad kernel/precision");
+    return -1;
+  }
+  int nv = num_variants(kernel, precision);
+  if (buf && cap > 0) {
+    size_t pos = 0;
+    for (int v = 0; v < nv; ++v) {
+      int bs, i, tj;
+      variant_shape(kernel, precision, v, bs, i, tj);
+      char tmp[64];
+      int len = snprintf(tmp, sizeof tmp, "bs=%d,i=%d,tj=%d", bs, i, tj);
+      if (pos + len + 1 > cap) break;
+      memcpy(buf + pos, tmp, len + 1);
+      pos += len + 1;
+    }
+  }
+  return nv;
+}
+
+__attribute__((visibility("default"))) int nbody_tile_lookup(int32_t kernel, int32_t precision, int64_t n,
+                                                             int32_t* variant, int32_t* j_split) {
+  g_err.clear();
+  if (kernel < 0 || kernel > 3 || precision < 0 || precision > 2 || !variant || !j_split)
+    return fail(NBODY_ERR_INVALID_ARG, "bad arguments");
+  Tile t = lookup_tile(kernel, precision, n);
+  *variant = t.variant;
+  *j_split = (int32_t)t.j_split;
+  return NBODY_OK;
+}
+
+}  // extern "C"

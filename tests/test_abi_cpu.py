@@ -1,0 +1,159 @@
+"""Host-side checks of libnbody.so that need no GPU: the library loads, exports
+every entry point include/nbody.h declares, and rejects bad arguments on the
+host before any HIP call (every error path below returns before touching the
+device)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import paper_2511_02655_amd as nb
+    if not os.path.exists(nb.LIB_PATH):
+        pytest.fail("libnbody.so is not built; run python -m paper_2511_02655_amd.build")
+    nb.lib()
+    return nb
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "nbody.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbody_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(nb):
+    syms = declared_symbols()
+    assert len(syms) >= 11
+    L = ctypes.CDLL(nb.LIB_PATH)
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(nb.EXPORTED)
+
+
+def test_abi_version(nb):
+    assert nb.lib().nbody_abi_version() == nb.NBODY_ABI_VERSION
+
+
+def test_tile_variants_listed(nb):
+    for k in nb.KERNELS:
+        for p in nb.PRECISIONS:
+            v = nb.tile_variants(k, p)
+            assert len(v) >= 2 and all(x.startswith("bs=") for x in v)
+
+
+def _cfg(nb, **kw):
+    c = nb.NBodyConfig()
+    c.abi_version = kw.get("abi", nb.NBODY_ABI_VERSION)
+    c.precision = kw.get("precision", 2)
+    c.G = kw.get("G", 1.0)
+    c.eps = kw.get("eps", 1e-2)
+    off = kw.get("offsets")
+    if off is not None:
+        arr = np.ascontiguousarray(off, dtype=np.int64)
+        c._keep = arr
+        c.n_systems = len(arr) - 1
+        c.offsets = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    else:
+        c.n_systems = kw.get("n_systems", 1)
+        c.offsets = None
+    c.workspace = kw.get("ws", None)
+    c.workspace_bytes = kw.get("ws_bytes", 0)
+    c.stream = None
+    c.flags = kw.get("flags", 0)
+    c.reserved = kw.get("reserved", 0)
+    return c
+
+
+def _ws_size(nb, c, n, steps=0, ck=0):
+    b = ctypes.c_size_t()
+    rc = nb.lib().nbody_workspace_size(ctypes.byref(c), n, steps, ck, ctypes.byref(b))
+    return rc, b.value
+
+
+def test_workspace_size_grows_with_n_and_backward(nb):
+    rc, a = _ws_size(nb, _cfg(nb), 1000)
+    assert rc == 0 and a > 0
+    rc, b = _ws_size(nb, _cfg(nb), 100000)
+    assert rc == 0 and b > a
+    rc, c = _ws_size(nb, _cfg(nb), 100000, 200, 20)
+    assert rc == 0 and c > b
+    rc, z = _ws_size(nb, _cfg(nb), 0)
+    assert rc == 0
+
+
+def test_workspace_covers_batched_partials(nb):
+    """Persistent batched passes always write one partial-sum slot per j-chunk: the
+    planned workspace must hold at least 4 planes (force) / 8 planes (adjoint) of n
+    doubles on top of the j-array, even when every system fits in one chunk."""
+    off = [0, 100, 300, 301, 700]
+    n = 700
+    rc, fw = _ws_size(nb, _cfg(nb, offsets=off, precision=2), n)
+    assert rc == 0 and fw >= n * 16 + 4 * n * 8
+    rc, bw = _ws_size(nb, _cfg(nb, offsets=off, precision=0), n, 6, 3)
+    assert rc == 0 and bw >= 2 * n * 32 + 8 * n * 8 + 4 * 3 * n * 8
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("kw,code,needle", [
+    (dict(abi=99), 1, "abi_version"),
+    (dict(precision=7), 1, "precision"),
+    (dict(eps=0.0), 1, "eps"),
+    (dict(eps=-1.0), 1, "eps"),
+    (dict(eps=float("nan")), 1, "eps"),
+    (dict(eps=1e-12), 1, "FP32"),
+    (dict(G=float("inf")), 1, "G"),
+    (dict(n_systems=0), 1, "n_systems"),
+    (dict(n_systems=2), 1, "offsets"),
+    (dict(offsets=[0, 5, 3, 10]), 1, "non-decreasing"),
+    (dict(offsets=[1, 5, 10]), 1, "offsets[0]"),
+    (dict(offsets=[0, 5, 9]), 1, "must equal n"),
+    (dict(flags=8), 1, "flags"),
+    (dict(reserved=1), 1, "reserved"),
+    (dict(), 4, "workspace is NULL"),
+    (dict(ws=0x1000, ws_bytes=10), 4, "too small"),
+    (dict(ws=0x1001, ws_bytes=1 << 40), 4, "aligned"),
+])
+def test_forces_argument_errors(nb, kw, code, needle):
+    c = _cfg(nb, **kw)
+    rc = nb.lib().nbody_forces(ctypes.byref(c), 10, FAKE, FAKE, FAKE, None)
+    assert rc == code
+    assert needle in nb.lib().nbody_last_error().decode()
+
+
+def test_other_entry_point_errors(nb):
+    L = nb.lib()
+    c = _cfg(nb, ws=0x1000, ws_bytes=1 << 40)
+    assert L.nbody_forces(ctypes.byref(c), -1, FAKE, FAKE, FAKE, None) == 1
+    assert L.nbody_forces(None, 10, FAKE, FAKE, FAKE, None) == 1
+    assert L.nbody_forces(ctypes.byref(c), 10, None, FAKE, FAKE, None) == 1
+    assert L.nbody_step(ctypes.byref(c), 10, float("nan"), FAKE, FAKE, FAKE, FAKE) == 1
+    assert L.nbody_rollout(ctypes.byref(c), 10, 1e-3, -1, 0, FAKE, FAKE, FAKE, FAKE, None, None) == 1
+    assert L.nbody_rollout(ctypes.byref(c), 10, 1e-3, 5, 0, FAKE, FAKE, FAKE, FAKE, FAKE, None) == 1
+    assert L.nbody_rollout_backward(ctypes.byref(c), 10, 1e-3, 5, 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE) == 1
+    assert L.nbody_rollout_backward(ctypes.byref(c), 10, 1e-3, 5, 2, None, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE) == 1
+    assert L.nbody_energy_momentum(ctypes.byref(c), 10, FAKE, FAKE, FAKE, None, None) == 1
+    assert "out" in L.nbody_last_error().decode()
+    # n == 0 is a valid no-op that touches nothing
+    assert L.nbody_forces(ctypes.byref(_cfg(nb)), 0, None, None, None, None) == 0
+    assert L.nbody_step(ctypes.byref(_cfg(nb)), 0, 1e-3, None, None, None, None) == 0
+
+
+def test_tile_table_validation(nb):
+    good = [dict(kernel="force", precision="fp32c", n_min=0, n_max=1 << 40, variant=0, j_split=1)]
+    nb.set_tile_table(good)
+    assert nb.tile_lookup("force", "fp32c", 5000) == (0, 1)
+    with pytest.raises(nb.NBodyError):
+        nb.set_tile_table([dict(kernel="force", precision="fp32c", n_min=0, n_max=10, variant=99, j_split=1)])
+    with pytest.raises(nb.NBodyError):
+        nb.set_tile_table([dict(kernel="force", precision="fp32c", n_min=5, n_max=1, variant=0, j_split=1)])
+    nb.set_tile_table([])
+    v, s = nb.tile_lookup("force", "fp32c", 1 << 20)
+    assert v >= 0 and s >= 1

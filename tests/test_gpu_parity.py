@@ -1,0 +1,427 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (force error e_i = |da_i| / max(|a_i|, 1e-6 rms|a|)):
+  FP64 pair math       max e_i <= 1e-12 (a 1-ulp-level rsqrt plus different sum order)
+  FP32 compensated     max e_i <= 1e-5  (positions and pair math rounded to float)
+  FP32 plain           max e_i <= 1e-4
+Potentials are compared relative to |phi_i|, energies relative to |E|.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2511_02655_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_F = {"fp64": 1e-12, "fp32c": 1e-5, "fp32": 1e-4}
+TOL_P = {"fp64": 1e-12, "fp32c": 1e-6, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_02655_amd as nb
+    nb.lib()
+    return nb
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def fp32_bound(pos, mass, eps, G=1.0, accumulate_plain=False):
+    """Worst-case error bound of the FP32 pair path for every particle.
+
+    Rounding the coordinates to float moves each separation by up to
+    sqrt(3) u (|x_i| + |x_j|); the Jacobian of d s^{-3/2} has norm <= 2 s^{-3/2};
+    the pair arithmetic and the compensated accumulation add a few u |term|.
+    B_i = u G sum_j m_j s^{-3/2} (2 sqrt(3) (|x_i| + |x_j|) + 8 |d|)  (u = 2^-24);
+    plain float accumulation adds sqrt(n) u sum |term|."""
+    u = 2.0 ** -24
+    n = mass.shape[0]
+    xn = np.sqrt(np.sum(pos ** 2, axis=0))
+    B = np.empty(n)
+    for i0 in range(0, n, 512):
+        i1 = min(n, i0 + 512)
+        d = pos[:, None, :] - pos[:, i0:i1, None]          # (3, bi, n)
+        dn = np.sqrt(np.sum(d * d, axis=0))
+        s = dn * dn + eps * eps
+        w = mass[None, :] * s ** -1.5
+        k = 2 * math.sqrt(3.0) * (xn[i0:i1, None] + xn[None, :]) + (8 + (math.sqrt(n) if accumulate_plain else 0)) * dn
+        B[i0:i1] = u * G * np.sum(w * k, axis=1)
+    return B
+
+
+def check_fp32(acc, ref, pos, mass, eps, prec, G=1.0):
+    B = fp32_bound(pos, mass, eps, G, accumulate_plain=(prec == "fp32"))
+    d = np.sqrt(np.sum((acc - ref) ** 2, axis=0))
+    worst = float(np.max(d / B))
+    assert worst <= 1.0, "error exceeds the FP32 bound by %.3g" % worst
+    return worst
+
+
+def force_err(a, ref):
+    rms = math.sqrt(np.mean(np.sum(ref ** 2, axis=0))) if ref.size else 1.0
+    d = np.sqrt(np.sum((a - ref) ** 2, axis=0))
+    m = np.sqrt(np.sum(ref ** 2, axis=0))
+    return float(np.max(d / np.maximum(m, 1e-6 * rms))) if d.size else 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 255, 257, 1000, 1024, 4097])
+def test_forces_vs_oracle(nb, oracle, prec, n):
+    s = inputs.uniform_cube(n, 100 + n)
+    acc_ref, pot_ref = oracle.forces(s.pos, s.mass, eps=1e-2)
+    acc, pot = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision=prec, want_pot=True)
+    acc, pot = host(acc), host(pot)
+    if n == 1:
+        assert np.all(acc == 0) and np.all(pot == 0)
+        return
+    if prec == "fp64":
+        assert force_err(acc, acc_ref) <= TOL_F[prec], force_err(acc, acc_ref)
+    else:
+        # small uniform cubes hold near pairs (|d| ~ eps) whose float-rounded separations
+        # limit any FP32 pair path: check against the per-particle error bound
+        check_fp32(acc, acc_ref, s.pos, s.mass, 1e-2, prec)
+    assert np.max(np.abs(pot - pot_ref) / np.abs(pot_ref)) <= TOL_P[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_forces_G_and_no_pot(nb, oracle, prec):
+    s = inputs.plummer(3000, 7)
+    acc_ref, _ = oracle.forces(s.pos, s.mass, G=2.5, eps=0.05)
+    acc, pot = nb.forces(dev(s.pos), dev(s.mass), G=2.5, eps=0.05, precision=prec)
+    assert pot is None
+    if prec == "fp64":
+        assert force_err(host(acc), acc_ref) <= TOL_F[prec]
+    else:
+        check_fp32(host(acc), acc_ref, s.pos, s.mass, 0.05, prec, G=2.5)
+
+
+def test_empty_system(nb):
+    import torch
+    acc, pot = nb.forces(torch.zeros((3, 0), dtype=torch.float64, device="cuda"),
+                         torch.zeros(0, dtype=torch.float64, device="cuda"), want_pot=True)
+    assert acc.shape == (3, 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_ring_closed_form_on_gpu(nb, prec):
+    n, R, m, eps = 1000, 1.0, 1e-3, 1e-2
+    s = inputs.ring(n, R=R, m=m, phase=0.1)
+    acc, pot = nb.forces(dev(s.pos), dev(s.mass), eps=eps, precision=prec, want_pot=True)
+    acc, pot = host(acc), host(pot)
+    k = np.arange(1, n)
+    sn2 = np.sin(np.pi * k / n) ** 2
+    a_rad = m * np.sum(2 * R * sn2 / (4 * R * R * sn2 + eps * eps) ** 1.5)
+    phi = -m * np.sum(1.0 / np.sqrt(4 * R * R * sn2 + eps * eps))
+    radial = np.sum(acc * s.pos / R, axis=0)
+    if prec == "fp64":
+        np.testing.assert_allclose(radial, -a_rad, rtol=1e-11)
+        np.testing.assert_allclose(pot, phi, rtol=1e-11)
+    else:
+        B = fp32_bound(s.pos, s.mass, eps)
+        assert np.max(np.abs(radial + a_rad) / B) <= 1.0
+        np.testing.assert_allclose(pot, phi, rtol=1e-6)
+
+
+def test_newton_third_law_gpu(nb):
+    s = inputs.plummer(20000, 8)
+    acc, _ = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision="fp64")
+    a = host(acc)
+    total = (a * s.mass).sum(axis=1)
+    assert np.max(np.abs(total)) < 1e-12 * np.abs(a * s.mass).sum()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_plummer64k_sampled(nb, oracle, prec):
+    """Plummer sphere n = 65536, eps = 1e-2 (the compensated-FP32 accuracy workload):
+    256 random particles plus the 64 nearest the centre against the oracle."""
+    s = inputs.make("plummer64k")
+    r = np.sqrt((s.pos ** 2).sum(axis=0))
+    g = np.random.Generator(np.random.PCG64(0))
+    idx = np.unique(np.concatenate([g.choice(s.n, 256, replace=False), np.argsort(r)[:64], [0, s.n - 1]]))
+    acc_ref, pot_ref = oracle.forces_sample(s.pos, s.mass, idx, eps=1e-2)
+    acc, pot = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision=prec, want_pot=True)
+    acc, pot = host(acc)[:, idx], host(pot)[idx]
+    e = force_err(acc, acc_ref)
+    print("plummer64k %s max e_i = %.3e" % (prec, e))
+    assert e <= TOL_F[prec]
+    assert np.max(np.abs(pot - pot_ref) / np.abs(pot_ref)) <= TOL_P[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_plummer1m_sampled(nb, oracle, prec):
+    """Full-size Plummer sphere n = 1048576, eps = 1e-3, in the launch configuration the
+    benchmark times: sampled particles (including the ragged last block) vs the oracle."""
+    s = inputs.make("plummer1m")
+    g = np.random.Generator(np.random.PCG64(1))
+    r = np.sqrt((s.pos ** 2).sum(axis=0))
+    idx = np.unique(np.concatenate([g.choice(s.n, 24, replace=False), np.argsort(r)[:8], [0, s.n - 1]]))
+    acc_ref, pot_ref = oracle.forces_sample(s.pos, s.mass, idx, eps=1e-3)
+    acc, pot = nb.forces(dev(s.pos), dev(s.mass), eps=1e-3, precision=prec, want_pot=True)
+    acc, pot = host(acc)[:, idx], host(pot)[idx]
+    e = force_err(acc, acc_ref)
+    print("plummer1m %s max e_i = %.3e" % (prec, e))
+    assert e <= TOL_F[prec]
+    assert np.max(np.abs(pot - pot_ref) / np.abs(pot_ref)) <= TOL_P[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_determinism(nb, prec):
+    s = inputs.plummer(5000, 9)
+    a1, p1 = nb.forces(dev(s.pos), dev(s.mass), precision=prec, want_pot=True)
+    a2, p2 = nb.forces(dev(s.pos), dev(s.mass), precision=prec, want_pot=True)
+    assert np.array_equal(host(a1), host(a2)) and np.array_equal(host(p1), host(p2))
+
+
+def test_golden_cube1k_rollout_fp64(nb):
+    """Uniform cube n = 1024, 10 KDK steps dt = 1e-3 in FP64 against the stored oracle fixture."""
+    import importlib.util
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("mg", os.path.join(here, "golden", "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    stored = mg.read(os.path.join(here, "golden", "cube1k_oracle.txt"))
+    s = inputs.make("cube1k")
+    pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+    acc, pot = nb.forces(pos, mass, eps=1e-2, precision="fp64", want_pot=True)
+    p = stored["particles"]
+    idx = p[:, 0].astype(int)
+    assert force_err(host(acc)[:, idx], p[:, 1:4].T) <= 1e-12
+    _, trace = nb.rollout(pos, vel, mass, acc, 1e-3, 10, energy_trace=True, eps=1e-2, precision="fp64")
+    x, v = host(pos)[:, idx], host(vel)[:, idx]
+    np.testing.assert_allclose(x, p[:, 5:8].T, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(v, p[:, 8:11].T, rtol=1e-9, atol=1e-12)
+    E = stored["energy"][:, 1:]
+    tr = host(trace)[:, 0, :]
+    np.testing.assert_allclose(tr[:, :2], E[:, :2], rtol=1e-12)
+    np.testing.assert_allclose(tr[:, 2:], E[:, 2:], atol=1e-15)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_rollout_vs_oracle_and_energy(nb, oracle, prec):
+    s = inputs.plummer(2048, 10)
+    xr, vr, _, er = oracle.kdk(s.pos, s.vel, s.mass, 1e-3, 20, eps=1e-2, want_energy=True)
+    pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+    acc, _ = nb.forces(pos, mass, eps=1e-2, precision=prec)
+    _, trace = nb.rollout(pos, vel, mass, acc, 1e-3, 20, energy_trace=True, eps=1e-2, precision=prec)
+    x, v, tr = host(pos), host(vel), host(trace)[:, 0, :]
+    rmsx = math.sqrt(np.mean(s.pos ** 2))
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert np.max(np.abs(x - xr)) / rmsx <= tol
+    E_ref = er[:, 0] + er[:, 1]
+    E = tr[:, 0] + tr[:, 1]
+    assert np.max(np.abs(E - E_ref) / abs(E_ref[0])) <= (1e-12 if prec == "fp64" else 1e-6)
+    # FP32 pair forces obey Newton's third law only to float rounding, so momentum drifts
+    # by about steps * dt * 1e-7 sum m|a| in the FP32 modes
+    assert np.max(np.abs(tr[:, 2:] - er[:, 2:])) <= (1e-12 if prec == "fp64" else 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_energy_momentum_entry(nb, oracle, prec):
+    s = inputs.plummer(3000, 11)
+    ref = oracle.energy_momentum(s.pos, s.vel, s.mass, eps=1e-2)
+    out = host(nb.energy_momentum(dev(s.pos), dev(s.vel), dev(s.mass), eps=1e-2, precision=prec))[0]
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert abs(out[0] - ref[0]) <= 1e-13 * abs(ref[0])
+    assert abs(out[1] - ref[1]) <= tol * abs(ref[1])
+    assert np.max(np.abs(out[2:] - ref[2:])) <= 1e-14
+
+
+def test_step_equals_rollout(nb):
+    s = inputs.plummer(1500, 12)
+    p1, v1, m = dev(s.pos), dev(s.vel), dev(s.mass)
+    a1, _ = nb.forces(p1, m, precision="fp32c")
+    p2, v2, a2 = p1.clone(), v1.clone(), a1.clone()
+    for _ in range(5):
+        nb.step(p1, v1, m, a1, 1e-3, precision="fp32c")
+    nb.rollout(p2, v2, m, a2, 1e-3, 5, precision="fp32c")
+    assert np.array_equal(host(p1), host(p2)) and np.array_equal(host(v1), host(v2))
+
+
+def test_rollout_energy_trace_does_not_change_state(nb):
+    """The potential-carrying force pass leaves the trajectory bitwise unchanged."""
+    s = inputs.plummer(1500, 13)
+    outs = []
+    for et in (False, True):
+        p, v, m = dev(s.pos), dev(s.vel), dev(s.mass)
+        a, _ = nb.forces(p, m, precision="fp32c")
+        nb.rollout(p, v, m, a, 1e-3, 6, energy_trace=et, precision="fp32c")
+        outs.append((host(p), host(v)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+# ------------------------------------------------------------------ batched
+
+def _batch(S, seed, nmin=64, nmax=1500):
+    return inputs.batched_mix(S, seed, nmin=nmin, nmax=nmax)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batched_vs_oracle_and_loop(nb, oracle, prec):
+    b = _batch(24, 3)
+    off = b.offsets
+    acc_ref, pot_ref = oracle.forces_batched(b.pos, b.mass, off, eps=1e-2)
+    acc, pot = nb.forces(dev(b.pos), dev(b.mass), eps=1e-2, precision=prec, want_pot=True, offsets=off)
+    accl, potl = nb.forces(dev(b.pos), dev(b.mass), eps=1e-2, precision=prec, want_pot=True, offsets=off,
+                           flags=nb.FLAG_LOOP_SYSTEMS)
+    acc, pot, accl, potl = host(acc), host(pot), host(accl), host(potl)
+    for s in range(len(off) - 1):
+        sl = slice(off[s], off[s + 1])
+        if prec == "fp64":
+            assert force_err(acc[:, sl], acc_ref[:, sl]) <= TOL_F[prec]
+            assert force_err(accl[:, sl], acc_ref[:, sl]) <= TOL_F[prec]
+        else:
+            check_fp32(acc[:, sl], acc_ref[:, sl], b.pos[:, sl], b.mass[sl], 1e-2, prec)
+            check_fp32(accl[:, sl], acc_ref[:, sl], b.pos[:, sl], b.mass[sl], 1e-2, prec)
+        assert np.max(np.abs(pot[sl] - pot_ref[sl]) / np.abs(pot_ref[sl])) <= TOL_P[prec]
+
+
+def test_batched_empty_and_single_systems(nb, oracle):
+    off = np.array([0, 0, 1, 1, 130, 130, 700], dtype=np.int64)
+    g = np.random.Generator(np.random.PCG64(5))
+    n = int(off[-1])
+    pos = g.random((3, n))
+    mass = g.uniform(0.5, 1.5, n) / n
+    vel = g.normal(size=(3, n)) * 0.1
+    acc_ref, _ = oracle.forces_batched(pos, mass, off, eps=1e-2)
+    acc, _ = nb.forces(dev(pos), dev(mass), eps=1e-2, precision="fp64", offsets=off)
+    acc = host(acc)
+    assert np.all(acc[:, 0] == 0)
+    for s in range(len(off) - 1):
+        sl = slice(off[s], off[s + 1])
+        if off[s + 1] - off[s] > 1:
+            assert force_err(acc[:, sl], acc_ref[:, sl]) <= 1e-12
+    em = host(nb.energy_momentum(dev(pos), dev(vel), dev(mass), eps=1e-2, precision="fp64", offsets=off))
+    assert em.shape == (6, 5)
+    assert np.all(em[[0, 2, 4]] == 0)
+    for s in [1, 3, 5]:
+        sl = slice(off[s], off[s + 1])
+        ref = oracle.energy_momentum(pos[:, sl], vel[:, sl], mass[sl], eps=1e-2)
+        np.testing.assert_allclose(em[s], ref, rtol=1e-12, atol=1e-15)
+
+
+def test_batched_rollout_energy(nb, oracle):
+    b = _batch(10, 4)
+    off = b.offsets
+    pos, vel, mass = dev(b.pos), dev(b.vel), dev(b.mass)
+    acc, _ = nb.forces(pos, mass, eps=1e-2, precision="fp64", offsets=off)
+    _, trace = nb.rollout(pos, vel, mass, acc, 1e-3, 5, energy_trace=True, eps=1e-2, precision="fp64", offsets=off)
+    tr = host(trace)
+    x = host(pos)
+    for s in range(len(off) - 1):
+        sl = slice(off[s], off[s + 1])
+        xr, _, _, er = oracle.kdk(b.pos[:, sl], b.vel[:, sl], b.mass[sl], 1e-3, 5, eps=1e-2, want_energy=True)
+        assert np.max(np.abs(x[:, sl] - xr)) <= 1e-12
+        np.testing.assert_allclose(tr[:, s, :2], er[:, :2], rtol=1e-11)
+
+
+# ------------------------------------------------------------------ adjoint
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32c", 1e-4), ("fp32", 1e-3)])
+def test_rollout_backward_vs_oracle(nb, oracle, prec, tol):
+    s = inputs.two_spheres(150, 21)
+    y = inputs.gaussian_targets(300, 22)
+    dt, steps, ck = 1e-2, 12, 5
+    xK, vK, _, _ = oracle.kdk(s.pos, s.vel, s.mass, dt, steps, eps=1e-1)
+    _, gxK = oracle.loss_msd(xK, y)
+    gvK = np.zeros_like(gxK)
+    gx_ref, gv_ref, gm_ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, dt, steps, gxK, gvK, eps=1e-1)
+    pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+    acc, _ = nb.forces(pos, mass, eps=1e-1, precision=prec)
+    ckpt, _ = nb.rollout(pos, vel, mass, acc, dt, steps, ckpt_every=ck, eps=1e-1, precision=prec)
+    gx, gv, gm = nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), dt, steps, ck, eps=1e-1, precision=prec)
+    assert _rel_l2(host(gx), gx_ref) <= tol
+    assert _rel_l2(host(gv), gv_ref) <= tol
+    assert _rel_l2(host(gm), gm_ref) <= tol
+
+
+def test_backward_checkpoint_interval_invariance(nb):
+    """Gradients are bitwise independent of the checkpoint interval (recomputation
+    reproduces the forward trajectory exactly)."""
+    s = inputs.plummer(700, 23)
+    g = np.random.Generator(np.random.PCG64(24))
+    gxK, gvK = g.normal(size=(3, 700)), g.normal(size=(3, 700))
+    steps = 14
+    res = []
+    for ck in (1, 3, 7, 14, 20):
+        pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+        acc, _ = nb.forces(pos, mass, precision="fp32c")
+        ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, steps, ckpt_every=ck, precision="fp32c")
+        out = nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, steps, ck, precision="fp32c")
+        res.append([host(t) for t in out])
+    for r in res[1:]:
+        for a, b in zip(r, res[0]):
+            assert np.array_equal(a, b)
+
+
+def test_force_vjp_single_step(nb, oracle):
+    """One step exercises both half-kick adjoints: compare with the oracle on a Plummer sphere."""
+    s = inputs.plummer(1000, 25)
+    g = np.random.Generator(np.random.PCG64(26))
+    gxK, gvK = g.normal(size=(3, 1000)), g.normal(size=(3, 1000))
+    ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, 1e-3, 1, gxK, gvK, eps=1e-2)
+    pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+    acc, _ = nb.forces(pos, mass, precision="fp64")
+    ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 1, ckpt_every=1, precision="fp64")
+    out = nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 1, 1, precision="fp64")
+    for a, b in zip(out, ref):
+        assert _rel_l2(host(a), b) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_batched_backward_vs_loop_and_oracle(nb, oracle, prec):
+    b = _batch(8, 27, nmin=64, nmax=700)
+    off = b.offsets
+    n = b.mass.shape[0]
+    g = np.random.Generator(np.random.PCG64(28))
+    gxK, gvK = g.normal(size=(3, n)), g.normal(size=(3, n))
+    outs = []
+    for flags in (0, nb.FLAG_LOOP_SYSTEMS):
+        pos, vel, mass = dev(b.pos), dev(b.vel), dev(b.mass)
+        acc, _ = nb.forces(pos, mass, precision=prec, offsets=off, flags=flags)
+        ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 6, ckpt_every=3, precision=prec, offsets=off, flags=flags)
+        outs.append([host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 6, 3,
+                                                          precision=prec, offsets=off, flags=flags)])
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    for s in range(len(off) - 1):
+        sl = slice(off[s], off[s + 1])
+        ref = oracle.rollout_adjoint(b.pos[:, sl], b.vel[:, sl], b.mass[sl], 1e-3, 6, gxK[:, sl], gvK[:, sl],
+                                     eps=1e-2)
+        for k in range(3):
+            for o in outs:
+                a = o[k][..., sl]
+                assert _rel_l2(a, ref[k]) <= tol
+
+
+def test_autograd_function(nb, oracle):
+    import torch
+    s = inputs.two_spheres(64, 30)
+    y = inputs.gaussian_targets(128, 31)
+    x0 = dev(s.pos).requires_grad_(True)
+    v0 = dev(s.vel).requires_grad_(True)
+    m = dev(s.mass).requires_grad_(True)
+    xK, vK = nb.rollout_fn(x0, v0, m, 1e-2, 10, 4, eps=0.1, precision="fp64")
+    loss = ((xK - dev(y)) ** 2).sum() / 128
+    loss.backward()
+    xr, _, _, _ = oracle.kdk(s.pos, s.vel, s.mass, 1e-2, 10, eps=0.1)
+    lr, gxK = oracle.loss_msd(xr, y)
+    ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, 1e-2, 10, gxK, np.zeros_like(gxK), eps=0.1)
+    assert abs(loss.item() - lr) <= 1e-12 * lr
+    for t, r in zip((x0.grad, v0.grad, m.grad), ref):
+        assert _rel_l2(host(t), r) <= 1e-10
