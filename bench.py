@@ -1,0 +1,346 @@
+"""Benchmark of the all-pairs N-body hot path on one MI355X.
+
+One timed step = the Plummer N = 1,048,576 workload (eps = 1e-3): one force pass with
+the fused potential, the energy/momentum reduction at t = 0, 10 kick-drift-kick steps
+of dt = 5e-4 (one force pass each), and the energy/momentum reduction at the end
+(its potential costs one more force pass): 12 all-pairs evaluations, FP32 pair math
+with compensated accumulation, FP64 state and reductions. Inputs are resident on the
+GPU before the timed region.
+
+Printed: ONE JSON line with the throughput in pair interactions/s, the roofline of the
+dominant kernel (the FP32 force pass, 20 flop per interaction against the 157.3
+TFLOP/s FP32 vector peak), the force error of this run against the FP64 GPU path and
+the CPU oracle, the adjoint and batched legs, and the CPU oracle timed on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12          # MI355X FP32 vector, FLOP/s
+FLOP_PER_INTERACTION = 20.0   # forward pair-interaction convention
+METRIC = "pair interactions/s (fwd & adjoint), % FP32 vector peak, at stated error"
+KERNEL_SRC = os.path.join(ROOT, "paper_2511_02655_amd", "csrc", "nbody_kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_fp32c_plummer1m_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(per_launch_n2):
+    """HBM bytes per force launch from the stored rocprofv3 counter runs, or None when
+    the kernel source has changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
+    ap.add_argument("--n", type=int, default=1048576)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the whole system on a single MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2511_02655_amd as nb
+    from paper_2511_02655_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    nb.lib()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    W = inputs.WORKLOADS["plummer1m"]
+    n, eps, dt, ksteps = args.n, W["eps"], W["dt"], W["steps"]
+    prec = args.precision
+    log("generating Plummer n=%d" % n)
+    s = inputs.plummer(n, W["seed"])
+    pos0 = torch.from_numpy(s.pos).to(dev)
+    vel0 = torch.from_numpy(s.vel).to(dev)
+    mass = torch.from_numpy(s.mass).to(dev)
+    pos, vel = pos0.clone(), vel0.clone()
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    evals_per_step = 1 + ksteps + 1
+    inter_per_step = evals_per_step * float(n) * float(n)
+
+    force_events = []
+
+    def one_step(timed):
+        pos.copy_(pos0)
+        vel.copy_(vel0)
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        nb.forces(pos, mass, eps=eps, precision=prec, want_pot=True, out_acc=acc, out_pot=pot)
+        if timed:
+            e1.record()
+            force_events.append((e0, e1))
+        em0 = nb.energy_momentum(pos, vel, mass, pot, eps=eps, precision=prec)
+        nb.rollout(pos, vel, mass, acc, dt, ksteps, eps=eps, precision=prec)
+        em1 = nb.energy_momentum(pos, vel, mass, None, eps=eps, precision=prec)
+        return em0, em1
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    log("timing %d steps" % args.steps)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        em0, em1 = one_step(True)
+        torch.cuda.synchronize()
+        log("  step %d done" % k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = inter_per_step * args.steps / elapsed
+    force_ms = float(np.mean([a.elapsed_time(b) for a, b in force_events]))
+    achieved = FLOP_PER_INTERACTION * float(n) * float(n) / (force_ms * 1e-3)
+    em0 = em0.cpu().numpy()[0]
+    em1 = em1.cpu().numpy()[0]
+    E0, E1 = em0[0] + em0[1], em1[0] + em1[1]
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "plummer1m: Plummer sphere N=%d (M=1, a=1, seed %d), eps=%g; per step 1 force pass with "
+                        "potential + energy/momentum, %d KDK steps dt=%g, energy/momentum at the end "
+                        "(%d all-pairs evaluations); %s pair math, FP64 state and reductions"
+                        % (n, W["seed"], eps, ksteps, dt, evals_per_step, prec),
+            "n": n, "eps": eps, "dt": dt, "kdk_steps": ksteps, "evaluations_per_step": evals_per_step,
+            "precision": prec,
+        },
+        "pct_fp32_peak": 100.0 * FLOP_PER_INTERACTION * value / PEAK_FP32,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "force_kernel<float,compensated,potential>",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32,
+            "traffic": stored_traffic(n),
+            "avg_launch_ms": force_ms,
+            "flop_per_interaction": FLOP_PER_INTERACTION,
+            "interactions_per_launch": float(n) * float(n),
+        },
+        "energy": {"E0": E0, "E_end": E1, "rel_drift": abs(E1 - E0) / abs(E0),
+                   "P_end": [float(x) for x in em1[2:]]},
+    }
+
+    if not args.no_extras:
+        out["error"] = force_errors(nb, torch, np, pos0, mass, s, eps, prec)
+        out["adjoint"] = adjoint_leg(nb, torch, np, inputs, dev)
+        out["batched"] = batched_leg(nb, torch, np, inputs, dev)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(np, s, eps)
+    print(json.dumps(out), flush=True)
+
+
+def force_errors(nb, torch, np, pos0, mass, s, eps, prec):
+    """Force error of this run's precision: every particle against the FP64 GPU path,
+    and a sample against the FP64 CPU oracle."""
+    import oracle
+    log("error leg")
+    a32, p32 = nb.forces(pos0, mass, eps=eps, precision=prec, want_pot=True)
+    a64, p64 = nb.forces(pos0, mass, eps=eps, precision="fp64", want_pot=True)
+    d = torch.sqrt(((a32 - a64) ** 2).sum(0))
+    m = torch.sqrt((a64 ** 2).sum(0))
+    rms = torch.sqrt((m ** 2).mean())
+    e = d / torch.clamp(m, min=1e-6 * rms.item())
+    g = np.random.Generator(np.random.PCG64(7))
+    idx = np.sort(g.choice(s.n, 32, replace=False))
+    ar, _ = oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
+    a = a32.cpu().numpy()[:, idx]
+    dd = np.sqrt(((a - ar) ** 2).sum(0))
+    mm = np.sqrt((ar ** 2).sum(0))
+    return {
+        "vs_fp64_gpu_all": {"max_e": float(e.max()), "p999_e": float(torch.quantile(e[::16].float(), 0.999)),
+                            "max_abs_over_rms": float((d / rms).max())},
+        "vs_oracle_sample32": {"max_e": float(np.max(dd / np.maximum(mm, 1e-6 * math.sqrt(np.mean(mm ** 2)))))},
+        "phi_vs_fp64_gpu_max_rel": float((torch.abs(p32 - p64) / torch.abs(p64)).max()),
+        "metric": "e_i = |a_i - a_i^ref| / max(|a_i^ref|, 1e-6 rms|a^ref|)",
+    }
+
+
+def adjoint_leg(nb, torch, np, inputs, dev):
+    """Two-sphere merger N = 2 x 8192, eps = 1e-2, 200 KDK steps dt = 1e-3, checkpoints
+    every 20; loss = mean squared distance of the final positions to a Gaussian target
+    set; gradient w.r.t. initial positions, velocities and masses (FP32 compensated)."""
+    log("adjoint leg")
+    W = inputs.WORKLOADS["merger2x8k"]
+    s = inputs.make("merger2x8k")
+    y = torch.from_numpy(inputs.gaussian_targets(s.n, W["target_seed"])).to(dev)
+    x0 = torch.from_numpy(s.pos).to(dev)
+    v0 = torch.from_numpy(s.vel).to(dev)
+    m = torch.from_numpy(s.mass).to(dev)
+    prec = "fp32c"
+
+    # forward + backward timing (backward includes the recomputation between checkpoints)
+    ckpt_every = W["ckpt"]
+    pos, vel = x0.clone(), v0.clone()
+    acc, _ = nb.forces(pos, m, eps=W["eps"], precision=prec)
+    ckpt, _ = nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], ckpt_every=ckpt_every, eps=W["eps"], precision=prec)
+    gxK = (2.0 / s.n) * (pos - y)
+    gvK = torch.zeros_like(gxK)
+    nb.rollout_backward(m, ckpt, gxK, gvK, W["dt"], W["steps"], ckpt_every, eps=W["eps"], precision=prec)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        pos.copy_(x0)
+        vel.copy_(v0)
+        nb.forces(pos, m, eps=W["eps"], precision=prec, out_acc=acc)
+        nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], ckpt_every=ckpt_every, eps=W["eps"], precision=prec,
+                   ckpt=ckpt)
+    e1.record()
+    for _ in range(reps):
+        g32 = nb.rollout_backward(m, ckpt, gxK, gvK, W["dt"], W["steps"], ckpt_every, eps=W["eps"], precision=prec)
+    e2.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    bwd_ms = e1.elapsed_time(e2) / reps
+    n2 = float(s.n) ** 2
+    adj_passes = W["steps"] + 1
+    # FP64 GPU reference gradient for the error statement
+    pos64, vel64 = x0.clone(), v0.clone()
+    acc64, _ = nb.forces(pos64, m, eps=W["eps"], precision="fp64")
+    ck64, _ = nb.rollout(pos64, vel64, m, acc64, W["dt"], W["steps"], ckpt_every=ckpt_every, eps=W["eps"],
+                         precision="fp64")
+    gxK64 = (2.0 / s.n) * (pos64 - y)
+    g64 = nb.rollout_backward(m, ck64, gxK64, torch.zeros_like(gxK64), W["dt"], W["steps"], ckpt_every,
+                              eps=W["eps"], precision="fp64")
+    rel = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(g32, g64)]
+    return {
+        "workload": "merger2x8k: two Plummer spheres N=2x8192, eps=1e-2, 200 KDK steps dt=1e-3, ckpt every 20, "
+                    "MSD loss to Gaussian targets; FP32 compensated",
+        "forward_ms": fwd_ms,
+        "backward_ms": bwd_ms,
+        "adjoint_passes": adj_passes,
+        "recompute_force_passes": W["steps"],
+        "adjoint_interactions_per_s_incl_recompute": adj_passes * n2 / (bwd_ms * 1e-3),
+        "forward_interactions_per_s": (W["steps"] + 1) * n2 / (fwd_ms * 1e-3),
+        "grad_rel_l2_vs_fp64_gpu": {"x0": rel[0], "v0": rel[1], "m": rel[2]},
+    }
+
+
+def batched_leg(nb, torch, np, inputs, dev):
+    """512 independent systems, N per system log-uniform in [64, 8192], cube or Plummer;
+    eps = 1e-2, dt = 1e-3, 50 KDK steps, FP32 compensated forward + adjoint: one persistent
+    launch per batched pass against looping the single-system kernels."""
+    log("batched leg")
+    W = inputs.WORKLOADS["batch512"]
+    b = inputs.make("batch512")
+    off = b.offsets
+    sizes = np.diff(off)
+    sum_n2 = float(np.sum(sizes.astype(np.float64) ** 2))
+    x0 = torch.from_numpy(b.pos).to(dev)
+    v0 = torch.from_numpy(b.vel).to(dev)
+    m = torch.from_numpy(b.mass).to(dev)
+    res = {"workload": "batch512: 512 systems, N_s log-uniform [64, 8192] (sum N = %d, sum N^2 = %.3e), eps=1e-2, "
+                       "50 KDK steps dt=1e-3, FP32 compensated" % (int(off[-1]), sum_n2)}
+    for name, flags in (("persistent", 0), ("looped", nb.FLAG_LOOP_SYSTEMS)):
+        pos, vel = x0.clone(), v0.clone()
+        acc, _ = nb.forces(pos, m, eps=W["eps"], precision="fp32c", offsets=off, flags=flags)
+        ckpt, _ = nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], ckpt_every=10, eps=W["eps"], precision="fp32c",
+                             offsets=off, flags=flags)
+        gx = torch.ones_like(pos)
+        gv = torch.zeros_like(pos)
+        nb.rollout_backward(m, ckpt, gx, gv, W["dt"], W["steps"], 10, eps=W["eps"], precision="fp32c", offsets=off,
+                            flags=flags)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        pos.copy_(x0)
+        vel.copy_(v0)
+        nb.forces(pos, m, eps=W["eps"], precision="fp32c", offsets=off, flags=flags, out_acc=acc)
+        nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], ckpt_every=10, eps=W["eps"], precision="fp32c",
+                   offsets=off, flags=flags, ckpt=ckpt)
+        e1.record()
+        g = nb.rollout_backward(m, ckpt, gx, gv, W["dt"], W["steps"], 10, eps=W["eps"], precision="fp32c",
+                                offsets=off, flags=flags)
+        e2.record()
+        torch.cuda.synchronize()
+        f_ms = e0.elapsed_time(e1)
+        b_ms = e1.elapsed_time(e2)
+        res[name] = {"forward_ms": f_ms, "backward_ms": b_ms,
+                     "forward_interactions_per_s": (W["steps"] + 1) * sum_n2 / (f_ms * 1e-3),
+                     "adjoint_interactions_per_s_incl_recompute": (W["steps"] + 1) * sum_n2 / (b_ms * 1e-3)}
+        res[name + "_final_pos"] = pos
+    d = float(torch.max(torch.abs(res["persistent_final_pos"] - res["looped_final_pos"])))
+    del res["persistent_final_pos"], res["looped_final_pos"]
+    res["max_abs_pos_diff_persistent_vs_looped"] = d
+    res["speedup_forward"] = res["looped"]["forward_ms"] / res["persistent"]["forward_ms"]
+    res["speedup_backward"] = res["looped"]["backward_ms"] / res["persistent"]["backward_ms"]
+    return res
+
+
+def cpu_baseline(np, s, eps, target_s=12.0):
+    """The CPU oracle (FP64, OpenMP over particles) on a bounded sample of the same
+    workload: k particles against all N, k scaled to about target_s seconds."""
+    import oracle
+    log("cpu baseline")
+    threads = oracle.num_threads()
+    g = np.random.Generator(np.random.PCG64(11))
+    k = 64
+    idx = np.sort(g.choice(s.n, k, replace=False))
+    t0 = time.perf_counter()
+    oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
+    t1 = time.perf_counter() - t0
+    k2 = int(min(s.n, max(k, k * target_s / max(t1, 1e-3))))
+    idx = np.sort(g.choice(s.n, k2, replace=False))
+    t0 = time.perf_counter()
+    oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
+    t2 = time.perf_counter() - t0
+    return {"value": k2 * float(s.n) / t2, "unit": "pair interactions/s", "cores": threads, "kind": "oracle",
+            "sample": "%d random particles of the Plummer N=%d system against all N (one FP64 force evaluation "
+                      "restricted to the sample), %.1f s" % (k2, s.n, t2)}
+
+
+if __name__ == "__main__":
+    main()
