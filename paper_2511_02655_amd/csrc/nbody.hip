@@ -149,6 +149,25 @@ const ForceVariant kForce64[] = {FV64(256, 1, 256), FV64(128, 1, 128), FV64(64, 
 const AdjVariant kAdj32[] = {AV32(256, 1, 256), AV32(128, 1, 128), AV32(64, 1, 128)};
 const AdjVariant kAdj64[] = {AV64(256, 1, 256), AV64(128, 1, 128), AV64(64, 1, 64)};
 
+// Symmetric FP32 force variants (each pair once), indices kNumForce32 + k in the
+// FORCE tile table.
+using SymFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part);
+template <int W, int I, bool POT, bool COMP>
+void launch_sym(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part) {
+  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, COMP>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
+}
+struct SymVariant {
+  int w, i;
+  SymFn fn[2][2];  // [pot][comp]
+};
+#define SV32(W, I)                                                                            \
+  SymVariant {                                                                                \
+    W, I, {{launch_sym<W, I, false, false>, launch_sym<W, I, false, true>},                   \
+           {launch_sym<W, I, true, false>, launch_sym<W, I, true, true>}}                     \
+  }
+const SymVariant kSym32[] = {SV32(8, 4), SV32(4, 4), SV32(8, 2), SV32(4, 2)};
+constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
+
 constexpr int kNumForce32 = sizeof(kForce32) / sizeof(kForce32[0]);
 constexpr int kNumForce64 = sizeof(kForce64) / sizeof(kForce64[0]);
 constexpr int kNumAdj32 = sizeof(kAdj32) / sizeof(kAdj32[0]);
@@ -158,12 +177,25 @@ bool is_fp64(int prec) { return prec == NBODY_FP64; }
 
 int num_variants(int kernel, int prec) {
   bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
+  if (kernel == NBODY_KERNEL_FORCE && !is_fp64(prec)) return kNumForce32 + kNumSym32;
   if (f) return is_fp64(prec) ? kNumForce64 : kNumForce32;
   return is_fp64(prec) ? kNumAdj64 : kNumAdj32;
 }
 
+// Symmetric variant index (or -1) of a FORCE tile variant.
+int sym_index(int kernel, int prec, int v) {
+  if (kernel != NBODY_KERNEL_FORCE || is_fp64(prec) || v < kNumForce32) return -1;
+  return v - kNumForce32;
+}
+
 void variant_shape(int kernel, int prec, int v, int& bs, int& i, int& tj) {
   bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
+  int sv = sym_index(kernel, prec, v);
+  if (sv >= 0) {
+    // symmetric: block of bs = W*64 threads, i per lane, tile edge tj = W*64*I
+    bs = kSym32[sv].w * 64; i = kSym32[sv].i; tj = bs * i;
+    return;
+  }
   if (f) {
     const ForceVariant& fv = is_fp64(prec) ? kForce64[v] : kForce32[v];
     bs = fv.bs; i = fv.i; tj = fv.tj;
@@ -182,6 +214,7 @@ struct Tile {
   int variant;
   int bs, i, tj;
   int64_t j_split;  // single: number of j-ranges; batched: j-chunk length
+  int sym = -1;     // symmetric variant index (single-system FP32 force only)
 };
 
 int g_num_cu = 0;
@@ -205,7 +238,16 @@ Tile default_tile(int kernel, int prec, int64_t n) {
   t.variant = 0;
   if (n <= 4096) t.variant = (kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED)
                                  ? (is_fp64(prec) ? 1 : 3) : 1;
+  if (kernel == NBODY_KERNEL_FORCE && !is_fp64(prec)) {
+    if (n >= 262144) t.variant = kNumForce32 + 0;      // symmetric, 2048-particle blocks
+    else if (n >= 32768) t.variant = kNumForce32 + 1;  // symmetric, 1024-particle blocks
+  }
+  t.sym = sym_index(kernel, prec, t.variant);
   variant_shape(kernel, prec, t.variant, t.bs, t.i, t.tj);
+  if (t.sym >= 0) {
+    t.j_split = 1;
+    return t;
+  }
   if (batched) {
     t.j_split = 1024;
   } else {
@@ -226,8 +268,9 @@ Tile lookup_tile(int kernel, int prec, int64_t n) {
         e.variant >= 0 && e.variant < num_variants(kernel, prec) && e.j_split >= 1) {
       Tile t{};
       t.variant = e.variant;
+      t.sym = sym_index(kernel, prec, t.variant);
       variant_shape(kernel, prec, t.variant, t.bs, t.i, t.tj);
-      t.j_split = e.j_split;
+      t.j_split = t.sym >= 0 ? 1 : e.j_split;
       bool batched = kernel == NBODY_KERNEL_FORCE_BATCHED || kernel == NBODY_KERNEL_ADJOINT_BATCHED;
       if (batched) t.j_split = std::max<int64_t>(t.tj, cdiv(t.j_split, t.tj) * t.tj);
       return t;
@@ -301,7 +344,7 @@ struct Plan {
   int64_t n_units_force = 0, n_units_adj = 0;
   // buffers
   size_t off_jbuf = 0, sz_jbuf = 0;
-  size_t off_part = 0, sz_part = 0, part_planes = 0;
+  size_t off_part = 0, sz_part = 0;
   size_t off_epart = 0, sz_epart = 0;
   size_t off_pot = 0, sz_pot = 0;
   size_t off_accs = 0, sz_accs = 0;   // scratch acc [3][n]
@@ -364,18 +407,37 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     return o;
   };
   int64_t force_S = 1, adj_S = 1;
+  size_t force_part = 0, adj_part = 0;  // bytes of partial sums each pass writes
+  const size_t nd = (size_t)n * dsz;
   UnitSet local_f, local_a;
   UnitSet& ufs = uf ? *uf : local_f;
   UnitSet& uas = ua ? *ua : local_a;
+  // partial sums of one system of ns particles under tile t (0 when written directly)
+  auto single_force_part = [&](const Tile& t, int64_t ns) -> size_t {
+    if (t.sym >= 0) {
+      const int64_t nb = cdiv(ns, (int64_t)t.tj);
+      return (size_t)nb * 4 * (size_t)ns * sizeof(float);
+    }
+    int64_t S, jc;
+    split_geometry(t, ns, S, jc);
+    return S > 1 ? (size_t)S * 4 * nd : 0;
+  };
+  auto single_adj_part = [&](const Tile& t, int64_t ns) -> size_t {
+    int64_t S, jc;
+    split_geometry(t, ns, S, jc);
+    return S > 1 ? (size_t)S * 8 * nd : 0;
+  };
   if (bat && !loop) {
     Tile tf = lookup_tile(NBODY_KERNEL_FORCE_BATCHED, prec, sys.max_n);
     build_units(sys, tf, ufs);
     force_S = max_nsplit(ufs);
+    force_part = (size_t)force_S * 4 * nd;  // the persistent kernels always write partials
     p.n_units_force = (int64_t)ufs.units.size();
     if (need & NEED_BACKWARD) {
       Tile ta = lookup_tile(NBODY_KERNEL_ADJOINT_BATCHED, prec, sys.max_n);
       build_units(sys, ta, uas);
       adj_S = max_nsplit(uas);
+      adj_part = (size_t)adj_S * 8 * nd;
       p.n_units_adj = (int64_t)uas.units.size();
     }
     p.off_meta = off;
@@ -388,37 +450,18 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     for (int64_t s = 0; s < sys.S; ++s) {
       int64_t ns = sys.off[s + 1] - sys.off[s];
       if (ns == 0) continue;
-      Tile tf = lookup_tile(NBODY_KERNEL_FORCE, prec, ns);
-      int64_t S, jc;
-      split_geometry(tf, ns, S, jc);
-      force_S = std::max(force_S, S);
-      if (need & NEED_BACKWARD) {
-        Tile ta = lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns);
-        split_geometry(ta, ns, S, jc);
-        adj_S = std::max(adj_S, S);
-      }
+      force_part = std::max(force_part, single_force_part(lookup_tile(NBODY_KERNEL_FORCE, prec, ns), ns));
+      if (need & NEED_BACKWARD)
+        adj_part = std::max(adj_part, single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns), ns));
     }
   } else {
-    Tile tf = lookup_tile(NBODY_KERNEL_FORCE, prec, n);
-    int64_t jc;
-    split_geometry(tf, n, force_S, jc);
-    if (need & NEED_BACKWARD) {
-      Tile ta = lookup_tile(NBODY_KERNEL_ADJOINT, prec, n);
-      split_geometry(ta, n, adj_S, jc);
-    }
+    force_part = single_force_part(lookup_tile(NBODY_KERNEL_FORCE, prec, n), n);
+    if (need & NEED_BACKWARD) adj_part = single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, n), n);
   }
   const size_t vec = is_fp64(prec) ? 32 : 16;
   p.sz_jbuf = (size_t)n * vec * ((need & NEED_BACKWARD) ? 2 : 1);
   p.off_jbuf = take(p.sz_jbuf);
-  // partial sums: the persistent batched kernels always write them (one slot per
-  // j-chunk); the single-system kernels only when the j-range is split.
-  const bool persistent = bat && !loop;
-  size_t part_planes = 0;
-  if (force_S > 1 || persistent) part_planes = std::max<size_t>(part_planes, (size_t)force_S * 4);
-  if ((need & NEED_BACKWARD) && (adj_S > 1 || persistent))
-    part_planes = std::max<size_t>(part_planes, (size_t)adj_S * 8);
-  p.part_planes = part_planes;
-  p.sz_part = part_planes * (size_t)n * dsz;
+  p.sz_part = std::max(force_part, adj_part);
   p.off_part = take(p.sz_part);
   // energy partials: chunks per system
   int64_t chunks = std::min<int64_t>(std::max<int64_t>(1, cdiv(sys.max_n, 256 * 4)), bat ? 16 : 1024);
@@ -518,10 +561,10 @@ int upload_meta(Ctx& c) {
 
 // Host-side guard: a pass about to write `planes` partial planes of n doubles must
 // find them inside the planned partial-sum region.
-int check_part(const Ctx& c, int64_t planes, const char* what) {
-  if ((size_t)planes > c.plan.part_planes)
-    return fail(NBODY_ERR_DEVICE, "internal: %s needs %lld partial planes, plan has %zu", what, (long long)planes,
-                c.plan.part_planes);
+int check_part(const Ctx& c, size_t bytes, const char* what) {
+  if (bytes > c.plan.sz_part)
+    return fail(NBODY_ERR_DEVICE, "internal: %s needs %zu bytes of partial sums, plan has %zu", what, bytes,
+                c.plan.sz_part);
   return NBODY_OK;
 }
 
@@ -583,6 +626,20 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
     const int64_t ns = e - b;
     if (ns == 0) return NBODY_OK;
     Tile t = lookup_tile(NBODY_KERNEL_FORCE, prec, ns);
+    if (t.sym >= 0) {
+      const SymVariant& sv = kSym32[t.sym];
+      const int64_t nb = cdiv(ns, (int64_t)t.tj);
+      const int64_t tiles = nb * (nb + 1) / 2;
+      if (tiles > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many symmetric tiles");
+      TRY(check_part(c, (size_t)nb * 4 * ns * sizeof(float), "force_sym_kernel"));
+      float* pf = (float*)(c.ws + c.plan.off_part);
+      sv.fn[pot_on][comp](dim3((unsigned)tiles), c.st, (const float4*)jarr + b, ns, (int32_t)nb, (float)eps2, pf);
+      LAUNCH_CHECK("force_sym_kernel");
+      hipLaunchKernelGGL(reduce_sym, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)nb, (const float*)pf, c.cfg->G,
+                         acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh);
+      LAUNCH_CHECK("reduce_sym");
+      return NBODY_OK;
+    }
     int64_t S, jc;
     split_geometry(t, ns, S, jc);
     const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
@@ -593,7 +650,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
     if (S == 1) {
       o.acc = acc; o.pot = pot; o.vel = vel; o.hh = hh;
     } else {
-      TRY(check_part(c, S * 4, "force_kernel"));
+      TRY(check_part(c, (size_t)S * 4 * n * sizeof(double), "force_kernel"));
       o.part = part;
     }
     fv.fn[pot_on][comp](g, c.st, jarr, b, e, b, e, jc, eps2, o);
@@ -616,7 +673,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
   // batched persistent launch
   Tile t = lookup_tile(NBODY_KERNEL_FORCE_BATCHED, prec, c.sys.max_n);
   const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
-  TRY(check_part(c, max_nsplit(c.uf) * 4, "force_batched_kernel"));
+  TRY(check_part(c, (size_t)max_nsplit(c.uf) * 4 * n * sizeof(double), "force_batched_kernel"));
   int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter);
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)2, 0);
   LAUNCH_CHECK("fill_i32");
@@ -691,7 +748,7 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
     if (S == 1) {
       o.gpos = gpos; o.gmass = gmass;
     } else {
-      TRY(check_part(c, S * 8, "adjoint_kernel"));
+      TRY(check_part(c, (size_t)S * 8 * n * sizeof(double), "adjoint_kernel"));
       o.part = part;
     }
     av.fn[comp](g, c.st, jadj, b, e, b, e, jc, eps2, o);
@@ -716,7 +773,7 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
   }
   Tile t = lookup_tile(NBODY_KERNEL_ADJOINT_BATCHED, prec, c.sys.max_n);
   const AdjVariant& av = is_fp64(prec) ? kAdj64[t.variant] : kAdj32[t.variant];
-  TRY(check_part(c, max_nsplit(c.ua) * 8, "adjoint_batched_kernel"));
+  TRY(check_part(c, (size_t)max_nsplit(c.ua) * 8 * n * sizeof(double), "adjoint_batched_kernel"));
   int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter) + 1;
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)1, 0);
   LAUNCH_CHECK("fill_i32");
@@ -962,7 +1019,9 @@ __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, i
       int bs, i, tj;
       variant_shape(kernel, precision, v, bs, i, tj);
       char tmp[64];
-      int len = snprintf(tmp, sizeof tmp, "bs=%d,i=%d,tj=%d", bs, i, tj);
+      int len = sym_index(kernel, precision, v) >= 0
+                    ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d", bs, i, tj)
+                    : snprintf(tmp, sizeof tmp, "bs=%d,i=%d,tj=%d", bs, i, tj);
       if (pos + len + 1 > cap) break;
       memcpy(buf + pos, tmp, len + 1);
       pos += len + 1;

@@ -323,6 +323,198 @@ __global__ __launch_bounds__(BS) void force_kernel(const typename Vec4<T>::type*
   force_store<I>(o, ib, ie, blockIdx.y, res, POT, BS);
 }
 
+// ----------------------------------------------------------------- symmetric force pass (FP32)
+
+// Rotate a wave's values one lane to the right (lane l receives lane l-1, lane 0
+// receives lane 63): DPP wave_ror:1, a VALU move with a cross-lane source.
+__device__ __forceinline__ float wave_ror1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x13C, 0xF, 0xF, false));
+}
+
+// Tile t of the upper triangle (A <= B) of an nb x nb block grid, row-major:
+// row A holds tiles B = A .. nb-1, and rows before A hold A*nb - A*(A-1)/2 tiles.
+__device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32_t& B) {
+  const double m = 2.0 * nb + 1.0;
+  int64_t a = (int64_t)((m - sqrt(m * m - 8.0 * (double)t)) * 0.5);
+  if (a < 0) a = 0;
+  if (a > nb - 1) a = nb - 1;
+  auto start = [&](int64_t r) { return r * nb - r * (r - 1) / 2; };
+  while (a > 0 && start(a) > t) --a;
+  while (a + 1 < nb && start(a + 1) <= t) ++a;
+  A = (int32_t)a;
+  B = (int32_t)(a + (t - start(a)));
+}
+
+// Each unordered pair once: a_i += m_j r3 d and a_j -= m_i r3 d (r3 = s^{-3/2}), with
+// phi_i -= m_j s^{-1/2}, phi_j -= m_i s^{-1/2} - the action-reaction symmetry of the
+// pair force halves the separations, square roots and scale factors per interaction.
+//
+// Blocks of BI = W*64*I consecutive particles; one workgroup per tile (A, B), A <= B.
+// Wave w keeps i-particles A*BI + w*64*I + u*64 + lane (u < I) in registers. Block B
+// streams through every wave in sub-blocks of 64 particles, one per lane; at each of
+// 64 steps a lane pairs its I i-particles with the j-particle it holds, then the
+// j-particle and its accumulators move one lane (wave_ror1). After 64 steps every j
+// has met every i of the wave and its accumulator is back in its home lane; the W
+// waves' j-accumulators are summed in LDS in wave order. Diagonal tiles (A == B) pair
+// every i with every j one-sidedly (i-side only, self pair excluded from phi).
+//
+// Output: float partial sums part[(slot*4 + c)*n + p], c = ax, ay, az, phi: the
+// i-side of tile (A, B) goes to slot B, the j-side to slot A, so every particle owns
+// exactly nb slots, summed in double (fixed order) by reduce_sym.
+template <int W, int I, bool POT, bool COMP>
+__global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restrict__ jarr, int64_t n, int32_t nb,
+                                                           float eps2_arg, float* __restrict__ part) {
+  constexpr int BI = W * 64 * I;
+  constexpr int NC = POT ? 4 : 3;
+  constexpr int NSUB = BI / 64;
+  __shared__ float red[2][W][NC][64];
+
+  int32_t A, B;
+  tile_rc(blockIdx.x, nb, A, B);
+  const bool diag = (A == B);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t Abase = (int64_t)A * BI, Bbase = (int64_t)B * BI;
+  const float eps2 = in_vgpr(eps2_arg);
+
+  float xi[I], yi[I], zi[I], mi[I];
+  float ai[NC][I], hi[NC][I], lo[NC][I];
+#pragma unroll
+  for (int u = 0; u < I; ++u) {
+    const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
+    const float4 p = jarr[i < n ? i : n - 1];
+    xi[u] = in_vgpr(p.x);
+    yi[u] = in_vgpr(p.y);
+    zi[u] = in_vgpr(p.z);
+    mi[u] = in_vgpr(i < n ? p.w : 0.f);  // padding lanes carry no mass: no j-side effect
+#pragma unroll
+    for (int c = 0; c < NC; ++c) { ai[c][u] = 0.f; hi[c][u] = 0.f; lo[c][u] = 0.f; }
+  }
+
+  float4 nxt;
+  {
+    const int64_t j = Bbase + lane;
+    nxt = j < n ? jarr[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int sb = 0; sb < NSUB; ++sb) {
+    const float4 q = nxt;
+    if (sb + 1 < NSUB) {
+      const int64_t j = Bbase + (int64_t)(sb + 1) * 64 + lane;
+      nxt = j < n ? jarr[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float xj = q.x, yj = q.y, zj = q.z, mj = q.w;
+    if (diag) {
+      // one-sided: i-side only; the self pair is the step-0 pair of sub-block w*I + u
+      for (int k = 0; k < 64; ++k) {
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+          const float dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+          const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
+          const float ri = __builtin_amdgcn_rsqf(r2);
+          const float mr = mj * ri;
+          const float s = (mr * ri) * ri;
+          ai[0][u] = __builtin_fmaf(s, dx, ai[0][u]);
+          ai[1][u] = __builtin_fmaf(s, dy, ai[1][u]);
+          ai[2][u] = __builtin_fmaf(s, dz, ai[2][u]);
+          if (POT) ai[3][u] -= (k == 0 && sb == w * I + u) ? 0.f : mr;
+        }
+        xj = wave_ror1(xj);
+        yj = wave_ror1(yj);
+        zj = wave_ror1(zj);
+        mj = wave_ror1(mj);
+      }
+    } else {
+      float aj[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) aj[c] = 0.f;
+      for (int k = 0; k < 64; ++k) {
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+          const float dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+          const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
+          const float ri = __builtin_amdgcn_rsqf(r2);
+          const float ri2 = ri * ri;
+          float si, sj;
+          if (POT) {
+            const float mri = mj * ri, mrj = mi[u] * ri;
+            si = mri * ri2;
+            sj = mrj * ri2;
+            ai[3][u] -= mri;
+            aj[3] -= mrj;
+          } else {
+            const float r3 = ri * ri2;
+            si = mj * r3;
+            sj = mi[u] * r3;
+          }
+          ai[0][u] = __builtin_fmaf(si, dx, ai[0][u]);
+          ai[1][u] = __builtin_fmaf(si, dy, ai[1][u]);
+          ai[2][u] = __builtin_fmaf(si, dz, ai[2][u]);
+          aj[0] = __builtin_fmaf(-sj, dx, aj[0]);
+          aj[1] = __builtin_fmaf(-sj, dy, aj[1]);
+          aj[2] = __builtin_fmaf(-sj, dz, aj[2]);
+        }
+        xj = wave_ror1(xj);
+        yj = wave_ror1(yj);
+        zj = wave_ror1(zj);
+        mj = wave_ror1(mj);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) aj[c] = wave_ror1(aj[c]);
+      }
+      // j-side of this sub-block: sum the W waves in wave order, write slot A
+#pragma unroll
+      for (int c = 0; c < NC; ++c) red[sb & 1][w][c][lane] = aj[c];
+      __syncthreads();
+      if (threadIdx.x < NC * 64) {
+        const int c = threadIdx.x >> 6, l = threadIdx.x & 63;
+        float sum = 0.f;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) sum += red[sb & 1][ww][c][l];
+        const int64_t j = Bbase + (int64_t)sb * 64 + l;
+        if (j < n) part[((int64_t)A * 4 + c) * n + j] = sum;
+      }
+    }
+    if (COMP) {
+#pragma unroll
+      for (int u = 0; u < I; ++u)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          float s, e;
+          two_sum(hi[c][u], ai[c][u], s, e);
+          hi[c][u] = s;
+          lo[c][u] += e;
+          ai[c][u] = 0.f;
+        }
+    }
+  }
+  // i-side of the tile: slot B
+#pragma unroll
+  for (int u = 0; u < I; ++u) {
+    const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
+    if (i < n)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) part[((int64_t)B * 4 + c) * n + i] = COMP ? hi[c][u] + lo[c][u] : ai[c][u];
+  }
+}
+
+// Sum of the nb float slots of every particle in double (fixed order), scaled by G;
+// optional potential and closing half-kick.
+// n: particles of the system (partial plane stride); stride: plane stride of acc/vel.
+__global__ void reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* __restrict__ part, double G,
+                           double* __restrict__ acc, double* __restrict__ pot, double* __restrict__ vel, double hh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int nc = pot ? 4 : 3;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t s = 0; s < nb; ++s)
+    for (int c = 0; c < nc; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double ac = G * a[c];
+    acc[c * stride + i] = ac;
+    if (vel) vel[c * stride + i] += hh * ac;
+  }
+  if (pot) pot[i] = G * a[3];
+}
+
 // ----------------------------------------------------------------- batched persistent force pass
 
 // One work unit: an i-tile of one system against one j-chunk of the same system.

@@ -425,3 +425,81 @@ def test_autograd_function(nb, oracle):
     assert abs(loss.item() - lr) <= 1e-12 * lr
     for t, r in zip((x0.grad, v0.grad, m.grad), ref):
         assert _rel_l2(host(t), r) <= 1e-10
+
+
+# ------------------------------------------------------------------ symmetric (action-reaction) force pass
+
+def _force_table(nb, variant, kernel="force", precision="fp32c", j_split=1):
+    nb.set_tile_table([dict(kernel=kernel, precision=p, n_min=0, n_max=1 << 40, variant=variant, j_split=j_split)
+                       for p in (["fp32", "fp32c"] if precision == "fp32*" else [precision])])
+
+
+def _sym_variants(nb):
+    return [k for k, d in enumerate(nb.tile_variants("force", "fp32c")) if "sym=" in d]
+
+
+@pytest.mark.parametrize("n", [1, 2, 100, 1023, 1024, 1025, 2049, 5000])
+def test_symmetric_kernel_vs_oracle(nb, oracle, n):
+    """Every symmetric variant (each pair once, both particles updated, DPP lane rotation),
+    forced through the tile table, on sizes below, at and across its block edge."""
+    s = inputs.uniform_cube(n, 300 + n)
+    acc_ref, pot_ref = oracle.forces(s.pos, s.mass, eps=1e-2)
+    try:
+        for v in _sym_variants(nb):
+            _force_table(nb, v, precision="fp32*")
+            for prec in ("fp32c", "fp32"):
+                for want_pot in (True, False):
+                    acc, pot = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision=prec, want_pot=want_pot)
+                    acc = host(acc)
+                    if n == 1:
+                        assert np.all(acc == 0)
+                        continue
+                    check_fp32(acc, acc_ref, s.pos, s.mass, 1e-2, prec)
+                    if want_pot:
+                        assert np.max(np.abs(host(pot) - pot_ref) / np.abs(pot_ref)) <= TOL_P[prec], (v, prec)
+    finally:
+        nb.set_tile_table([])
+
+
+def test_symmetric_plummer_and_determinism(nb, oracle):
+    s = inputs.plummer(20000, 33)
+    r = np.sqrt((s.pos ** 2).sum(axis=0))
+    idx = np.unique(np.concatenate([np.arange(0, 20000, 97), np.argsort(r)[:32], [19999]]))
+    acc_ref, pot_ref = oracle.forces_sample(s.pos, s.mass, idx, eps=1e-2)
+    try:
+        for v in _sym_variants(nb):
+            _force_table(nb, v)
+            a1, p1 = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision="fp32c", want_pot=True)
+            a2, p2 = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision="fp32c", want_pot=True)
+            assert np.array_equal(host(a1), host(a2)) and np.array_equal(host(p1), host(p2))
+            e = force_err(host(a1)[:, idx], acc_ref)
+            assert e <= 1e-5, (v, e)
+            assert np.max(np.abs(host(p1)[idx] - pot_ref) / np.abs(pot_ref)) <= 1e-6
+    finally:
+        nb.set_tile_table([])
+
+
+def test_symmetric_rollout_backward_invariance(nb, oracle):
+    """Recomputation with the symmetric force pass reproduces the forward trajectory
+    bitwise (gradients independent of the checkpoint interval) and matches the oracle."""
+    s = inputs.plummer(3000, 34)
+    g = np.random.Generator(np.random.PCG64(35))
+    gxK, gvK = g.normal(size=(3, 3000)), g.normal(size=(3, 3000))
+    sym = _sym_variants(nb)[1]
+    try:
+        _force_table(nb, sym)
+        res = []
+        for ck in (1, 4, 9):
+            pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+            acc, _ = nb.forces(pos, mass, precision="fp32c")
+            ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 9, ckpt_every=ck, precision="fp32c")
+            res.append([host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 9, ck,
+                                                             precision="fp32c")])
+        for r in res[1:]:
+            for a, b in zip(r, res[0]):
+                assert np.array_equal(a, b)
+        ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, 1e-3, 9, gxK, gvK, eps=1e-2)
+        for a, b in zip(res[0], ref):
+            assert _rel_l2(a, b) <= 1e-4
+    finally:
+        nb.set_tile_table([])
