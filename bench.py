@@ -2,10 +2,10 @@
 
 One timed step = the Plummer N = 1,048,576 workload (eps = 1e-3): one force pass with
 the fused potential, the energy/momentum reduction at t = 0, 10 kick-drift-kick steps
-of dt = 5e-4 (one force pass each), and the energy/momentum reduction at the end
-(its potential costs one more force pass): 12 all-pairs evaluations, FP32 pair math
-with compensated accumulation, FP64 state and reductions. Inputs are resident on the
-GPU before the timed region.
+of dt = 5e-4 (one force pass each, through nbody_step), and the energy/momentum
+reduction at the end (its potential costs one more force pass): 12 all-pairs
+evaluations, FP32 pair math with compensated accumulation, FP64 state and reductions.
+Inputs are resident on the GPU before the timed region.
 
 Printed: ONE JSON line with the throughput in pair interactions/s, the roofline of the
 dominant kernel (the FP32 force pass, 20 flop per interaction against the 157.3
@@ -96,21 +96,27 @@ def main():
     evals_per_step = 1 + ksteps + 1
     inter_per_step = evals_per_step * float(n) * float(n)
 
-    force_events = []
+    pot_events = []   # force pass with the fused potential (2 per step)
+    step_events = []  # KDK steps: kick/drift/stage + force pass + closing kick (10 per step)
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
 
     def one_step(timed):
         pos.copy_(pos0)
         vel.copy_(vel0)
-        if timed:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
+        e0 = ev() if timed else None
         nb.forces(pos, mass, eps=eps, precision=prec, want_pot=True, out_acc=acc, out_pot=pot)
         if timed:
-            e1.record()
-            force_events.append((e0, e1))
+            pot_events.append((e0, ev()))
         em0 = nb.energy_momentum(pos, vel, mass, pot, eps=eps, precision=prec)
-        nb.rollout(pos, vel, mass, acc, dt, ksteps, eps=eps, precision=prec)
+        for _ in range(ksteps):
+            e0 = ev() if timed else None
+            nb.step(pos, vel, mass, acc, dt, eps=eps, precision=prec)
+            if timed:
+                step_events.append((e0, ev()))
         em1 = nb.energy_momentum(pos, vel, mass, None, eps=eps, precision=prec)
         return em0, em1
 
@@ -128,8 +134,11 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = inter_per_step * args.steps / elapsed
-    force_ms = float(np.mean([a.elapsed_time(b) for a, b in force_events]))
+    force_ms = float(np.mean([a.elapsed_time(b) for a, b in step_events]))
+    pot_ms = float(np.mean([a.elapsed_time(b) for a, b in pot_events]))
     achieved = FLOP_PER_INTERACTION * float(n) * float(n) / (force_ms * 1e-3)
+    vid, _ = nb.tile_lookup("force", prec, n)
+    kdesc = nb.tile_variants("force", prec)[vid]
     em0 = em0.cpu().numpy()[0]
     em1 = em1.cpu().numpy()[0]
     E0, E1 = em0[0] + em0[1], em1[0] + em1[1]
@@ -158,13 +167,16 @@ def main():
         "pct_fp32_peak": 100.0 * FLOP_PER_INTERACTION * value / PEAK_FP32,
         "roofline": {
             "bound": "alu",
-            "kernel": "force_kernel<float,compensated,potential>",
+            "kernel": "%s force pass (%s, %s), no potential; timed per KDK step (kick/drift/stage + force + "
+                      "closing kick, > 99%% force)" % ("symmetric" if "sym=" in kdesc else "one-sided", kdesc, prec),
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
             "traffic": stored_traffic(n),
             "avg_launch_ms": force_ms,
+            "avg_launch_ms_with_potential": pot_ms,
+            "frac_with_potential": FLOP_PER_INTERACTION * float(n) * float(n) / (pot_ms * 1e-3) / PEAK_FP32,
             "flop_per_interaction": FLOP_PER_INTERACTION,
             "interactions_per_launch": float(n) * float(n),
         },

@@ -1,0 +1,197 @@
+"""Tile autotuner for libnbody.so.
+
+For every (kernel, precision, particle-count bucket) it times each compiled tile
+variant (and, for the split kernels, a few j-split / j-chunk settings) through
+the C ABI on the current GPU, keeps the fastest, and writes the winners as a
+tile table (JSON) that the library loads at start-up (tune/<arch>.json, or the
+file named by NBODY_TILE_TABLE).
+
+Timing: HIP events on the current stream around `reps` back-to-back calls after
+one warm-up call; the median of `trials` such measurements is the score.
+
+Usage (on the GPU): python -m paper_2511_02655_amd.autotune [--out PATH] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+FORCE_BUCKETS = [1024, 4096, 16384, 65536, 262144, 1048576]
+ADJ_BUCKETS = [1024, 4096, 16384, 65536]
+J_SPLITS = [1, 2, 4, 8, 16, 32]
+BATCH_JCHUNK = [512, 1024, 2048, 4096]
+
+
+def _bounds(buckets, k):
+    lo = 0 if k == 0 else int(math.sqrt(buckets[k - 1] * buckets[k])) + 1
+    hi = (1 << 40) if k == len(buckets) - 1 else int(math.sqrt(buckets[k] * buckets[k + 1]))
+    return lo, hi
+
+
+def _time(fn, reps, trials=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(trials):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / reps)
+    return float(np.median(out))
+
+
+def _reps_for(n):
+    work = float(n) * n
+    return int(min(50, max(2, 2e11 / max(work, 1.0))))
+
+
+def tune_force(nb, torch, precision, buckets, log):
+    from . import inputs
+    entries = []
+    nvar = len(nb.tile_variants("force", precision))
+    for k, n in enumerate(buckets):
+        s = inputs.plummer(n, 100 + k)
+        pos = torch.from_numpy(s.pos).cuda()
+        mass = torch.from_numpy(s.mass).cuda()
+        acc = torch.empty((3, n), dtype=torch.float64, device="cuda")
+        reps = _reps_for(n)
+        best = None
+        descs = nb.tile_variants("force", precision)
+        for v in range(nvar):
+            sym = "sym=" in descs[v]
+            if sym and n < 4096:
+                continue
+            for js in ([1] if sym else J_SPLITS):
+                if js > 1 and n >= 262144:
+                    continue
+                nb.set_tile_table([dict(kernel="force", precision=precision, n_min=0, n_max=1 << 40, variant=v,
+                                        j_split=js)])
+                t = _time(lambda: nb.forces(pos, mass, eps=1e-2, precision=precision, out_acc=acc), reps)
+                rate = float(n) * n / (t * 1e-3)
+                log("force %s n=%d variant %d (%s) j_split %d: %.3f ms  %.3e inter/s" % (precision, n, v, descs[v], js,
+                                                                                      t, rate))
+                # prefer bigger symmetric blocks (half the partial-sum workspace) within 1%
+                key = t * (0.99 if (sym and best is not None and "sym=" in descs[best[1]] and
+                                    int(descs[v].split("sym=")[1]) > int(descs[best[1]].split("sym=")[1])) else 1.0)
+                if best is None or key < best[0]:
+                    best = (t, v, js, rate)
+        lo, hi = _bounds(buckets, k)
+        entries.append(dict(kernel="force", precision=precision, n_min=lo, n_max=hi, variant=best[1],
+                            j_split=best[2], tuned_n=n, ms=best[0], interactions_per_s=best[3]))
+        nb.set_tile_table([])
+    return entries
+
+
+def tune_adjoint(nb, torch, precision, buckets, log):
+    """Times one adjoint pass (backward of a 1-step rollout, dominated by two adjoint
+    passes and one recomputed force pass) per variant."""
+    from . import inputs
+    entries = []
+    descs = nb.tile_variants("adjoint", precision)
+    for k, n in enumerate(buckets):
+        s = inputs.plummer(n, 200 + k)
+        pos = torch.from_numpy(s.pos).cuda()
+        vel = torch.from_numpy(s.vel).cuda()
+        mass = torch.from_numpy(s.mass).cuda()
+        acc, _ = nb.forces(pos, mass, precision=precision)
+        ckpt, _ = nb.rollout(pos.clone(), vel.clone(), mass, acc.clone(), 1e-3, 1, ckpt_every=1, precision=precision)
+        g = torch.ones((3, n), dtype=torch.float64, device="cuda")
+        reps = max(1, _reps_for(n) // 2)
+        best = None
+        for v in range(len(descs)):
+            for js in J_SPLITS:
+                nb.set_tile_table([dict(kernel="adjoint", precision=precision, n_min=0, n_max=1 << 40, variant=v,
+                                        j_split=js)])
+                t = _time(lambda: nb.rollout_backward(mass, ckpt, g, g, 1e-3, 1, 1, precision=precision), reps)
+                log("adjoint %s n=%d variant %d (%s) j_split %d: %.3f ms" % (precision, n, v, descs[v], js, t))
+                if best is None or t < best[0]:
+                    best = (t, v, js)
+        lo, hi = _bounds(buckets, k)
+        entries.append(dict(kernel="adjoint", precision=precision, n_min=lo, n_max=hi, variant=best[1],
+                            j_split=best[2], tuned_n=n, ms=best[0]))
+        nb.set_tile_table([])
+    return entries
+
+
+def tune_batched(nb, torch, precision, log, n_systems=512):
+    """Batched persistent force and adjoint passes on the 512-system mix."""
+    from . import inputs
+    b = inputs.batched_mix(n_systems, 6)
+    off = b.offsets
+    pos = torch.from_numpy(b.pos).cuda()
+    vel = torch.from_numpy(b.vel).cuda()
+    mass = torch.from_numpy(b.mass).cuda()
+    acc = torch.empty_like(pos)
+    nmax = int(np.max(np.diff(off)))
+    entries = []
+    for kernel in ("force_batched", "adjoint_batched"):
+        descs = nb.tile_variants(kernel, precision)
+        best = None
+        if kernel == "adjoint_batched":
+            a0, _ = nb.forces(pos, mass, precision=precision, offsets=off)
+            ckpt, _ = nb.rollout(pos.clone(), vel.clone(), mass, a0, 1e-3, 1, ckpt_every=1, precision=precision,
+                                 offsets=off)
+            g = torch.ones_like(pos)
+        for v in range(len(descs)):
+            for jc in BATCH_JCHUNK:
+                nb.set_tile_table([dict(kernel=kernel, precision=precision, n_min=0, n_max=1 << 40, variant=v,
+                                        j_split=jc)])
+                if kernel == "force_batched":
+                    fn = lambda: nb.forces(pos, mass, precision=precision, offsets=off, out_acc=acc)
+                else:
+                    fn = lambda: nb.rollout_backward(mass, ckpt, g, g, 1e-3, 1, 1, precision=precision, offsets=off)
+                t = _time(fn, 5)
+                log("%s %s variant %d (%s) j_chunk %d: %.3f ms" % (kernel, precision, v, descs[v], jc, t))
+                if best is None or t < best[0]:
+                    best = (t, v, jc)
+        entries.append(dict(kernel=kernel, precision=precision, n_min=0, n_max=1 << 40, variant=best[1],
+                            j_split=best[2], tuned_n=nmax, ms=best[0]))
+        nb.set_tile_table([])
+    return entries
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--quick", action="store_true", help="FP32-compensated force buckets only")
+    args = ap.parse_args()
+    import torch
+    import paper_2511_02655_amd as nb
+    nb.lib()
+    nb.set_tile_table([])
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.time()
+    entries = []
+    precs = ["fp32c"] if args.quick else ["fp32c", "fp32", "fp64"]
+    for p in precs:
+        entries += tune_force(nb, torch, p, FORCE_BUCKETS, log)
+    if not args.quick:
+        for p in ("fp32c", "fp32", "fp64"):
+            entries += tune_adjoint(nb, torch, p, ADJ_BUCKETS, log)
+        for p in ("fp32c", "fp32", "fp64"):
+            entries += tune_batched(nb, torch, p, log)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    table = {"arch": arch, "tuned_in_s": time.time() - t0, "entries": entries}
+    out = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune", arch + ".json")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    log("wrote %s (%d entries, %.0f s)" % (out, len(entries), time.time() - t0))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
