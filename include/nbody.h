@@ -62,10 +62,11 @@ typedef enum {
  * every reduction are FP64 in all modes.
  *   NBODY_FP64       pair math in double.
  *   NBODY_FP32       pair math in float; per-particle float accumulators.
- *   NBODY_FP32_COMP  pair math in float; per-particle accumulation compensated:
- *                    a float (hi, lo) pair per component, the partial sum of
- *                    each staged j-tile folded into it with an error-free
- *                    TwoSum; the result is (double)hi + (double)lo. */
+ *   NBODY_FP32_COMP  pair math in float; per-particle accumulation blocked and
+ *                    compensated: no float sum spans more than one tile of
+ *                    j-particles, and the tile sums are combined without
+ *                    rounding loss - folded with an error-free TwoSum into a
+ *                    float (hi, lo) pair, or added in double. */
 typedef enum { NBODY_FP64 = 0, NBODY_FP32 = 1, NBODY_FP32_COMP = 2 } nbody_precision;
 
 /* config.flags */
@@ -111,9 +112,11 @@ int nbody_forces(const nbody_config *cfg, int64_t n, const double *pos, const do
 /* One kick-drift-kick step of size dt with force reuse (the Verlet
  * half-step update of Sec. II-A):
  *   v += dt/2 a;  x += dt v;  a = a(x);  v += dt/2 a
- *   pos, vel [3][n] in/out; acc [3][n] in: a(x_n), out: a(x_{n+1}). */
+ *   pos, vel [3][n] in/out; acc [3][n] in: a(x_n), out: a(x_{n+1});
+ *   pot [n] nullable, out: the potential at x_{n+1} from the same force pass
+ *   (for an energy reduction after the step without another pass). */
 int nbody_step(const nbody_config *cfg, int64_t n, double dt, double *pos, double *vel,
-               const double *mass, double *acc);
+               const double *mass, double *acc, double *pot);
 
 /* `steps` KDK steps (steps >= 0), state in place.
  *   acc   in: a(x_0) (e.g. from nbody_forces), out: a(x_steps)

@@ -85,7 +85,7 @@ def lib():
         "nbody_last_error": ([], ctypes.c_char_p),
         "nbody_workspace_size": ([C, I64, I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "nbody_forces": ([C, I64, P, P, P, P], ctypes.c_int),
-        "nbody_step": ([C, I64, D, P, P, P, P], ctypes.c_int),
+        "nbody_step": ([C, I64, D, P, P, P, P, P], ctypes.c_int),
         "nbody_rollout": ([C, I64, D, I64, I64, P, P, P, P, P, P], ctypes.c_int),
         "nbody_energy_momentum": ([C, I64, P, P, P, P, P], ctypes.c_int),
         "nbody_rollout_backward": ([C, I64, D, I64, I64, P, P, P, P, P, P, P], ctypes.c_int),
@@ -257,13 +257,15 @@ def forces(pos, mass, *, G=1.0, eps=1e-2, precision="fp32c", want_pot=False, off
     return acc, pot
 
 
-def step(pos, vel, mass, acc, dt, *, G=1.0, eps=1e-2, precision="fp32c", offsets=None, flags=0, stream=None):
-    """One KDK step in place (acc: in a(x_n), out a(x_{n+1}))."""
+def step(pos, vel, mass, acc, dt, *, G=1.0, eps=1e-2, precision="fp32c", offsets=None, flags=0, out_pot=None,
+         stream=None):
+    """One KDK step in place (acc: in a(x_n), out a(x_{n+1})); out_pot (n,), when given,
+    receives the potential at x_{n+1} from the same force pass."""
     n = _n_of(mass)
     c = _Cfg(precision, G, eps, offsets, flags, stream)
     c.workspace(n, device=mass.device)
     _check(lib().nbody_step(ctypes.byref(c.cfg), n, float(dt), _dptr(pos, "pos", (3, n)), _dptr(vel, "vel", (3, n)),
-                            _dptr(mass, "mass"), _dptr(acc, "acc", (3, n))))
+                            _dptr(mass, "mass"), _dptr(acc, "acc", (3, n)), _dptr(out_pot, "pot", (n,))))
 
 
 def rollout(pos, vel, mass, acc, dt, steps, *, ckpt_every=0, energy_trace=False, G=1.0, eps=1e-2,

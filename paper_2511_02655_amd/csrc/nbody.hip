@@ -850,7 +850,7 @@ __attribute__((visibility("default"))) int nbody_forces(const nbody_config* cfg,
 }
 
 __attribute__((visibility("default"))) int nbody_step(const nbody_config* cfg, int64_t n, double dt, double* pos,
-                                                      double* vel, const double* mass, double* acc) {
+                                                      double* vel, const double* mass, double* acc, double* pot) {
   g_err.clear();
   Ctx c;
   TRY(prepare(c, cfg, n, 1, NEED_FORCE));
@@ -859,7 +859,7 @@ __attribute__((visibility("default"))) int nbody_step(const nbody_config* cfg, i
   if (!pos || !vel || !mass || !acc) return fail(NBODY_ERR_INVALID_ARG, "pos, vel, mass and acc must be non-NULL");
   TRY(upload_meta(c));
   TRY(kick_drift(c, dt, pos, vel, acc, mass));
-  return force_pass(c, acc, nullptr, vel, 0.5 * dt);
+  return force_pass(c, acc, pot, vel, 0.5 * dt);
 }
 
 __attribute__((visibility("default"))) int nbody_rollout(const nbody_config* cfg, int64_t n, double dt, int64_t steps,

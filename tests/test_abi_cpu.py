@@ -134,7 +134,7 @@ def test_other_entry_point_errors(nb):
     assert L.nbody_forces(ctypes.byref(c), -1, FAKE, FAKE, FAKE, None) == 1
     assert L.nbody_forces(None, 10, FAKE, FAKE, FAKE, None) == 1
     assert L.nbody_forces(ctypes.byref(c), 10, None, FAKE, FAKE, None) == 1
-    assert L.nbody_step(ctypes.byref(c), 10, float("nan"), FAKE, FAKE, FAKE, FAKE) == 1
+    assert L.nbody_step(ctypes.byref(c), 10, float("nan"), FAKE, FAKE, FAKE, FAKE, None) == 1
     assert L.nbody_rollout(ctypes.byref(c), 10, 1e-3, -1, 0, FAKE, FAKE, FAKE, FAKE, None, None) == 1
     assert L.nbody_rollout(ctypes.byref(c), 10, 1e-3, 5, 0, FAKE, FAKE, FAKE, FAKE, FAKE, None) == 1
     assert L.nbody_rollout_backward(ctypes.byref(c), 10, 1e-3, 5, 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE) == 1
@@ -143,7 +143,7 @@ def test_other_entry_point_errors(nb):
     assert "out" in L.nbody_last_error().decode()
     # n == 0 is a valid no-op that touches nothing
     assert L.nbody_forces(ctypes.byref(_cfg(nb)), 0, None, None, None, None) == 0
-    assert L.nbody_step(ctypes.byref(_cfg(nb)), 0, 1e-3, None, None, None, None) == 0
+    assert L.nbody_step(ctypes.byref(_cfg(nb)), 0, 1e-3, None, None, None, None, None) == 0
 
 
 def test_tile_table_validation(nb):

@@ -503,3 +503,17 @@ def test_symmetric_rollout_backward_invariance(nb, oracle):
             assert _rel_l2(a, b) <= 1e-4
     finally:
         nb.set_tile_table([])
+
+
+def test_step_potential_output(nb):
+    """The potential a KDK step emits is bitwise the one a force pass at the new positions gives."""
+    import torch
+    for n in (3000, 40000):
+        s = inputs.plummer(n, 36)
+        pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+        acc, _ = nb.forces(pos, mass, precision="fp32c")
+        pot = torch.empty(n, dtype=torch.float64, device="cuda")
+        nb.step(pos, vel, mass, acc, 1e-3, precision="fp32c", out_pot=pot)
+        a2, p2 = nb.forces(pos, mass, precision="fp32c", want_pot=True)
+        assert np.array_equal(host(pot), host(p2))
+        assert np.array_equal(host(acc), host(a2))
