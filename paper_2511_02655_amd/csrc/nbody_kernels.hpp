@@ -432,18 +432,15 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
           const float dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
           const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
           const float ri = __builtin_amdgcn_rsqf(r2);
-          const float ri2 = ri * ri;
-          float si, sj;
+          // the acceleration terms round identically with and without the potential,
+          // so both variants give bitwise-equal accelerations (trajectories must not
+          // depend on whether an energy trace is taken)
+          const float r3 = ri * (ri * ri);
+          const float si = mj * r3;
+          const float sj = mi[u] * r3;
           if (POT) {
-            const float mri = mj * ri, mrj = mi[u] * ri;
-            si = mri * ri2;
-            sj = mrj * ri2;
-            ai[3][u] -= mri;
-            aj[3] -= mrj;
-          } else {
-            const float r3 = ri * ri2;
-            si = mj * r3;
-            sj = mi[u] * r3;
+            ai[3][u] -= mj * ri;
+            aj[3] -= mi[u] * ri;
           }
           ai[0][u] = __builtin_fmaf(si, dx, ai[0][u]);
           ai[1][u] = __builtin_fmaf(si, dy, ai[1][u]);

@@ -250,14 +250,16 @@ def test_step_equals_rollout(nb):
     assert np.array_equal(host(p1), host(p2)) and np.array_equal(host(v1), host(v2))
 
 
-def test_rollout_energy_trace_does_not_change_state(nb):
-    """The potential-carrying force pass leaves the trajectory bitwise unchanged."""
-    s = inputs.plummer(1500, 13)
+@pytest.mark.parametrize("n", [1500, 40000])
+def test_rollout_energy_trace_does_not_change_state(nb, n):
+    """The potential-carrying force pass leaves the trajectory bitwise unchanged
+    (n = 40000 runs the symmetric pass, n = 1500 the one-sided one)."""
+    s = inputs.plummer(n, 13)
     outs = []
     for et in (False, True):
         p, v, m = dev(s.pos), dev(s.vel), dev(s.mass)
         a, _ = nb.forces(p, m, precision="fp32c")
-        nb.rollout(p, v, m, a, 1e-3, 6, energy_trace=et, precision="fp32c")
+        nb.rollout(p, v, m, a, 1e-3, 3, energy_trace=et, precision="fp32c")
         outs.append((host(p), host(v)))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
