@@ -59,7 +59,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp32ds", "fp64"])
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -196,28 +196,49 @@ def main():
 
 
 def force_errors(nb, torch, np, pos0, mass, s, eps, prec):
-    """Force error of this run's precision: every particle against the FP64 GPU path,
-    and a sample against the FP64 CPU oracle."""
+    """Force error of this run's precision and of every other pair-math mode: each mode's
+    force pass (with potential) timed once and compared on every particle with the FP64 GPU
+    path; this run's mode also against the FP64 CPU oracle on a sample."""
     import oracle
     log("error leg")
-    a32, p32 = nb.forces(pos0, mass, eps=eps, precision=prec, want_pot=True)
     a64, p64 = nb.forces(pos0, mass, eps=eps, precision="fp64", want_pot=True)
-    d = torch.sqrt(((a32 - a64) ** 2).sum(0))
     m = torch.sqrt((a64 ** 2).sum(0))
     rms = torch.sqrt((m ** 2).mean())
-    e = d / torch.clamp(m, min=1e-6 * rms.item())
+    n2 = float(s.n) ** 2
+    modes = {}
+    for mode in ("fp32", "fp32c", "fp32ds", "fp64"):
+        a32, p32 = nb.forces(pos0, mass, eps=eps, precision=mode, want_pot=True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nb.forces(pos0, mass, eps=eps, precision=mode, want_pot=False, out_acc=a32)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        d = torch.sqrt(((a32 - a64) ** 2).sum(0))
+        e = d / torch.clamp(m, min=1e-6 * rms.item())
+        modes[mode] = {"force_ms": ms, "interactions_per_s": n2 / (ms * 1e-3),
+                       "pct_fp32_peak": 100.0 * FLOP_PER_INTERACTION * n2 / (ms * 1e-3) / PEAK_FP32,
+                       "max_e": float(e.max()), "p999_e": float(torch.quantile(e[::16].float(), 0.999)),
+                       "max_abs_over_rms": float((d / rms).max()),
+                       "phi_max_rel": float((torch.abs(p32 - p64) / torch.abs(p64)).max())}
+        if mode == prec:
+            mine = a32.clone()
     g = np.random.Generator(np.random.PCG64(7))
     idx = np.sort(g.choice(s.n, 32, replace=False))
     ar, _ = oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
-    a = a32.cpu().numpy()[:, idx]
-    dd = np.sqrt(((a - ar) ** 2).sum(0))
-    mm = np.sqrt((ar ** 2).sum(0))
+    out = {}
+    for name, a_gpu in (("this_run_" + prec, mine), ("fp64", a64)):
+        a = a_gpu.cpu().numpy()[:, idx]
+        dd = np.sqrt(((a - ar) ** 2).sum(0))
+        mm = np.sqrt((ar ** 2).sum(0))
+        out[name] = float(np.max(dd / np.maximum(mm, 1e-6 * math.sqrt(np.mean(mm ** 2)))))
     return {
-        "vs_fp64_gpu_all": {"max_e": float(e.max()), "p999_e": float(torch.quantile(e[::16].float(), 0.999)),
-                            "max_abs_over_rms": float((d / rms).max())},
-        "vs_oracle_sample32": {"max_e": float(np.max(dd / np.maximum(mm, 1e-6 * math.sqrt(np.mean(mm ** 2)))))},
-        "phi_vs_fp64_gpu_max_rel": float((torch.abs(p32 - p64) / torch.abs(p64)).max()),
-        "metric": "e_i = |a_i - a_i^ref| / max(|a_i^ref|, 1e-6 rms|a^ref|)",
+        "vs_fp64_gpu_all": modes[prec] if prec in modes else None,
+        "modes_vs_fp64_gpu_all": modes,
+        "vs_oracle_sample32_max_e": out,
+        "metric": "e_i = |a_i - a_i^ref| / max(|a_i^ref|, 1e-6 rms|a^ref|), all N particles unless noted",
     }
 
 

@@ -66,8 +66,13 @@ typedef enum {
  *                    compensated: no float sum spans more than one tile of
  *                    j-particles, and the tile sums are combined without
  *                    rounding loss - folded with an error-free TwoSum into a
- *                    float (hi, lo) pair, or added in double. */
-typedef enum { NBODY_FP64 = 0, NBODY_FP32 = 1, NBODY_FP32_COMP = 2 } nbody_precision;
+ *                    float (hi, lo) pair, or added in double.
+ *   NBODY_FP32_DS    as NBODY_FP32_COMP, and every separation is formed from
+ *                    double-float coordinates (x = hi + lo, two floats), so it is
+ *                    exact to the float rounding of the separation itself instead
+ *                    of the coordinates; costs about 6 more float operations per
+ *                    pair (adjoint passes run as NBODY_FP32_COMP). */
+typedef enum { NBODY_FP64 = 0, NBODY_FP32 = 1, NBODY_FP32_COMP = 2, NBODY_FP32_DS = 3 } nbody_precision;
 
 /* config.flags */
 #define NBODY_FLAG_LOOP_SYSTEMS 1u /* batched calls: one plain launch per system

@@ -10,7 +10,8 @@ Arrays: positions/velocities/accelerations are float64 tensors of shape (3, n)
 on the GPU (SoA planes), masses float64 of shape (n,).
 
 Precision names: "fp64", "fp32", "fp32c" (FP32 pair math with compensated
-accumulation). State, updates and reductions are FP64 in every mode.
+accumulation), "fp32ds" (compensated, with double-float separations). State,
+updates and reductions are FP64 in every mode.
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libnbody.so")
 
 NBODY_ABI_VERSION = 1
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32ds": 3}
 KERNELS = {"force": 0, "adjoint": 1, "force_batched": 2, "adjoint_batched": 3}
 FLAG_LOOP_SYSTEMS = 1
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPACE"}

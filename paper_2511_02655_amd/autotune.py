@@ -176,7 +176,7 @@ def main():
 
     t0 = time.time()
     entries = []
-    precs = ["fp32c"] if args.quick else ["fp32c", "fp32", "fp64"]
+    precs = ["fp32c"] if args.quick else ["fp32c", "fp32", "fp32ds", "fp64"]
     for p in precs:
         entries += tune_force(nb, torch, p, FORCE_BUCKETS, log)
     if not args.quick:

@@ -66,16 +66,16 @@ using AdjFn = void (*)(dim3, hipStream_t, const void* jadj, int64_t i0, int64_t 
 using AdjBatchedFn = void (*)(dim3, hipStream_t, const void* jadj, const WorkUnit* units, int32_t n_units,
                               int32_t* counter, double eps2, const AdjOut&);
 
-template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE>
 void launch_force(dim3 g, hipStream_t st, const void* jarr, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
                   int64_t jchunk, double eps2, const ForceOut& o) {
-  hipLaunchKernelGGL((force_kernel<T, BS, I, TJ, POT, COMP>), g, dim3(BS), 0, st,
+  hipLaunchKernelGGL((force_kernel<T, BS, I, TJ, POT, MODE>), g, dim3(BS), 0, st,
                      (const typename Vec4<T>::type*)jarr, i0, i1, j0, j1, jchunk, (T)eps2, o);
 }
-template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE>
 void launch_force_batched(dim3 g, hipStream_t st, const void* jarr, const WorkUnit* units, int32_t n_units,
                           int32_t* counter, double eps2, const ForceOut& o) {
-  hipLaunchKernelGGL((force_batched_kernel<T, BS, I, TJ, POT, COMP>), g, dim3(BS), 0, st,
+  hipLaunchKernelGGL((force_batched_kernel<T, BS, I, TJ, POT, MODE>), g, dim3(BS), 0, st,
                      (const typename Vec4<T>::type*)jarr, units, n_units, counter, (T)eps2, o);
 }
 template <typename T, int BS, int I, int TJ, bool COMP>
@@ -92,16 +92,16 @@ void launch_adj_batched(dim3 g, hipStream_t st, const void* jadj, const WorkUnit
 }
 
 // Kernel pointers for occupancy queries of the persistent kernels.
-template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
-const void* force_batched_ptr() { return (const void*)&force_batched_kernel<T, BS, I, TJ, POT, COMP>; }
+template <typename T, int BS, int I, int TJ, bool POT, int MODE>
+const void* force_batched_ptr() { return (const void*)&force_batched_kernel<T, BS, I, TJ, POT, MODE>; }
 template <typename T, int BS, int I, int TJ, bool COMP>
 const void* adj_batched_ptr() { return (const void*)&adjoint_batched_kernel<T, BS, I, TJ, COMP>; }
 
 struct ForceVariant {
   int bs, i, tj;
-  ForceFn fn[2][2];               // [pot][comp]
-  ForceBatchedFn bfn[2][2];
-  const void* (*bptr[2][2])();
+  ForceFn fn[2][3];               // [pot][mode]: plain, compensated, double-float separations
+  ForceBatchedFn bfn[2][3];
+  const void* (*bptr[2][3])();
 };
 struct AdjVariant {
   int bs, i, tj;
@@ -110,25 +110,24 @@ struct AdjVariant {
   const void* (*bptr[2])();
 };
 
+#define FV32_MODES(F, BS, I, TJ, POT) \
+  { F<float, BS, I, TJ, POT, 0>, F<float, BS, I, TJ, POT, 1>, F<float, BS, I, TJ, POT, 2> }
 #define FV32(BS, I, TJ)                                                                                    \
   ForceVariant {                                                                                           \
     BS, I, TJ,                                                                                             \
-        {{launch_force<float, BS, I, TJ, false, false>, launch_force<float, BS, I, TJ, false, true>},     \
-         {launch_force<float, BS, I, TJ, true, false>, launch_force<float, BS, I, TJ, true, true>}},      \
-        {{launch_force_batched<float, BS, I, TJ, false, false>, launch_force_batched<float, BS, I, TJ, false, true>}, \
-         {launch_force_batched<float, BS, I, TJ, true, false>, launch_force_batched<float, BS, I, TJ, true, true>}},  \
-        {{force_batched_ptr<float, BS, I, TJ, false, false>, force_batched_ptr<float, BS, I, TJ, false, true>},       \
-         {force_batched_ptr<float, BS, I, TJ, true, false>, force_batched_ptr<float, BS, I, TJ, true, true>}}         \
+        {FV32_MODES(launch_force, BS, I, TJ, false), FV32_MODES(launch_force, BS, I, TJ, true)},           \
+        {FV32_MODES(launch_force_batched, BS, I, TJ, false), FV32_MODES(launch_force_batched, BS, I, TJ, true)}, \
+        {FV32_MODES(force_batched_ptr, BS, I, TJ, false), FV32_MODES(force_batched_ptr, BS, I, TJ, true)} \
   }
 #define FV64(BS, I, TJ)                                                                                    \
   ForceVariant {                                                                                           \
     BS, I, TJ,                                                                                             \
-        {{launch_force<double, BS, I, TJ, false, false>, nullptr},                                         \
-         {launch_force<double, BS, I, TJ, true, false>, nullptr}},                                         \
-        {{launch_force_batched<double, BS, I, TJ, false, false>, nullptr},                                 \
-         {launch_force_batched<double, BS, I, TJ, true, false>, nullptr}},                                 \
-        {{force_batched_ptr<double, BS, I, TJ, false, false>, nullptr},                                    \
-         {force_batched_ptr<double, BS, I, TJ, true, false>, nullptr}}                                     \
+        {{launch_force<double, BS, I, TJ, false, 0>, nullptr, nullptr},                                   \
+         {launch_force<double, BS, I, TJ, true, 0>, nullptr, nullptr}},                                   \
+        {{launch_force_batched<double, BS, I, TJ, false, 0>, nullptr, nullptr},                           \
+         {launch_force_batched<double, BS, I, TJ, true, 0>, nullptr, nullptr}},                           \
+        {{force_batched_ptr<double, BS, I, TJ, false, 0>, nullptr, nullptr},                              \
+         {force_batched_ptr<double, BS, I, TJ, true, 0>, nullptr, nullptr}}                               \
   }
 #define AV32(BS, I, TJ)                                                                                    \
   AdjVariant {                                                                                             \
@@ -152,18 +151,18 @@ const AdjVariant kAdj64[] = {AV64(256, 1, 256), AV64(128, 1, 128), AV64(64, 1, 6
 // Symmetric FP32 force variants (each pair once), indices kNumForce32 + k in the
 // FORCE tile table.
 using SymFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part);
-template <int W, int I, bool POT, bool COMP>
+template <int W, int I, bool POT, int MODE>
 void launch_sym(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part) {
-  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, COMP>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
+  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
 }
 struct SymVariant {
   int w, i;
-  SymFn fn[2][2];  // [pot][comp]
+  SymFn fn[2][3];  // [pot][mode]
 };
 #define SV32(W, I)                                                                            \
   SymVariant {                                                                                \
-    W, I, {{launch_sym<W, I, false, false>, launch_sym<W, I, false, true>},                   \
-           {launch_sym<W, I, true, false>, launch_sym<W, I, true, true>}}                     \
+    W, I, {{launch_sym<W, I, false, 0>, launch_sym<W, I, false, 1>, launch_sym<W, I, false, 2>}, \
+           {launch_sym<W, I, true, 0>, launch_sym<W, I, true, 1>, launch_sym<W, I, true, 2>}}    \
   }
 const SymVariant kSym32[] = {SV32(8, 4), SV32(4, 4), SV32(8, 2), SV32(4, 2)};
 constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
@@ -174,6 +173,14 @@ constexpr int kNumAdj32 = sizeof(kAdj32) / sizeof(kAdj32[0]);
 constexpr int kNumAdj64 = sizeof(kAdj64) / sizeof(kAdj64[0]);
 
 bool is_fp64(int prec) { return prec == NBODY_FP64; }
+bool is_ds(int prec) { return prec == NBODY_FP32_DS; }
+// force-kernel mode index: 0 plain float / double, 1 compensated, 2 double-float separations
+int force_mode(int prec) { return prec == NBODY_FP32_COMP ? 1 : prec == NBODY_FP32_DS ? 2 : 0; }
+// adjoint kernels: compensated for both compensated modes
+int adj_comp(int prec) { return prec == NBODY_FP32_COMP || prec == NBODY_FP32_DS; }
+// bytes of one particle in the force j-array and in the adjoint j-array
+size_t jvec_bytes(int prec) { return is_fp64(prec) ? 32 : is_ds(prec) ? 32 : 16; }
+size_t jadj_bytes(int prec) { return is_fp64(prec) ? 64 : 32; }
 
 int num_variants(int kernel, int prec) {
   bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
@@ -301,7 +308,8 @@ int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys) {
   if (cfg->abi_version != NBODY_ABI_VERSION)
     return fail(NBODY_ERR_INVALID_ARG, "abi_version %d does not match library ABI %d", cfg->abi_version,
                 NBODY_ABI_VERSION);
-  if (cfg->precision != NBODY_FP64 && cfg->precision != NBODY_FP32 && cfg->precision != NBODY_FP32_COMP)
+  if (cfg->precision != NBODY_FP64 && cfg->precision != NBODY_FP32 && cfg->precision != NBODY_FP32_COMP &&
+      cfg->precision != NBODY_FP32_DS)
     return fail(NBODY_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
   if (!std::isfinite(cfg->G)) return fail(NBODY_ERR_INVALID_ARG, "G must be finite");
   if (!(cfg->eps > 0.0) || !std::isfinite(cfg->eps))
@@ -458,8 +466,7 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     force_part = single_force_part(lookup_tile(NBODY_KERNEL_FORCE, prec, n), n);
     if (need & NEED_BACKWARD) adj_part = single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, n), n);
   }
-  const size_t vec = is_fp64(prec) ? 32 : 16;
-  p.sz_jbuf = (size_t)n * vec * ((need & NEED_BACKWARD) ? 2 : 1);
+  p.sz_jbuf = (size_t)n * std::max(jvec_bytes(prec), (need & NEED_BACKWARD) ? jadj_bytes(prec) : (size_t)0);
   p.off_jbuf = take(p.sz_jbuf);
   p.sz_part = std::max(force_part, adj_part);
   p.off_part = take(p.sz_part);
@@ -568,9 +575,8 @@ int check_part(const Ctx& c, size_t bytes, const char* what) {
   return NBODY_OK;
 }
 
-int check_jbuf(const Ctx& c, int vectors_per_particle, const char* what) {
-  const size_t vec = is_fp64(c.cfg->precision) ? 32 : 16;
-  if (c.plan.sz_jbuf < (size_t)c.n * vec * vectors_per_particle)
+int check_jbuf(const Ctx& c, size_t bytes_per_particle, const char* what) {
+  if (c.plan.sz_jbuf < (size_t)c.n * bytes_per_particle)
     return fail(NBODY_ERR_DEVICE, "internal: %s j-array larger than the planned region", what);
   return NBODY_OK;
 }
@@ -580,25 +586,30 @@ inline dim3 grid1d(int64_t n, int bs = 256) { return dim3((unsigned)cdiv(std::ma
 // ------------------------------------------------------------------ passes
 
 int stage(Ctx& c, const double* pos, const double* mass) {
-  TRY(check_jbuf(c, 1, "stage_j"));
+  TRY(check_jbuf(c, jvec_bytes(c.cfg->precision), "stage_j"));
   void* j = c.ws + c.plan.off_jbuf;
   if (is_fp64(c.cfg->precision))
-    hipLaunchKernelGGL(stage_j<double>, grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (D4*)j);
+    hipLaunchKernelGGL((stage_j<double, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (D4*)j);
+  else if (is_ds(c.cfg->precision))
+    hipLaunchKernelGGL((stage_j<float, true>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (float4*)j);
   else
-    hipLaunchKernelGGL(stage_j<float>, grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (float4*)j);
+    hipLaunchKernelGGL((stage_j<float, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (float4*)j);
   LAUNCH_CHECK("stage_j");
   return NBODY_OK;
 }
 
 int kick_drift(Ctx& c, double dt, double* pos, double* vel, const double* acc, const double* mass) {
-  TRY(check_jbuf(c, 1, "kick_drift_stage"));
+  TRY(check_jbuf(c, jvec_bytes(c.cfg->precision), "kick_drift_stage"));
   void* j = c.ws + c.plan.off_jbuf;
   if (is_fp64(c.cfg->precision))
-    hipLaunchKernelGGL(kick_drift_stage<double>, grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel, acc,
-                       mass, (D4*)j);
+    hipLaunchKernelGGL((kick_drift_stage<double, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel,
+                       acc, mass, (D4*)j);
+  else if (is_ds(c.cfg->precision))
+    hipLaunchKernelGGL((kick_drift_stage<float, true>), grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel,
+                       acc, mass, (float4*)j);
   else
-    hipLaunchKernelGGL(kick_drift_stage<float>, grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel, acc,
-                       mass, (float4*)j);
+    hipLaunchKernelGGL((kick_drift_stage<float, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel,
+                       acc, mass, (float4*)j);
   LAUNCH_CHECK("kick_drift_stage");
   return NBODY_OK;
 }
@@ -615,7 +626,7 @@ int persistent_grid(const void* kfn, int bs, int64_t units, unsigned& grid) {
 // Force pass on the staged j-array: acc = a, pot (nullable), vel += hh*acc when vel != NULL.
 int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
   const int prec = c.cfg->precision;
-  const bool comp = prec == NBODY_FP32_COMP;
+  const int mode = force_mode(prec);
   const int pot_on = pot != nullptr;
   const double eps2 = c.cfg->eps * c.cfg->eps;
   const void* jarr = c.ws + c.plan.off_jbuf;
@@ -633,7 +644,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
       if (tiles > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many symmetric tiles");
       TRY(check_part(c, (size_t)nb * 4 * ns * sizeof(float), "force_sym_kernel"));
       float* pf = (float*)(c.ws + c.plan.off_part);
-      sv.fn[pot_on][comp](dim3((unsigned)tiles), c.st, (const float4*)jarr + b, ns, (int32_t)nb, (float)eps2, pf);
+      sv.fn[pot_on][mode](dim3((unsigned)tiles), c.st, (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b, ns, (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("force_sym_kernel");
       hipLaunchKernelGGL(reduce_sym, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)nb, (const float*)pf, c.cfg->G,
                          acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh);
@@ -653,7 +664,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
       TRY(check_part(c, (size_t)S * 4 * n * sizeof(double), "force_kernel"));
       o.part = part;
     }
-    fv.fn[pot_on][comp](g, c.st, jarr, b, e, b, e, jc, eps2, o);
+    fv.fn[pot_on][mode](g, c.st, jarr, b, e, b, e, jc, eps2, o);
     LAUNCH_CHECK("force_kernel");
     if (S > 1) {
       // reduce only this system's particle range: offset pointers into the planes
@@ -678,12 +689,12 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)2, 0);
   LAUNCH_CHECK("fill_i32");
   unsigned grid;
-  persistent_grid(fv.bptr[pot_on][comp](), t.bs, c.plan.n_units_force, grid);
+  persistent_grid(fv.bptr[pot_on][mode](), t.bs, c.plan.n_units_force, grid);
   ForceOut o{};
   o.G = c.cfg->G;
   o.n_plane = n;
   o.part = part;
-  fv.bfn[pot_on][comp](dim3(grid), c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
+  fv.bfn[pot_on][mode](dim3(grid), c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
                        (int32_t)c.plan.n_units_force, counter, eps2, o);
   LAUNCH_CHECK("force_batched_kernel");
   hipLaunchKernelGGL(reduce_splits, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, c.cfg->G, acc, pot, vel, hh,
@@ -722,7 +733,7 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
   const int prec = c.cfg->precision;
   const bool comp = prec == NBODY_FP32_COMP;
   const double eps2 = c.cfg->eps * c.cfg->eps;
-  TRY(check_jbuf(c, 2, "adjoint_stage"));
+  TRY(check_jbuf(c, jadj_bytes(c.cfg->precision), "adjoint_stage"));
   void* jadj = c.ws + c.plan.off_jbuf;
   double* part = (double*)(c.ws + c.plan.off_part);
   const int64_t n = c.n;
@@ -995,7 +1006,7 @@ __attribute__((visibility("default"))) int nbody_set_tile_table(const nbody_tile
   for (int64_t k = 0; k < count; ++k) {
     const auto& e = entries[k];
     if (e.kernel < 0 || e.kernel > 3) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad kernel", (long long)k);
-    if (e.precision < 0 || e.precision > 2) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad precision", (long long)k);
+    if (e.precision < 0 || e.precision > 3) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad precision", (long long)k);
     if (e.variant < 0 || e.variant >= num_variants(e.kernel, e.precision))
       return fail(NBODY_ERR_INVALID_ARG, "entry %lld: variant %d out of range", (long long)k, e.variant);
     if (e.j_split < 1 || e.n_min > e.n_max) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad range/j_split", (long long)k);
@@ -1008,7 +1019,7 @@ __attribute__((visibility("default"))) int nbody_set_tile_table(const nbody_tile
 __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, int32_t precision, char* buf,
                                                                size_t cap) {
   g_err.clear();
-  if (kernel < 0 || kernel > 3 || precision < 0 || precision > 2) {
+  if (kernel < 0 || kernel > 3 || precision < 0 || precision > 3) {
     fail(NBODY_ERR_INVALID_ARG, "bad kernel/precision");
     return -1;
   }
@@ -1033,7 +1044,7 @@ __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, i
 __attribute__((visibility("default"))) int nbody_tile_lookup(int32_t kernel, int32_t precision, int64_t n,
                                                              int32_t* variant, int32_t* j_split) {
   g_err.clear();
-  if (kernel < 0 || kernel > 3 || precision < 0 || precision > 2 || !variant || !j_split)
+  if (kernel < 0 || kernel > 3 || precision < 0 || precision > 3 || !variant || !j_split)
     return fail(NBODY_ERR_INVALID_ARG, "bad arguments");
   Tile t = lookup_tile(kernel, precision, n);
   *variant = t.variant;

@@ -93,22 +93,41 @@ __device__ __forceinline__ double pair_rsqrt<double>(double s) { return rsqrt_f6
 // ----------------------------------------------------------------- staging / update kernels
 
 // j-array: (x, y, z, m) per particle in the pair precision, 16 B (float) or 32 B (double).
-template <typename T>
+// Double-float form (DS): two float4 per particle, (hi_x, hi_y, hi_z, m) and
+// (lo_x, lo_y, lo_z, 0) with hi = fl32(x), lo = fl32(x - hi), so hi + lo carries x to
+// about 48 bits and a separation (hi_j - hi_i) + (lo_j - lo_i) is exact to float
+// rounding of the separation itself, not of the coordinates.
+template <typename T, bool DS>
+__device__ __forceinline__ void put_j(typename Vec4<T>::type* __restrict__ jarr, int64_t i, const double x[3],
+                                      double m) {
+  if constexpr (DS) {
+    float4 h, l;
+    h.x = (float)x[0]; h.y = (float)x[1]; h.z = (float)x[2]; h.w = (float)m;
+    l.x = (float)(x[0] - (double)h.x);
+    l.y = (float)(x[1] - (double)h.y);
+    l.z = (float)(x[2] - (double)h.z);
+    l.w = 0.f;
+    jarr[2 * i] = h;
+    jarr[2 * i + 1] = l;
+  } else {
+    typename Vec4<T>::type v;
+    v.x = (T)x[0]; v.y = (T)x[1]; v.z = (T)x[2]; v.w = (T)m;
+    jarr[i] = v;
+  }
+}
+
+template <typename T, bool DS>
 __global__ void stage_j(int64_t n, const double* __restrict__ pos, const double* __restrict__ mass,
                         typename Vec4<T>::type* __restrict__ jarr) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  typename Vec4<T>::type v;
-  v.x = (T)pos[i];
-  v.y = (T)pos[n + i];
-  v.z = (T)pos[2 * n + i];
-  v.w = (T)mass[i];
-  jarr[i] = v;
+  const double x[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+  put_j<T, DS>(jarr, i, x, mass[i]);
 }
 
 // First half of a KDK step fused with the staging of the new positions:
 //   v += hh a;  x += h v;  jarr = (x, m) in pair precision.
-template <typename T>
+template <typename T, bool DS>
 __global__ void kick_drift_stage(int64_t n, double hh, double h, double* __restrict__ pos,
                                  double* __restrict__ vel, const double* __restrict__ acc,
                                  const double* __restrict__ mass, typename Vec4<T>::type* __restrict__ jarr) {
@@ -122,12 +141,7 @@ __global__ void kick_drift_stage(int64_t n, double hh, double h, double* __restr
     x[c] = pos[c * n + i] + h * v;
     pos[c * n + i] = x[c];
   }
-  typename Vec4<T>::type q;
-  q.x = (T)x[0];
-  q.y = (T)x[1];
-  q.z = (T)x[2];
-  q.w = (T)mass[i];
-  jarr[i] = q;
+  put_j<T, DS>(jarr, i, x, mass[i]);
 }
 
 // Sum of j-split partials (fixed order p = 0..S-1), scaled by G; optional potential
@@ -180,19 +194,28 @@ struct ForceOut {
   int64_t n_plane;
 };
 
+// Pair-math modes of the FP32 kernels: plain float sums, compensated sums, and
+// compensated sums with double-float separations.
+enum { MODE_PLAIN = 0, MODE_COMP = 1, MODE_DS = 2 };
+
 // One block's work: i in [ib, ie) (ie - ib <= BS*I) against j in [jb, je).
 // Returns the unscaled sums of every component in res[c][u] (c = ax, ay, az, phi).
-template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE>
 __device__ __forceinline__ void force_block(const typename Vec4<T>::type* __restrict__ jarr,
                                             int64_t ib, int64_t ie, int64_t jb, int64_t je, T eps2_arg,
-                                            typename Vec4<T>::type* tile, double res[4][I]) {
+                                            typename Vec4<T>::type* tile /* [TJ * (DS ? 2 : 1)] */,
+                                            double res[4][I]) {
   using V = typename Vec4<T>::type;
+  constexpr bool COMP = MODE != MODE_PLAIN;
+  constexpr bool DS = MODE == MODE_DS;
+  constexpr int NV = DS ? 2 : 1;  // vectors per particle in the j-array
   static_assert(TJ % BS == 0, "TJ must be a multiple of BS");
+  static_assert(!DS || sizeof(T) == 4, "double-float separations are a float mode");
   constexpr int PER = TJ / BS;
   const T eps2 = in_vgpr(eps2_arg);
   const int t = threadIdx.x;
 
-  T xi[I], yi[I], zi[I];
+  T xi[I], yi[I], zi[I], xl[I], yl[I], zl[I];
   T acc_t[4][I];        // running sum inside the current tile (or whole range if !COMP)
   float hi[4][I], lo[4][I];
   int64_t my_i[I];
@@ -201,69 +224,74 @@ __device__ __forceinline__ void force_block(const typename Vec4<T>::type* __rest
     int64_t i = ib + t + (int64_t)u * BS;
     my_i[u] = i;
     int64_t ic = i < ie ? i : ie - 1;  // lanes past the end read a valid particle, results dropped
-    V p = jarr[ic];
+    V p = jarr[NV * ic];
     xi[u] = in_vgpr(p.x);
     yi[u] = in_vgpr(p.y);
     zi[u] = in_vgpr(p.z);
+    if constexpr (DS) {
+      V pl = jarr[NV * ic + 1];
+      xl[u] = in_vgpr(pl.x);
+      yl[u] = in_vgpr(pl.y);
+      zl[u] = in_vgpr(pl.z);
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) { acc_t[c][u] = T(0); hi[c][u] = 0.f; lo[c][u] = 0.f; }
   }
 
-  V pre[PER];
+  V pre[NV * PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     int64_t j = jb + t + (int64_t)k * BS;
-    pre[k] = j < je ? jarr[j] : zero4<T>();  // zero-mass padding adds exactly 0
+#pragma unroll
+    for (int v = 0; v < NV; ++v) pre[NV * k + v] = j < je ? jarr[NV * j + v] : zero4<T>();  // zero mass adds 0
   }
 
   for (int64_t j0 = jb; j0 < je; j0 += TJ) {
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < PER; ++k) tile[t + k * BS] = pre[k];
+    for (int k = 0; k < PER; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) tile[NV * (t + k * BS) + v] = pre[NV * k + v];
     __syncthreads();
     if (j0 + TJ < je) {
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         int64_t j = j0 + TJ + t + (int64_t)k * BS;
-        pre[k] = j < je ? jarr[j] : zero4<T>();
+#pragma unroll
+        for (int v = 0; v < NV; ++v) pre[NV * k + v] = j < je ? jarr[NV * j + v] : zero4<T>();
       }
     }
     const bool diag = POT && (j0 < ie) && (j0 + TJ > ib);
+#define NBODY_FORCE_PAIR(MASKED)                                                          \
+    {                                                                                     \
+      const V q = tile[NV * jj];                                                          \
+      V ql;                                                                               \
+      if constexpr (DS) ql = tile[NV * jj + 1];                                           \
+      _Pragma("unroll") for (int u = 0; u < I; ++u) {                                     \
+        T dx = q.x - xi[u], dy = q.y - yi[u], dz = q.z - zi[u];                           \
+        if constexpr (DS) {                                                               \
+          dx += ql.x - xl[u];                                                             \
+          dy += ql.y - yl[u];                                                             \
+          dz += ql.z - zl[u];                                                             \
+        }                                                                                 \
+        T r2 = fmaT(dx, dx, fmaT(dy, dy, fmaT(dz, dz, eps2)));                            \
+        T ri = pair_rsqrt<T>(r2);                                                         \
+        T mr = q.w * ri;                                                                  \
+        T s = (mr * ri) * ri;                                                             \
+        acc_t[0][u] = fmaT(s, dx, acc_t[0][u]);                                           \
+        acc_t[1][u] = fmaT(s, dy, acc_t[1][u]);                                           \
+        acc_t[2][u] = fmaT(s, dz, acc_t[2][u]);                                           \
+        if (MASKED) acc_t[3][u] -= (j0 + jj == my_i[u]) ? T(0) : mr;                      \
+        else if (POT) acc_t[3][u] -= mr;                                                  \
+      }                                                                                   \
+    }
     if (!diag) {
 #pragma unroll 8
-      for (int jj = 0; jj < TJ; ++jj) {
-        const V q = tile[jj];
-#pragma unroll
-        for (int u = 0; u < I; ++u) {
-          T dx = q.x - xi[u], dy = q.y - yi[u], dz = q.z - zi[u];
-          T r2 = fmaT(dx, dx, fmaT(dy, dy, fmaT(dz, dz, eps2)));
-          T ri = pair_rsqrt<T>(r2);
-          T mr = q.w * ri;
-          T s = (mr * ri) * ri;
-          acc_t[0][u] = fmaT(s, dx, acc_t[0][u]);
-          acc_t[1][u] = fmaT(s, dy, acc_t[1][u]);
-          acc_t[2][u] = fmaT(s, dz, acc_t[2][u]);
-          if (POT) acc_t[3][u] -= mr;
-        }
-      }
+      for (int jj = 0; jj < TJ; ++jj) NBODY_FORCE_PAIR(false)
     } else {
-      for (int jj = 0; jj < TJ; ++jj) {
-        const V q = tile[jj];
-        const int64_t jg = j0 + jj;
-#pragma unroll
-        for (int u = 0; u < I; ++u) {
-          T dx = q.x - xi[u], dy = q.y - yi[u], dz = q.z - zi[u];
-          T r2 = fmaT(dx, dx, fmaT(dy, dy, fmaT(dz, dz, eps2)));
-          T ri = pair_rsqrt<T>(r2);
-          T mr = q.w * ri;
-          T s = (mr * ri) * ri;
-          acc_t[0][u] = fmaT(s, dx, acc_t[0][u]);
-          acc_t[1][u] = fmaT(s, dy, acc_t[1][u]);
-          acc_t[2][u] = fmaT(s, dz, acc_t[2][u]);
-          acc_t[3][u] -= (jg == my_i[u]) ? T(0) : mr;
-        }
-      }
+      for (int jj = 0; jj < TJ; ++jj) NBODY_FORCE_PAIR(true)
     }
+#undef NBODY_FORCE_PAIR
     if (COMP) {
 #pragma unroll
       for (int u = 0; u < I; ++u)
@@ -309,17 +337,17 @@ __device__ __forceinline__ void force_store(const ForceOut& o, int64_t ib, int64
 // Single system (or one i-range of it): grid (ceil(ni / (BS*I)), S).
 // Block (bx, by) takes i-range [i0 + bx*BS*I, ...) and the by-th of S j-ranges
 // of length jchunk (a multiple of TJ) inside [j0, j1).
-template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE>
 __global__ __launch_bounds__(BS) void force_kernel(const typename Vec4<T>::type* __restrict__ jarr,
                                                    int64_t i0, int64_t i1, int64_t j0, int64_t j1,
                                                    int64_t jchunk, T eps2, ForceOut o) {
-  __shared__ typename Vec4<T>::type tile[TJ];
+  __shared__ typename Vec4<T>::type tile[TJ * (MODE == MODE_DS ? 2 : 1)];
   const int64_t ib = i0 + (int64_t)blockIdx.x * BS * I;
   const int64_t ie = ib + BS * I < i1 ? ib + BS * I : i1;
   const int64_t jb = j0 + (int64_t)blockIdx.y * jchunk;
   const int64_t je = jb + jchunk < j1 ? jb + jchunk : j1;
   double res[4][I];
-  force_block<T, BS, I, TJ, POT, COMP>(jarr, ib, ie, jb, je, eps2, tile, res);
+  force_block<T, BS, I, TJ, POT, MODE>(jarr, ib, ie, jb, je, eps2, tile, res);
   force_store<I>(o, ib, ie, blockIdx.y, res, POT, BS);
 }
 
@@ -361,9 +389,12 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 // Output: float partial sums part[(slot*4 + c)*n + p], c = ax, ay, az, phi: the
 // i-side of tile (A, B) goes to slot B, the j-side to slot A, so every particle owns
 // exactly nb slots, summed in double (fixed order) by reduce_sym.
-template <int W, int I, bool POT, bool COMP>
+template <int W, int I, bool POT, int MODE>
 __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restrict__ jarr, int64_t n, int32_t nb,
                                                            float eps2_arg, float* __restrict__ part) {
+  constexpr bool COMP = MODE != MODE_PLAIN;
+  constexpr bool DS = MODE == MODE_DS;
+  constexpr int NV = DS ? 2 : 1;
   constexpr int BI = W * 64 * I;
   constexpr int NC = POT ? 4 : 3;
   constexpr int NSUB = BI / 64;
@@ -375,39 +406,54 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t Abase = (int64_t)A * BI, Bbase = (int64_t)B * BI;
   const float eps2 = in_vgpr(eps2_arg);
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 
-  float xi[I], yi[I], zi[I], mi[I];
+  float xi[I], yi[I], zi[I], mi[I], xl[I], yl[I], zl[I];
   float ai[NC][I], hi[NC][I], lo[NC][I];
 #pragma unroll
   for (int u = 0; u < I; ++u) {
     const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
-    const float4 p = jarr[i < n ? i : n - 1];
+    const int64_t ic = i < n ? i : n - 1;
+    const float4 p = jarr[NV * ic];
     xi[u] = in_vgpr(p.x);
     yi[u] = in_vgpr(p.y);
     zi[u] = in_vgpr(p.z);
     mi[u] = in_vgpr(i < n ? p.w : 0.f);  // padding lanes carry no mass: no j-side effect
+    if constexpr (DS) {
+      const float4 pl = jarr[NV * ic + 1];
+      xl[u] = in_vgpr(pl.x);
+      yl[u] = in_vgpr(pl.y);
+      zl[u] = in_vgpr(pl.z);
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) { ai[c][u] = 0.f; hi[c][u] = 0.f; lo[c][u] = 0.f; }
   }
 
-  float4 nxt;
+  float4 nxt, nxtl = zero;
   {
     const int64_t j = Bbase + lane;
-    nxt = j < n ? jarr[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    nxt = j < n ? jarr[NV * j] : zero;
+    if constexpr (DS) nxtl = j < n ? jarr[NV * j + 1] : zero;
   }
   for (int sb = 0; sb < NSUB; ++sb) {
-    const float4 q = nxt;
+    const float4 q = nxt, ql = nxtl;
     if (sb + 1 < NSUB) {
       const int64_t j = Bbase + (int64_t)(sb + 1) * 64 + lane;
-      nxt = j < n ? jarr[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      nxt = j < n ? jarr[NV * j] : zero;
+      if constexpr (DS) nxtl = j < n ? jarr[NV * j + 1] : zero;
     }
-    float xj = q.x, yj = q.y, zj = q.z, mj = q.w;
+    float xj = q.x, yj = q.y, zj = q.z, mj = q.w, xjl = ql.x, yjl = ql.y, zjl = ql.z;
     if (diag) {
       // one-sided: i-side only; the self pair is the step-0 pair of sub-block w*I + u
       for (int k = 0; k < 64; ++k) {
 #pragma unroll
         for (int u = 0; u < I; ++u) {
-          const float dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+          float dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+          if constexpr (DS) {
+            dx += xjl - xl[u];
+            dy += yjl - yl[u];
+            dz += zjl - zl[u];
+          }
           const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
           const float ri = __builtin_amdgcn_rsqf(r2);
           const float mr = mj * ri;
@@ -421,6 +467,11 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
         yj = wave_ror1(yj);
         zj = wave_ror1(zj);
         mj = wave_ror1(mj);
+        if constexpr (DS) {
+          xjl = wave_ror1(xjl);
+          yjl = wave_ror1(yjl);
+          zjl = wave_ror1(zjl);
+        }
       }
     } else {
       float aj[NC];
@@ -429,7 +480,12 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
       for (int k = 0; k < 64; ++k) {
 #pragma unroll
         for (int u = 0; u < I; ++u) {
-          const float dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+          float dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+          if constexpr (DS) {
+            dx += xjl - xl[u];
+            dy += yjl - yl[u];
+            dz += zjl - zl[u];
+          }
           const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
           const float ri = __builtin_amdgcn_rsqf(r2);
           // the acceleration terms round identically with and without the potential,
@@ -453,6 +509,11 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
         yj = wave_ror1(yj);
         zj = wave_ror1(zj);
         mj = wave_ror1(mj);
+        if constexpr (DS) {
+          xjl = wave_ror1(xjl);
+          yjl = wave_ror1(yjl);
+          zjl = wave_ror1(zjl);
+        }
 #pragma unroll
         for (int c = 0; c < NC; ++c) aj[c] = wave_ror1(aj[c]);
       }
@@ -526,11 +587,11 @@ struct WorkUnit {
 // is exhausted (units are sorted by decreasing cost on the host). Each unit writes
 // its own partial slot, so the result does not depend on which block ran it.
 // counter must be 0 at launch.
-template <typename T, int BS, int I, int TJ, bool POT, bool COMP>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE>
 __global__ __launch_bounds__(BS) void force_batched_kernel(const typename Vec4<T>::type* __restrict__ jarr,
                                                            const WorkUnit* __restrict__ units, int32_t n_units,
                                                            int32_t* __restrict__ counter, T eps2, ForceOut o) {
-  __shared__ typename Vec4<T>::type tile[TJ];
+  __shared__ typename Vec4<T>::type tile[TJ * (MODE == MODE_DS ? 2 : 1)];
   __shared__ int32_t next;
   for (;;) {
     __syncthreads();  // everyone has finished with the previous `next`
@@ -540,7 +601,7 @@ __global__ __launch_bounds__(BS) void force_batched_kernel(const typename Vec4<T
     if (u >= n_units) break;
     const WorkUnit w = units[u];
     double res[4][I];
-    force_block<T, BS, I, TJ, POT, COMP>(jarr, w.ib, w.ie, w.jb, w.je, eps2, tile, res);
+    force_block<T, BS, I, TJ, POT, MODE>(jarr, w.ib, w.ie, w.jb, w.je, eps2, tile, res);
     force_store<I>(o, w.ib, w.ie, w.slot, res, POT, BS);
   }
 }

@@ -15,8 +15,8 @@ from paper_2511_02655_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TOL_F = {"fp64": 1e-12, "fp32c": 1e-5, "fp32": 1e-4}
-TOL_P = {"fp64": 1e-12, "fp32c": 1e-6, "fp32": 1e-5}
+TOL_F = {"fp64": 1e-12, "fp32c": 1e-5, "fp32": 1e-4, "fp32ds": 1e-5}
+TOL_P = {"fp64": 1e-12, "fp32c": 1e-6, "fp32": 1e-5, "fp32ds": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -38,14 +38,15 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def fp32_bound(pos, mass, eps, G=1.0, accumulate_plain=False):
+def fp32_bound(pos, mass, eps, G=1.0, accumulate_plain=False, exact_coords=False):
     """Worst-case error bound of the FP32 pair path for every particle.
 
     Rounding the coordinates to float moves each separation by up to
     sqrt(3) u (|x_i| + |x_j|); the Jacobian of d s^{-3/2} has norm <= 2 s^{-3/2};
     the pair arithmetic and the compensated accumulation add a few u |term|.
     B_i = u G sum_j m_j s^{-3/2} (2 sqrt(3) (|x_i| + |x_j|) + 8 |d|)  (u = 2^-24);
-    plain float accumulation adds sqrt(n) u sum |term|."""
+    plain float accumulation adds sqrt(n) u sum |term|; double-float separations
+    (exact_coords) remove the coordinate term and leave 16 u |term|."""
     u = 2.0 ** -24
     n = mass.shape[0]
     xn = np.sqrt(np.sum(pos ** 2, axis=0))
@@ -56,13 +57,16 @@ def fp32_bound(pos, mass, eps, G=1.0, accumulate_plain=False):
         dn = np.sqrt(np.sum(d * d, axis=0))
         s = dn * dn + eps * eps
         w = mass[None, :] * s ** -1.5
-        k = 2 * math.sqrt(3.0) * (xn[i0:i1, None] + xn[None, :]) + (8 + (math.sqrt(n) if accumulate_plain else 0)) * dn
+        if exact_coords:
+            k = 16.0 * dn
+        else:
+            k = 2 * math.sqrt(3.0) * (xn[i0:i1, None] + xn[None, :]) + (8 + (math.sqrt(n) if accumulate_plain else 0)) * dn
         B[i0:i1] = u * G * np.sum(w * k, axis=1)
     return B
 
 
 def check_fp32(acc, ref, pos, mass, eps, prec, G=1.0):
-    B = fp32_bound(pos, mass, eps, G, accumulate_plain=(prec == "fp32"))
+    B = fp32_bound(pos, mass, eps, G, accumulate_plain=(prec == "fp32"), exact_coords=(prec == "fp32ds"))
     d = np.sqrt(np.sum((acc - ref) ** 2, axis=0))
     worst = float(np.max(d / B))
     assert worst <= 1.0, "error exceeds the FP32 bound by %.3g" % worst
@@ -76,7 +80,7 @@ def force_err(a, ref):
     return float(np.max(d / np.maximum(m, 1e-6 * rms))) if d.size else 0.0
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32", "fp32ds"])
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 255, 257, 1000, 1024, 4097])
 def test_forces_vs_oracle(nb, oracle, prec, n):
     s = inputs.uniform_cube(n, 100 + n)
@@ -142,7 +146,7 @@ def test_newton_third_law_gpu(nb):
     assert np.max(np.abs(total)) < 1e-12 * np.abs(a * s.mass).sum()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32", "fp32ds"])
 def test_plummer64k_sampled(nb, oracle, prec):
     """Plummer sphere n = 65536, eps = 1e-2 (the compensated-FP32 accuracy workload):
     256 random particles plus the 64 nearest the centre against the oracle."""
@@ -159,7 +163,7 @@ def test_plummer64k_sampled(nb, oracle, prec):
     assert np.max(np.abs(pot - pot_ref) / np.abs(pot_ref)) <= TOL_P[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32c", "fp64", "fp32ds"])
 def test_plummer1m_sampled(nb, oracle, prec):
     """Full-size Plummer sphere n = 1048576, eps = 1e-3, in the launch configuration the
     benchmark times: sampled particles (including the ragged last block) vs the oracle."""
@@ -433,7 +437,7 @@ def test_autograd_function(nb, oracle):
 
 def _force_table(nb, variant, kernel="force", precision="fp32c", j_split=1):
     nb.set_tile_table([dict(kernel=kernel, precision=p, n_min=0, n_max=1 << 40, variant=variant, j_split=j_split)
-                       for p in (["fp32", "fp32c"] if precision == "fp32*" else [precision])])
+                       for p in (["fp32", "fp32c", "fp32ds"] if precision == "fp32*" else [precision])])
 
 
 def _sym_variants(nb):
@@ -449,7 +453,7 @@ def test_symmetric_kernel_vs_oracle(nb, oracle, n):
     try:
         for v in _sym_variants(nb):
             _force_table(nb, v, precision="fp32*")
-            for prec in ("fp32c", "fp32"):
+            for prec in ("fp32c", "fp32", "fp32ds"):
                 for want_pot in (True, False):
                     acc, pot = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision=prec, want_pot=want_pot)
                     acc = host(acc)
@@ -519,3 +523,28 @@ def test_step_potential_output(nb):
         a2, p2 = nb.forces(pos, mass, precision="fp32c", want_pot=True)
         assert np.array_equal(host(pot), host(p2))
         assert np.array_equal(host(acc), host(a2))
+
+
+@pytest.mark.parametrize("n", [3000, 40000])
+def test_double_float_rollout_backward(nb, oracle, n):
+    """Double-float separations: rollout matches the oracle, and the backward pass
+    (recomputing with the same mode) is bitwise independent of the checkpoint interval."""
+    s = inputs.plummer(n, 37)
+    g = np.random.Generator(np.random.PCG64(38))
+    gxK, gvK = g.normal(size=(3, n)), g.normal(size=(3, n))
+    res = []
+    for ck in (1, 3):
+        pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+        acc, _ = nb.forces(pos, mass, precision="fp32ds")
+        ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 3, ckpt_every=ck, precision="fp32ds")
+        res.append([host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 3, ck,
+                                                         precision="fp32ds")])
+        x = host(pos)
+    for a, b in zip(res[1], res[0]):
+        assert np.array_equal(a, b)
+    if n <= 3000:
+        xr, _, _, _ = oracle.kdk(s.pos, s.vel, s.mass, 1e-3, 3, eps=1e-2)
+        assert np.max(np.abs(x - xr)) <= 1e-9
+        ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, 1e-3, 3, gxK, gvK, eps=1e-2)
+        for a, b in zip(res[0], ref):
+            assert _rel_l2(a, b) <= 1e-4
