@@ -165,6 +165,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--quick", action="store_true", help="FP32-compensated force buckets only")
+    ap.add_argument("--precisions", default=None, help="comma list (default: all)")
+    ap.add_argument("--kernels", default="force,adjoint,batched", help="comma list of force, adjoint, batched")
+    ap.add_argument("--merge", default=None, help="existing table: keep its entries for everything not re-tuned")
+    ap.add_argument("--force-buckets", default=None, help="comma list of particle counts for the force buckets")
     args = ap.parse_args()
     import torch
     import paper_2511_02655_amd as nb
@@ -177,13 +181,25 @@ def main():
     t0 = time.time()
     entries = []
     precs = ["fp32c"] if args.quick else ["fp32c", "fp32", "fp32ds", "fp64"]
-    for p in precs:
-        entries += tune_force(nb, torch, p, FORCE_BUCKETS, log)
-    if not args.quick:
-        for p in ("fp32c", "fp32", "fp64"):
-            entries += tune_adjoint(nb, torch, p, ADJ_BUCKETS, log)
-        for p in ("fp32c", "fp32", "fp64"):
+    if args.precisions:
+        precs = args.precisions.split(",")
+    kernels = ["force"] if args.quick else args.kernels.split(",")
+    fb = [int(x) for x in args.force_buckets.split(",")] if args.force_buckets else FORCE_BUCKETS
+    if "force" in kernels:
+        for p in precs:
+            entries += tune_force(nb, torch, p, fb, log)
+    if "adjoint" in kernels:
+        for p in precs:
+            if p != "fp32ds":  # adjoint passes of the double-float mode run the compensated kernels
+                entries += tune_adjoint(nb, torch, p, ADJ_BUCKETS, log)
+    if "batched" in kernels:
+        for p in precs:
             entries += tune_batched(nb, torch, p, log)
+    if args.merge and os.path.exists(args.merge):
+        with open(args.merge) as f:
+            old = json.load(f).get("entries", [])
+        tuned = {(e["kernel"], e["precision"]) for e in entries}
+        entries = [e for e in old if (e["kernel"], e["precision"]) not in tuned] + entries
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     table = {"arch": arch, "tuned_in_s": time.time() - t0, "entries": entries}
     out = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune", arch + ".json")

@@ -478,32 +478,41 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 #pragma unroll
       for (int c = 0; c < NC; ++c) aj[c] = 0.f;
       for (int k = 0; k < 64; ++k) {
+        // phase 1: separations and r^2 of the I pairs; phase 2: their square roots;
+        // phase 3: scale factors and accumulation - independent work behind every rsq
+        float dx[I], dy[I], dz[I], ri[I];
 #pragma unroll
         for (int u = 0; u < I; ++u) {
-          float dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+          dx[u] = xj - xi[u];
+          dy[u] = yj - yi[u];
+          dz[u] = zj - zi[u];
           if constexpr (DS) {
-            dx += xjl - xl[u];
-            dy += yjl - yl[u];
-            dz += zjl - zl[u];
+            dx[u] += xjl - xl[u];
+            dy[u] += yjl - yl[u];
+            dz[u] += zjl - zl[u];
           }
-          const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
-          const float ri = __builtin_amdgcn_rsqf(r2);
+          ri[u] = __builtin_fmaf(dx[u], dx[u], __builtin_fmaf(dy[u], dy[u], __builtin_fmaf(dz[u], dz[u], eps2)));
+        }
+#pragma unroll
+        for (int u = 0; u < I; ++u) ri[u] = __builtin_amdgcn_rsqf(ri[u]);
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
           // the acceleration terms round identically with and without the potential,
           // so both variants give bitwise-equal accelerations (trajectories must not
           // depend on whether an energy trace is taken)
-          const float r3 = ri * (ri * ri);
+          const float r3 = ri[u] * (ri[u] * ri[u]);
           const float si = mj * r3;
           const float sj = mi[u] * r3;
           if (POT) {
-            ai[3][u] -= mj * ri;
-            aj[3] -= mi[u] * ri;
+            ai[3][u] -= mj * ri[u];
+            aj[3] -= mi[u] * ri[u];
           }
-          ai[0][u] = __builtin_fmaf(si, dx, ai[0][u]);
-          ai[1][u] = __builtin_fmaf(si, dy, ai[1][u]);
-          ai[2][u] = __builtin_fmaf(si, dz, ai[2][u]);
-          aj[0] = __builtin_fmaf(-sj, dx, aj[0]);
-          aj[1] = __builtin_fmaf(-sj, dy, aj[1]);
-          aj[2] = __builtin_fmaf(-sj, dz, aj[2]);
+          ai[0][u] = __builtin_fmaf(si, dx[u], ai[0][u]);
+          ai[1][u] = __builtin_fmaf(si, dy[u], ai[1][u]);
+          ai[2][u] = __builtin_fmaf(si, dz[u], ai[2][u]);
+          aj[0] = __builtin_fmaf(-sj, dx[u], aj[0]);
+          aj[1] = __builtin_fmaf(-sj, dy[u], aj[1]);
+          aj[2] = __builtin_fmaf(-sj, dz[u], aj[2]);
         }
         xj = wave_ror1(xj);
         yj = wave_ror1(yj);
