@@ -188,6 +188,8 @@ def main():
 
     if not args.no_extras:
         out["error"] = force_errors(nb, torch, np, pos0, mass, s, eps, prec)
+        out["cube1k"] = cube1k_leg(nb, torch, np, inputs, dev)
+        out["plummer64k"] = plummer64k_leg(nb, torch, np, inputs, dev)
         out["adjoint"] = adjoint_leg(nb, torch, np, inputs, dev)
         out["batched"] = batched_leg(nb, torch, np, inputs, dev)
     if not args.no_cpu:
@@ -242,6 +244,77 @@ def force_errors(nb, torch, np, pos0, mass, s, eps, prec):
     }
 
 
+def cube1k_leg(nb, torch, np, inputs, dev):
+    """Uniform cube N = 1024, eps = 1e-2, 10 KDK steps dt = 1e-3 in FP64 on the GPU against
+    the CPU oracle: forces, final state, energy and momentum."""
+    import oracle
+    log("cube1k leg")
+    W = inputs.WORKLOADS["cube1k"]
+    s = inputs.make("cube1k")
+    pos = torch.from_numpy(s.pos).to(dev)
+    vel = torch.from_numpy(s.vel).to(dev)
+    m = torch.from_numpy(s.mass).to(dev)
+    acc, pot = nb.forces(pos, m, eps=W["eps"], precision="fp64", want_pot=True)
+    a_ref, p_ref = oracle.forces(s.pos, s.mass, eps=W["eps"])
+    a = acc.cpu().numpy()
+    rms = math.sqrt(np.mean(np.sum(a_ref ** 2, axis=0)))
+    e = np.sqrt(np.sum((a - a_ref) ** 2, axis=0)) / np.maximum(np.sqrt(np.sum(a_ref ** 2, axis=0)), 1e-6 * rms)
+    _, trace = nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], energy_trace=True, eps=W["eps"], precision="fp64")
+    xr, vr, _, er = oracle.kdk(s.pos, s.vel, s.mass, W["dt"], W["steps"], eps=W["eps"], want_energy=True)
+    tr = trace.cpu().numpy()[:, 0, :]
+    E, Er = tr[:, 0] + tr[:, 1], er[:, 0] + er[:, 1]
+    return {"workload": "cube1k: uniform cube N=1024, eps=1e-2, 10 KDK steps dt=1e-3, FP64 GPU vs CPU oracle",
+            "force_max_e": float(e.max()),
+            "phi_max_rel": float(np.max(np.abs(pot.cpu().numpy() - p_ref) / np.abs(p_ref))),
+            "final_x_max_abs_diff": float(np.max(np.abs(pos.cpu().numpy() - xr))),
+            "final_v_max_abs_diff": float(np.max(np.abs(vel.cpu().numpy() - vr))),
+            "energy_max_rel_diff": float(np.max(np.abs(E - Er) / abs(Er[0]))),
+            "momentum_max_abs_diff": float(np.max(np.abs(tr[:, 2:] - er[:, 2:]))),
+            "energy_drift_gpu": float(np.max(np.abs(E - E[0])) / abs(E[0]))}
+
+
+def plummer64k_leg(nb, torch, np, inputs, dev):
+    """Plummer sphere N = 65536, eps = 1e-2, 100 KDK steps dt = 1e-3 in every pair-math mode
+    with an energy trace: energy drift, final-state error against the FP64 GPU path, time;
+    the initial energy also against the CPU oracle."""
+    import oracle
+    log("plummer64k leg")
+    W = inputs.WORKLOADS["plummer64k"]
+    s = inputs.make("plummer64k")
+    x0 = torch.from_numpy(s.pos).to(dev)
+    v0 = torch.from_numpy(s.vel).to(dev)
+    m = torch.from_numpy(s.mass).to(dev)
+    res = {"workload": "plummer64k: Plummer N=65536, eps=1e-2, 100 KDK steps dt=1e-3"}
+    finals = {}
+    for mode in ("fp64", "fp32c", "fp32ds", "fp32"):
+        pos, vel = x0.clone(), v0.clone()
+        acc, _ = nb.forces(pos, m, eps=W["eps"], precision=mode)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, trace = nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], energy_trace=True, eps=W["eps"],
+                              precision=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        tr = trace.cpu().numpy()[:, 0, :]
+        E = tr[:, 0] + tr[:, 1]
+        finals[mode] = (pos, vel, E)
+        res[mode] = {"rollout_ms": e0.elapsed_time(e1),
+                     "interactions_per_s_with_potential": (W["steps"] + 1) * 65536.0 ** 2 / (e0.elapsed_time(e1) * 1e-3),
+                     "energy_drift": float(np.max(np.abs(E - E[0])) / abs(E[0])),
+                     "momentum_drift": float(np.max(np.abs(tr[:, 2:] - tr[0, 2:])))}
+    x64, v64, E64 = finals["fp64"]
+    rmsx = float(torch.sqrt((x64 ** 2).mean()))
+    for mode in ("fp32c", "fp32ds", "fp32"):
+        x, v, E = finals[mode]
+        res[mode]["final_x_max_abs_diff_over_rms_vs_fp64_gpu"] = float(torch.max(torch.abs(x - x64))) / rmsx
+        res[mode]["energy_trace_max_rel_diff_vs_fp64_gpu"] = float(np.max(np.abs(E - E64) / abs(E64[0])))
+    em = oracle.energy_momentum(s.pos, s.vel, s.mass, eps=W["eps"])
+    res["fp64"]["E0_rel_diff_vs_oracle"] = float(abs(E64[0] - (em[0] + em[1])) / abs(em[0] + em[1]))
+    return res
+
+
 def adjoint_leg(nb, torch, np, inputs, dev):
     """Two-sphere merger N = 2 x 8192, eps = 1e-2, 200 KDK steps dt = 1e-3, checkpoints
     every 20; loss = mean squared distance of the final positions to a Gaussian target
@@ -291,6 +364,28 @@ def adjoint_leg(nb, torch, np, inputs, dev):
     g64 = nb.rollout_backward(m, ck64, gxK64, torch.zeros_like(gxK64), W["dt"], W["steps"], ckpt_every,
                               eps=W["eps"], precision="fp64")
     rel = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(g32, g64)]
+
+    # FP64 finite differences of the loss along random directions (central, h relative to the group scale)
+    def loss64(xa, va, ma):
+        p, v = xa.clone(), va.clone()
+        a, _ = nb.forces(p, ma, eps=W["eps"], precision="fp64")
+        nb.rollout(p, v, ma, a, W["dt"], W["steps"], eps=W["eps"], precision="fp64")
+        return float(((p - y) ** 2).sum()) / s.n
+
+    gen = torch.Generator(device="cpu").manual_seed(9)
+    fd = {}
+    for k, (name, scale) in enumerate((("x0", 1.0), ("v0", 0.3), ("m", float(m.mean())))):
+        base = (x0, v0, m)[k]
+        d = torch.randn(base.shape, generator=gen, dtype=torch.float64).to(dev)
+        h = 1e-6 * scale
+        args_p = [x0, v0, m]
+        args_m = [x0, v0, m]
+        args_p[k] = base + h * d
+        args_m[k] = base - h * d
+        fdv = (loss64(*args_p) - loss64(*args_m)) / (2 * h)
+        fd[name] = {"fd": fdv, "adjoint_fp32c": float((g32[k] * d).sum()), "adjoint_fp64": float((g64[k] * d).sum()),
+                    "rel_err_fp32c": abs(float((g32[k] * d).sum()) - fdv) / abs(fdv),
+                    "rel_err_fp64": abs(float((g64[k] * d).sum()) - fdv) / abs(fdv)}
     return {
         "workload": "merger2x8k: two Plummer spheres N=2x8192, eps=1e-2, 200 KDK steps dt=1e-3, ckpt every 20, "
                     "MSD loss to Gaussian targets; FP32 compensated",
@@ -301,6 +396,7 @@ def adjoint_leg(nb, torch, np, inputs, dev):
         "adjoint_interactions_per_s_incl_recompute": adj_passes * n2 / (bwd_ms * 1e-3),
         "forward_interactions_per_s": (W["steps"] + 1) * n2 / (fwd_ms * 1e-3),
         "grad_rel_l2_vs_fp64_gpu": {"x0": rel[0], "v0": rel[1], "m": rel[2]},
+        "directional_vs_fp64_finite_differences": fd,
     }
 
 

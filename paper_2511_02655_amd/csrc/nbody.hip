@@ -164,7 +164,7 @@ struct SymVariant {
     W, I, {{launch_sym<W, I, false, 0>, launch_sym<W, I, false, 1>, launch_sym<W, I, false, 2>}, \
            {launch_sym<W, I, true, 0>, launch_sym<W, I, true, 1>, launch_sym<W, I, true, 2>}}    \
   }
-const SymVariant kSym32[] = {SV32(8, 4), SV32(4, 4), SV32(8, 2), SV32(4, 2)};
+const SymVariant kSym32[] = {SV32(8, 4), SV32(4, 4), SV32(8, 2), SV32(4, 2), SV32(2, 4)};
 constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
 
 constexpr int kNumForce32 = sizeof(kForce32) / sizeof(kForce32[0]);

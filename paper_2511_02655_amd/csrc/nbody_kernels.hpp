@@ -530,8 +530,8 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 #pragma unroll
       for (int c = 0; c < NC; ++c) red[sb & 1][w][c][lane] = aj[c];
       __syncthreads();
-      if (threadIdx.x < NC * 64) {
-        const int c = threadIdx.x >> 6, l = threadIdx.x & 63;
+      for (int idx = threadIdx.x; idx < NC * 64; idx += W * 64) {  // any W, any NC
+        const int c = idx >> 6, l = idx & 63;
         float sum = 0.f;
 #pragma unroll
         for (int ww = 0; ww < W; ++ww) sum += red[sb & 1][ww][c][l];
