@@ -83,7 +83,7 @@ def tune_force(nb, torch, precision, buckets, log):
                                                                                       t, rate))
                 # prefer bigger symmetric blocks (half the partial-sum workspace) within 1%
                 key = t * (0.99 if (sym and best is not None and "sym=" in descs[best[1]] and
-                                    int(descs[v].split("sym=")[1]) > int(descs[best[1]].split("sym=")[1])) else 1.0)
+                                    int(descs[v].split("sym=")[1].split(",")[0]) > int(descs[best[1]].split("sym=")[1].split(",")[0])) else 1.0)
                 if best is None or key < best[0]:
                     best = (t, v, js, rate)
         lo, hi = _bounds(buckets, k)

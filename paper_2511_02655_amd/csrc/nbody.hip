@@ -151,20 +151,21 @@ const AdjVariant kAdj64[] = {AV64(256, 1, 256), AV64(128, 1, 128), AV64(64, 1, 6
 // Symmetric FP32 force variants (each pair once), indices kNumForce32 + k in the
 // FORCE tile table.
 using SymFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part);
-template <int W, int I, bool POT, int MODE>
+template <int W, int I, bool POT, int MODE, int ROT>
 void launch_sym(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part) {
-  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
+  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE, ROT>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
 }
 struct SymVariant {
-  int w, i;
+  int w, i, rot;   // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
   SymFn fn[2][3];  // [pot][mode]
 };
-#define SV32(W, I)                                                                            \
-  SymVariant {                                                                                \
-    W, I, {{launch_sym<W, I, false, 0>, launch_sym<W, I, false, 1>, launch_sym<W, I, false, 2>}, \
-           {launch_sym<W, I, true, 0>, launch_sym<W, I, true, 1>, launch_sym<W, I, true, 2>}}    \
+#define SV32(W, I, R)                                                                                     \
+  SymVariant {                                                                                            \
+    W, I, R, {{launch_sym<W, I, false, 0, R>, launch_sym<W, I, false, 1, R>, launch_sym<W, I, false, 2, R>}, \
+              {launch_sym<W, I, true, 0, R>, launch_sym<W, I, true, 1, R>, launch_sym<W, I, true, 2, R>}}    \
   }
-const SymVariant kSym32[] = {SV32(8, 4), SV32(4, 4), SV32(8, 2), SV32(4, 2), SV32(2, 4)};
+const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4, 2, 0), SV32(2, 4, 0),
+                             SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1)};
 constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
 
 constexpr int kNumForce32 = sizeof(kForce32) / sizeof(kForce32[0]);
@@ -200,7 +201,7 @@ void variant_shape(int kernel, int prec, int v, int& bs, int& i, int& tj) {
   int sv = sym_index(kernel, prec, v);
   if (sv >= 0) {
     // symmetric: block of bs = W*64 threads, i per lane, tile edge tj = W*64*I
-    bs = kSym32[sv].w * 64; i = kSym32[sv].i; tj = bs * i;
+    bs = kSym32[sv].w * 64; i = kSym32[sv].i; tj = bs * i;  // rotation kind: kSym32[sv].rot
     return;
   }
   if (f) {
@@ -1031,7 +1032,8 @@ __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, i
       variant_shape(kernel, precision, v, bs, i, tj);
       char tmp[64];
       int len = sym_index(kernel, precision, v) >= 0
-                    ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d", bs, i, tj)
+                    ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d%s", bs, i, tj,
+                               kSym32[sym_index(kernel, precision, v)].rot ? ",rot=lds" : "")
                     : snprintf(tmp, sizeof tmp, "bs=%d,i=%d,tj=%d", bs, i, tj);
       if (pos + len + 1 > cap) break;
       memcpy(buf + pos, tmp, len + 1);

@@ -359,6 +359,18 @@ __device__ __forceinline__ float wave_ror1(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x13C, 0xF, 0xF, false));
 }
 
+// The same rotation through the LDS crossbar (ds_bpermute: no LDS storage, no VALU
+// issue slot). src_byte = 4 * ((lane - 1) & 63).
+__device__ __forceinline__ float wave_ror1_lds(float v, int src_byte) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
+}
+
+template <int ROT>
+__device__ __forceinline__ float rotate1(float v, int src_byte) {
+  if constexpr (ROT == 0) return wave_ror1(v);
+  else return wave_ror1_lds(v, src_byte);
+}
+
 // Tile t of the upper triangle (A <= B) of an nb x nb block grid, row-major:
 // row A holds tiles B = A .. nb-1, and rows before A hold A*nb - A*(A-1)/2 tiles.
 __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32_t& B) {
@@ -389,7 +401,7 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 // Output: float partial sums part[(slot*4 + c)*n + p], c = ax, ay, az, phi: the
 // i-side of tile (A, B) goes to slot B, the j-side to slot A, so every particle owns
 // exactly nb slots, summed in double (fixed order) by reduce_sym.
-template <int W, int I, bool POT, int MODE>
+template <int W, int I, bool POT, int MODE, int ROT>
 __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restrict__ jarr, int64_t n, int32_t nb,
                                                            float eps2_arg, float* __restrict__ part) {
   constexpr bool COMP = MODE != MODE_PLAIN;
@@ -404,6 +416,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
   tile_rc(blockIdx.x, nb, A, B);
   const bool diag = (A == B);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rot_src = ((lane - 1) & 63) << 2;  // rotation source lane (byte address) for ROT = 1
   const int64_t Abase = (int64_t)A * BI, Bbase = (int64_t)B * BI;
   const float eps2 = in_vgpr(eps2_arg);
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -463,14 +476,14 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
           ai[2][u] = __builtin_fmaf(s, dz, ai[2][u]);
           if (POT) ai[3][u] -= (k == 0 && sb == w * I + u) ? 0.f : mr;
         }
-        xj = wave_ror1(xj);
-        yj = wave_ror1(yj);
-        zj = wave_ror1(zj);
-        mj = wave_ror1(mj);
+        xj = rotate1<ROT>(xj, rot_src);
+        yj = rotate1<ROT>(yj, rot_src);
+        zj = rotate1<ROT>(zj, rot_src);
+        mj = rotate1<ROT>(mj, rot_src);
         if constexpr (DS) {
-          xjl = wave_ror1(xjl);
-          yjl = wave_ror1(yjl);
-          zjl = wave_ror1(zjl);
+          xjl = rotate1<ROT>(xjl, rot_src);
+          yjl = rotate1<ROT>(yjl, rot_src);
+          zjl = rotate1<ROT>(zjl, rot_src);
         }
       }
     } else {
@@ -514,17 +527,17 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
           aj[1] = __builtin_fmaf(-sj, dy[u], aj[1]);
           aj[2] = __builtin_fmaf(-sj, dz[u], aj[2]);
         }
-        xj = wave_ror1(xj);
-        yj = wave_ror1(yj);
-        zj = wave_ror1(zj);
-        mj = wave_ror1(mj);
+        xj = rotate1<ROT>(xj, rot_src);
+        yj = rotate1<ROT>(yj, rot_src);
+        zj = rotate1<ROT>(zj, rot_src);
+        mj = rotate1<ROT>(mj, rot_src);
         if constexpr (DS) {
-          xjl = wave_ror1(xjl);
-          yjl = wave_ror1(yjl);
-          zjl = wave_ror1(zjl);
+          xjl = rotate1<ROT>(xjl, rot_src);
+          yjl = rotate1<ROT>(yjl, rot_src);
+          zjl = rotate1<ROT>(zjl, rot_src);
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) aj[c] = wave_ror1(aj[c]);
+        for (int c = 0; c < NC; ++c) aj[c] = rotate1<ROT>(aj[c], rot_src);
       }
       // j-side of this sub-block: sum the W waves in wave order, write slot A
 #pragma unroll
