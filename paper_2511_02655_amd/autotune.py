@@ -56,6 +56,18 @@ def _reps_for(n):
     return int(min(50, max(2, 2e11 / max(work, 1.0))))
 
 
+def _sym_edge(desc):
+    return int(desc.split("sym=")[1].split(",")[0]) if "sym=" in desc else 0
+
+
+def _pick(cands, descs, slack=0.01):
+    """Fastest candidate; among those within `slack` of it, the one with the largest
+    symmetric block (fewer partial-sum slots: half the workspace per doubling)."""
+    tmin = min(c[0] for c in cands)
+    near = [c for c in cands if c[0] <= tmin * (1.0 + slack)]
+    return max(near, key=lambda c: (_sym_edge(descs[c[1]]), -c[0]))
+
+
 def tune_force(nb, torch, precision, buckets, log):
     from . import inputs
     entries = []
@@ -66,7 +78,7 @@ def tune_force(nb, torch, precision, buckets, log):
         mass = torch.from_numpy(s.mass).cuda()
         acc = torch.empty((3, n), dtype=torch.float64, device="cuda")
         reps = _reps_for(n)
-        best = None
+        cands = []
         descs = nb.tile_variants("force", precision)
         for v in range(nvar):
             sym = "sym=" in descs[v]
@@ -81,11 +93,8 @@ def tune_force(nb, torch, precision, buckets, log):
                 rate = float(n) * n / (t * 1e-3)
                 log("force %s n=%d variant %d (%s) j_split %d: %.3f ms  %.3e inter/s" % (precision, n, v, descs[v], js,
                                                                                       t, rate))
-                # prefer bigger symmetric blocks (half the partial-sum workspace) within 1%
-                key = t * (0.99 if (sym and best is not None and "sym=" in descs[best[1]] and
-                                    int(descs[v].split("sym=")[1].split(",")[0]) > int(descs[best[1]].split("sym=")[1].split(",")[0])) else 1.0)
-                if best is None or key < best[0]:
-                    best = (t, v, js, rate)
+                cands.append((t, v, js, rate))
+        best = _pick(cands, descs)
         lo, hi = _bounds(buckets, k)
         entries.append(dict(kernel="force", precision=precision, n_min=lo, n_max=hi, variant=best[1],
                             j_split=best[2], tuned_n=n, ms=best[0], interactions_per_s=best[3]))
