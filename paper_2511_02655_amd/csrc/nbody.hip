@@ -165,7 +165,8 @@ struct SymVariant {
               {launch_sym<W, I, true, 0, R>, launch_sym<W, I, true, 1, R>, launch_sym<W, I, true, 2, R>}}    \
   }
 const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4, 2, 0), SV32(2, 4, 0),
-                             SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1)};
+                             SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1), SV32(2, 4, 1),
+                             SV32(4, 2, 1), SV32(2, 2, 1)};
 constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
 
 constexpr int kNumForce32 = sizeof(kForce32) / sizeof(kForce32[0]);
