@@ -37,9 +37,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+SYM_BEGIN = "// ----------------------------------------------------------------- symmetric force pass (FP32)"
+SYM_END = "// ----------------------------------------------------------------- batched persistent force pass"
+
+
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the symmetric force pass's source (the kernel the stored counters describe)."""
+    with open(KERNEL_SRC) as f:
+        src = f.read()
+    if SYM_BEGIN in src and SYM_END in src:
+        src = src[src.index(SYM_BEGIN):src.index(SYM_END)]
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def stored_traffic(per_launch_n2):
