@@ -96,10 +96,10 @@ typedef struct {
   uint32_t reserved;       /* must be 0 */
 } nbody_config;
 
-/* Bytes of workspace any call below needs for n particles (in cfg's systems),
- * a rollout/backward of `steps` steps with checkpoints every `ckpt_every`
- * steps (pass 0, 0 when no rollout/backward is planned). The size depends on
- * cfg->precision, cfg->n_systems/offsets and the tile table.
+/* Bytes of workspace any call below needs for n particles (in cfg's systems).
+ * For nbody_rollout_backward pass its ckpt_every (>= 1; the size grows with it);
+ * pass 0 when no backward pass is planned. `steps` must be >= 0. The size depends
+ * on cfg->precision, cfg->n_systems/offsets and the tile table.
  * Returns NBODY_OK and writes *bytes. */
 int nbody_workspace_size(const nbody_config *cfg, int64_t n, int64_t steps, int64_t ckpt_every,
                          size_t *bytes);

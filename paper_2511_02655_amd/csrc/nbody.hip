@@ -844,7 +844,7 @@ __attribute__((visibility("default"))) int nbody_workspace_size(const nbody_conf
   if (ckpt_every < 0) return fail(NBODY_ERR_INVALID_ARG, "ckpt_every must be >= 0");
   Plan p;
   unsigned need = NEED_FORCE | NEED_ENERGY | NEED_ROLLOUT;
-  if (steps > 0 && ckpt_every > 0) need |= NEED_BACKWARD;
+  if (ckpt_every > 0) need |= NEED_BACKWARD;  // what nbody_rollout_backward plans for any step count
   TRY(make_plan(cfg, sys, n, std::max<int64_t>(ckpt_every, 1), need, p, nullptr, nullptr));
   *bytes = p.total;
   return NBODY_OK;

@@ -548,3 +548,78 @@ def test_double_float_rollout_backward(nb, oracle, n):
         ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, 1e-3, 3, gxK, gvK, eps=1e-2)
         for a, b in zip(res[0], ref):
             assert _rel_l2(a, b) <= 1e-4
+
+
+# ------------------------------------------------------------------ edge cases
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32ds"])
+def test_coincident_particles_closed_form(nb, prec):
+    """All particles at one point: every separation is 0, so a = 0 exactly and
+    phi_i = -G (M - m_i) / eps."""
+    n = 3000
+    g = np.random.Generator(np.random.PCG64(40))
+    mass = g.uniform(0.5, 1.5, n) / n
+    pos = np.tile(np.array([[0.3], [-0.2], [0.7]]), (1, n))
+    acc, pot = nb.forces(dev(pos), dev(mass), G=1.7, eps=0.05, precision=prec, want_pot=True)
+    assert np.all(host(acc) == 0)
+    ref = -1.7 * (mass.sum() - mass) / 0.05
+    np.testing.assert_allclose(host(pot), ref, rtol=1e-12 if prec == "fp64" else 1e-6)
+
+
+def test_zero_and_negative_G_and_massless(nb, oracle):
+    s = inputs.plummer(2000, 41)
+    a0, p0 = nb.forces(dev(s.pos), dev(s.mass), G=0.0, precision="fp64", want_pot=True)
+    assert np.all(host(a0) == 0) and np.all(host(p0) == 0)
+    an, _ = nb.forces(dev(s.pos), dev(s.mass), G=-1.0, precision="fp64")
+    ap, _ = nb.forces(dev(s.pos), dev(s.mass), G=1.0, precision="fp64")
+    np.testing.assert_array_equal(host(an), -host(ap))
+    m = s.mass.copy()
+    m[::2] = 0.0  # massless tracers feel the field but exert none
+    acc, _ = nb.forces(dev(s.pos), dev(m), precision="fp64")
+    ref, _ = oracle.forces(s.pos, m, eps=1e-2)
+    assert force_err(host(acc), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_large_softening_is_harmonic_core(nb, oracle, prec):
+    """eps much larger than the system: a_i -> -G sum_j m_j (x_i - x_j) / eps^3 (harmonic)."""
+    s = inputs.uniform_cube(1500, 42)
+    eps = 1e3
+    acc, _ = nb.forces(dev(s.pos), dev(s.mass), eps=eps, precision=prec)
+    xbar = (s.pos * s.mass).sum(axis=1, keepdims=True)
+    M = s.mass.sum()
+    harm = -(M * s.pos - xbar) / eps ** 3  # the self pair adds 0 to this sum as well
+    ref, _ = oracle.forces(s.pos, s.mass, eps=eps)
+    # the limit holds up to the next term of the expansion, 1.5 |d|^2 / eps^2 ~ 5e-6 here
+    assert np.max(np.abs(ref - harm)) <= 1e-5 * np.max(np.abs(harm))
+    assert force_err(host(acc), ref) <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_empty_and_zero_step_calls(nb):
+    import torch
+    z3 = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    z1 = torch.zeros(0, dtype=torch.float64, device="cuda")
+    nb.step(z3, z3.clone(), z1, z3.clone(), 1e-3)
+    nb.rollout(z3, z3.clone(), z1, z3.clone(), 1e-3, 5, ckpt_every=2)
+    em = nb.energy_momentum(z3, z3, z1)
+    assert em.shape == (1, 5) and torch.all(em == 0)
+    # zero steps: the rollout leaves the state alone and the backward returns the seeds
+    s = inputs.plummer(500, 43)
+    pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+    acc, _ = nb.forces(pos, mass)
+    ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 0, ckpt_every=1)
+    assert np.array_equal(host(pos), s.pos) and np.array_equal(host(ckpt[0, :3]), s.pos)
+    gx, gv = dev(np.ones((3, 500))), dev(2 * np.ones((3, 500)))
+    a, b, c = nb.rollout_backward(mass, ckpt, gx, gv, 1e-3, 0, 1)
+    assert np.all(host(a) == 1) and np.all(host(b) == 2) and np.all(host(c) == 0)
+
+
+def test_single_particle_rollout_is_free_motion(nb):
+    """One particle feels no force: x(t) = x0 + v0 t exactly up to rounding."""
+    pos = dev(np.array([[0.1], [0.2], [0.3]]))
+    vel = dev(np.array([[1.0], [-2.0], [0.5]]))
+    mass = dev(np.array([1.0]))
+    acc, pot = nb.forces(pos, mass, want_pot=True)
+    assert np.all(host(acc) == 0) and np.all(host(pot) == 0)
+    nb.rollout(pos, vel, mass, acc, 1e-2, 100, precision="fp64")
+    np.testing.assert_allclose(host(pos)[:, 0], [1.1, -1.8, 0.8], rtol=1e-13)
