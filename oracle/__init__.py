@@ -15,6 +15,12 @@ half-step scheme of Sec. II-A read as kick-drift-kick):
     phi_i = -G sum_{j!=i} m_j s_ij^{-1/2}
     KE = 1/2 sum m|v|^2, PE = 1/2 sum m phi, P = sum m v
 
+The paper's own pair law, the Lennard-Jones gas of Eq. (1), with an optional
+softening w (r^2 -> r^2 + w^2; w = 0 is the plain law) and the reflective-wall
+boundary check applied after every drift:
+    V(r) = 4 e [(s/r)^12 - (s/r)^6],  a_i = (1/m_i) sum_j 24 e [2 s^12/r^13 - s^6/r^7] r_hat_ji
+    pot_i = (1/m_i) sum_{j!=i} V(r_ij)   (so PE = 1/2 sum m pot as for gravity)
+
 Arrays are numpy float64, SoA planes of shape (3, n).
 """
 from __future__ import annotations
@@ -67,6 +73,12 @@ def _load():
     lib.oracle_rollout_adjoint.restype = None
     lib.oracle_loss_msd.argtypes = [I64, P, P, P]
     lib.oracle_loss_msd.restype = D
+    lib.oracle_lj_forces.argtypes = [I64, P, P, D, D, D, P, P]
+    lib.oracle_lj_forces.restype = None
+    lib.oracle_lj_energy.argtypes = [I64, P, P, P, D, D, D, P]
+    lib.oracle_lj_energy.restype = None
+    lib.oracle_lj_kdk.argtypes = [I64, D, D, D, D, I64, P, P, P, P, P, P]
+    lib.oracle_lj_kdk.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -192,3 +204,42 @@ def forces_batched(pos, mass, offsets, G=1.0, eps=1e-2, want_pot=True):
         if want_pot:
             pot[a:b] = pi
     return acc, pot
+
+
+# ---- Lennard-Jones gas (the paper's pair law, Eq. (1)) ----
+
+def lj_forces(pos, mass, sigma=1.0, epsilon=1.0, soft=0.0, want_pot=True):
+    """Accelerations F_i / m_i (3, n) and potential per unit mass (1/m_i) sum_j V(r_ij)."""
+    mass = _f64(mass)
+    n = mass.shape[0]
+    pos = _f64(pos, (3, n))
+    acc = np.empty((3, n))
+    pot = np.empty(n) if want_pot else None
+    _load().oracle_lj_forces(n, _p(pos), _p(mass), sigma, epsilon, soft, _p(acc), _p(pot))
+    return acc, pot
+
+
+def lj_energy(pos, vel, mass, sigma=1.0, epsilon=1.0, soft=0.0):
+    """(KE, PE, Px, Py, Pz) of a Lennard-Jones system."""
+    mass = _f64(mass)
+    n = mass.shape[0]
+    out = np.empty(5)
+    _load().oracle_lj_energy(n, _p(_f64(pos, (3, n))), _p(_f64(vel, (3, n))), _p(mass), sigma, epsilon, soft,
+                             _p(out))
+    return out
+
+
+def lj_kdk(pos, vel, mass, dt, steps, sigma=1.0, epsilon=1.0, soft=0.0, box=None, want_energy=False):
+    """KDK steps with reflective walls of box = (lo[3], hi[3]) (None: open space)."""
+    mass = _f64(mass)
+    n = mass.shape[0]
+    pos = _f64(pos, (3, n)).copy()
+    vel = _f64(vel, (3, n)).copy()
+    lo = hi = None
+    if box is not None:
+        lo = _f64(box[0], (3,))
+        hi = _f64(box[1], (3,))
+    energy = np.empty((steps + 1, 5)) if want_energy else None
+    _load().oracle_lj_kdk(n, sigma, epsilon, soft, dt, steps, _p(pos), _p(vel), _p(mass), _p(lo), _p(hi),
+                          _p(energy))
+    return pos, vel, energy

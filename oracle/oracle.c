@@ -21,6 +21,8 @@
  *     phi_i = -G sum_{j != i} m_j s_ij^{-1/2}
  * The Verlet half-step scheme is read as kick-drift-kick leapfrog with force
  * reuse (one force evaluation per step plus one initial evaluation).
+ * The paper's own Lennard-Jones law (Eq. (1)) and its boundary check (read as
+ * reflective walls) are at the end of this file (oracle_lj_*).
  *
  * Layout: positions, velocities, accelerations are SoA planes [3][n]
  * (x plane, y plane, z plane), all double, host memory owned by the caller.
@@ -265,4 +267,101 @@ EXPORT int oracle_num_threads(void)
     }
 #endif
     return t;
+}
+
+/* ---------------------------------------------------------------------------
+ * Lennard-Jones gas: the paper's pair law, Eq. (1), V(r) = 4 e [(s/r)^12 - (s/r)^6]
+ * with F = -grad V = 24 e [2 s^12 / r^13 - s^6 / r^7] r_hat (repulsive for r < 2^{1/6} s).
+ * An optional softening w enters as r^2 -> r^2 + w^2 (w = 0 is the plain law).
+ * Acceleration a_i = F_i / m_i. The per-particle potential is returned per unit mass,
+ * pot_i = (1/m_i) sum_{j != i} V(r_ij), so that PE = 1/2 sum_i m_i pot_i = sum_{i<j} V(r_ij)
+ * (the same bookkeeping as the gravitational phi).
+ * --------------------------------------------------------------------------- */
+EXPORT void oracle_lj_forces(int64_t n, const double *pos, const double *mass, double sigma, double epsilon,
+                             double soft, double *acc, double *pot)
+{
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double fx = 0.0, fy = 0.0, fz = 0.0, v = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            /* separation from j to i: the force on i points along x_i - x_j when repulsive */
+            double rx = X[i] - X[j], ry = Y[i] - Y[j], rz = Z[i] - Z[j];
+            double r2 = rx * rx + ry * ry + rz * rz + soft * soft;
+            double sr2 = sigma * sigma / r2;
+            double sr6 = sr2 * sr2 * sr2;
+            double sr12 = sr6 * sr6;
+            /* |F| / r = 24 e (2 (s/r)^12 - (s/r)^6) / r^2 */
+            double f_over_r = 24.0 * epsilon * (2.0 * sr12 - sr6) / r2;
+            fx += f_over_r * rx;
+            fy += f_over_r * ry;
+            fz += f_over_r * rz;
+            v += 4.0 * epsilon * (sr12 - sr6);
+        }
+        acc[i] = fx / mass[i];
+        acc[n + i] = fy / mass[i];
+        acc[2 * n + i] = fz / mass[i];
+        if (pot) pot[i] = v / mass[i];
+    }
+}
+
+/* Reflective walls of the box [lo, hi]^3 (the paper's boundary check): a particle
+ * past a wall is mirrored back into the box and its velocity component flips. */
+static void reflect(int64_t n, double *pos, double *vel, const double *lo, const double *hi)
+{
+    for (int c = 0; c < 3; ++c)
+        for (int64_t i = 0; i < n; ++i) {
+            double x = pos[c * n + i];
+            if (x < lo[c]) {
+                pos[c * n + i] = 2.0 * lo[c] - x;
+                vel[c * n + i] = -vel[c * n + i];
+            } else if (x > hi[c]) {
+                pos[c * n + i] = 2.0 * hi[c] - x;
+                vel[c * n + i] = -vel[c * n + i];
+            }
+        }
+}
+
+/* Lennard-Jones energy of one system: out = {KE, PE, Px, Py, Pz}. */
+EXPORT void oracle_lj_energy(int64_t n, const double *pos, const double *vel, const double *mass, double sigma,
+                             double epsilon, double soft, double *out)
+{
+    double *pot = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *acc = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? 3 * n : 1));
+    oracle_lj_forces(n, pos, mass, sigma, epsilon, soft, acc, pot);
+    double ke = 0.0, pe = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+        ke += 0.5 * mass[i] * (vx * vx + vy * vy + vz * vz);
+        pe += 0.5 * mass[i] * pot[i];
+        px += mass[i] * vx;
+        py += mass[i] * vy;
+        pz += mass[i] * vz;
+    }
+    out[0] = ke; out[1] = pe; out[2] = px; out[3] = py; out[4] = pz;
+    free(pot);
+    free(acc);
+}
+
+/* Kick-drift-kick steps of the Lennard-Jones gas with the reflective-wall check after
+ * every drift (box given by lo[3], hi[3]; box == NULL: open space). energy nullable,
+ * [steps+1][5]. */
+EXPORT void oracle_lj_kdk(int64_t n, double sigma, double epsilon, double soft, double dt, int64_t steps,
+                          double *pos, double *vel, const double *mass, const double *lo, const double *hi,
+                          double *energy)
+{
+    double *acc = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? 3 * n : 1));
+    oracle_lj_forces(n, pos, mass, sigma, epsilon, soft, acc, NULL);
+    if (energy) oracle_lj_energy(n, pos, vel, mass, sigma, epsilon, soft, energy);
+    const double h = dt, hh = 0.5 * dt;
+    for (int64_t step = 0; step < steps; ++step) {
+        for (int64_t k = 0; k < 3 * n; ++k) vel[k] += hh * acc[k];
+        for (int64_t k = 0; k < 3 * n; ++k) pos[k] += h * vel[k];
+        if (lo && hi) reflect(n, pos, vel, lo, hi);
+        oracle_lj_forces(n, pos, mass, sigma, epsilon, soft, acc, NULL);
+        for (int64_t k = 0; k < 3 * n; ++k) vel[k] += hh * acc[k];
+        if (energy) oracle_lj_energy(n, pos, vel, mass, sigma, epsilon, soft, energy + 5 * (step + 1));
+    }
+    free(acc);
 }

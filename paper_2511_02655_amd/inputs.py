@@ -15,7 +15,9 @@ time step are silent), so the workloads are the standard gravitational ones:
   * two Plummer spheres on a collision course (mass 1/2 each, offsets +-2 in x,
     bulk velocities +-0.3 in y) and a Gaussian target cloud;
   * a regular N-gon ring and a Kepler pair (closed-form test cases);
-  * a batch of systems with log-uniform sizes, each a cube or a Plummer sphere.
+  * a batch of systems with log-uniform sizes, each a cube or a Plummer sphere;
+  * a Lennard-Jones gas for the paper's own pair law: a simple cubic lattice in a
+    box with reflective walls, Maxwell-Boltzmann velocities (reduced units).
 """
 from __future__ import annotations
 
@@ -166,6 +168,37 @@ def batched_mix(n_systems: int, seed: int, nmin: int = 64, nmax: int = 8192) -> 
                  np.ascontiguousarray(mass), kinds)
 
 
+@dataclass
+class Box:
+    lo: np.ndarray  # (3,)
+    hi: np.ndarray  # (3,)
+
+
+def lj_gas(n: int, seed: int, spacing: float = 1.5, temperature: float = 1.0, m: float = 1.0,
+           sigma: float = 1.0) -> tuple:
+    """Lennard-Jones gas on a simple cubic lattice, returned as (System, Box).
+
+    k = ceil(n^(1/3)) sites per edge at ((i + 1/2) a, (j + 1/2) a, (l + 1/2) a) with
+    a = spacing * sigma; the first n sites in x-fastest order are occupied (the top
+    layer is partly filled when n is not a cube). Box [0, k a]^3. Velocities are
+    Maxwell-Boltzmann at temperature kT = temperature (each component ~ N(0, kT/m)),
+    with the net momentum removed. Equal masses m."""
+    k = max(1, int(math.ceil(round(n ** (1.0 / 3.0), 9))))
+    while k ** 3 < n:
+        k += 1
+    a = spacing * sigma
+    idx = np.arange(n)
+    ix, iy, iz = idx % k, (idx // k) % k, idx // (k * k)
+    pos = (np.stack([ix, iy, iz]).astype(np.float64) + 0.5) * a
+    g = rng(seed)
+    vel = g.normal(0.0, math.sqrt(temperature / m), (3, n))
+    if n > 0:
+        vel -= vel.mean(axis=1, keepdims=True)
+    mass = np.full(n, float(m))
+    box = Box(np.zeros(3), np.full(3, k * a))
+    return System(np.ascontiguousarray(pos), np.ascontiguousarray(vel), mass), box
+
+
 # ---- the five reference workloads (sizes, softening, step, seeds) ----
 
 WORKLOADS = {
@@ -175,6 +208,10 @@ WORKLOADS = {
     "merger2x8k": dict(kind="two_spheres", n=16384, eps=1e-2, dt=1e-3, steps=200, ckpt=20,
                        seed=4, target_seed=5),
     "batch512": dict(kind="batch", n_systems=512, eps=1e-2, dt=1e-3, steps=50, seed=6),
+    # the paper's own experiment size: a Lennard-Jones gas of 10 000 particles, 2500 steps
+    # (sigma = epsilon = m = 1, lattice spacing 1.5 sigma, kT = 1, dt = 0.002 in reduced units)
+    "lj10k": dict(kind="lj", n=10000, sigma=1.0, epsilon=1.0, spacing=1.5, temperature=1.0, dt=2e-3,
+                  steps=2500, seed=7),
 }
 
 
@@ -189,4 +226,7 @@ def make(name: str, n: int | None = None):
         return two_spheres((n or w["n"]) // 2, w["seed"])
     if w["kind"] == "batch":
         return batched_mix(n or w["n_systems"], w["seed"])
+    if w["kind"] == "lj":
+        return lj_gas(n or w["n"], w["seed"], spacing=w["spacing"], temperature=w["temperature"],
+                      sigma=w["sigma"])
     raise KeyError(name)
