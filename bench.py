@@ -13,7 +13,12 @@ TFLOP/s FP32 vector peak), the force error of this run against the FP64 GPU path
 the CPU oracle, the adjoint and batched legs, and the CPU oracle timed on a bounded
 sample of the same workload.
 
+Also reported (not part of the timed step): the paper's own workload, a Lennard-Jones
+gas of 10 000 particles in a box with reflective walls run for 2500 KDK steps, with and
+without the per-step energy reduction, in FP64 and FP32 (the "lj10k" leg).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+       python bench.py --lj-only     (only the Lennard-Jones leg, printed as one JSON line)
 """
 import argparse
 import hashlib
@@ -28,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector, FLOP/s
 FLOP_PER_INTERACTION = 20.0   # forward pair-interaction convention
+LJ_FLOP_PER_INTERACTION = 22.0  # Lennard-Jones pair: 3 sub, 3 FMA (r^2), rcp, 2 mul (u^3), FMA, 2 mul, 3 FMA
 METRIC = "pair interactions/s (fwd & adjoint), % FP32 vector peak, at stated error"
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_02655_amd", "csrc", "nbody_kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_fp32c_plummer1m_traffic.json")
@@ -71,6 +77,7 @@ def main():
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--lj-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole system on a single MI355X "
@@ -89,6 +96,9 @@ def main():
     nb.lib()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.lj_only:
+        print(json.dumps({"lj10k": lj_leg(nb, torch, np, inputs, dev)}), flush=True)
+        return
 
     W = inputs.WORKLOADS["plummer1m"]
     n, eps, dt, ksteps = args.n, W["eps"], W["dt"], W["steps"]
@@ -200,6 +210,7 @@ def main():
         out["plummer64k"] = plummer64k_leg(nb, torch, np, inputs, dev)
         out["adjoint"] = adjoint_leg(nb, torch, np, inputs, dev)
         out["batched"] = batched_leg(nb, torch, np, inputs, dev)
+        out["lj10k"] = lj_leg(nb, torch, np, inputs, dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(np, s, eps)
     print(json.dumps(out), flush=True)
@@ -456,6 +467,84 @@ def batched_leg(nb, torch, np, inputs, dev):
     res["max_abs_pos_diff_persistent_vs_looped"] = d
     res["speedup_forward"] = res["looped"]["forward_ms"] / res["persistent"]["forward_ms"]
     res["speedup_backward"] = res["looped"]["backward_ms"] / res["persistent"]["backward_ms"]
+    return res
+
+
+def lj_leg(nb, torch, np, inputs, dev):
+    """The paper's experiment size with its own pair law: a Lennard-Jones gas of N = 10 000
+    (sigma = epsilon = m = 1, simple cubic lattice of spacing 1.5 sigma, kT = 1) in a box
+    with reflective walls, 2500 KDK steps of dt = 0.002, with the energy reduction after
+    every step ("with reduction") and without it. Also: the force pass alone (roofline) and
+    the first 20 steps against the CPU oracle."""
+    import oracle
+    log("lj10k leg")
+    W = inputs.WORKLOADS["lj10k"]
+    s, box = inputs.make("lj10k")
+    n, dt, steps = s.n, W["dt"], W["steps"]
+    bx = (box.lo, box.hi)
+    x0 = torch.from_numpy(s.pos).to(dev)
+    v0 = torch.from_numpy(s.vel).to(dev)
+    m = torch.from_numpy(s.mass).to(dev)
+    res = {"workload": "lj10k: Lennard-Jones gas N=%d (sigma=eps=m=1, sc lattice spacing 1.5, kT=1, seed %d) in a "
+                       "reflective box of edge %.1f; %d KDK steps dt=%g, no cutoff" % (n, W["seed"], box.hi[0], steps, dt),
+           "flop_per_interaction": LJ_FLOP_PER_INTERACTION}
+    for prec in ("fp64", "fp32", "fp32c"):
+        r = {}
+        pos, vel = x0.clone(), v0.clone()
+        acc, _ = nb.lj_forces(pos, m, precision=prec)
+        nb.lj_rollout(pos, vel, m, acc, dt, 20, box=bx, precision=prec)  # warm-up
+        for label, trace in (("no_reduction", False), ("with_reduction", True)):
+            pos.copy_(x0)
+            vel.copy_(v0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nb.lj_forces(pos, m, precision=prec, out_acc=acc)
+            tr = nb.lj_rollout(pos, vel, m, acc, dt, steps, box=bx, energy_trace=trace, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            r[label] = {"seconds": ms * 1e-3, "ms_per_step": ms / steps,
+                        "interactions_per_s": (steps + 1) * float(n) * n / (ms * 1e-3)}
+            if trace:
+                t = tr.cpu().numpy()[:, 0, :]
+                E = t[:, 0] + t[:, 1]
+                r[label]["energy_rel_drift_max"] = float(np.max(np.abs(E - E[0])) / abs(t[0, 0]))
+                r[label]["in_box"] = bool(torch.all(pos >= torch.from_numpy(box.lo).to(dev)[:, None]).item()
+                                          and torch.all(pos <= torch.from_numpy(box.hi).to(dev)[:, None]).item())
+        # the force pass alone: 200 back-to-back launches on the current stream
+        reps = 200
+        pot = torch.empty(n, dtype=torch.float64, device=dev)
+        for want_pot in (False, True):
+            nb.lj_forces(x0, m, precision=prec, out_acc=acc, want_pot=want_pot, out_pot=pot if want_pot else None)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                nb.lj_forces(x0, m, precision=prec, out_acc=acc, want_pot=want_pot, out_pot=pot if want_pot else None)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            flops = LJ_FLOP_PER_INTERACTION * float(n) * n / (ms * 1e-3)
+            r["force_call_us" + ("_with_potential" if want_pot else "")] = ms * 1e3
+            r["force_frac_fp32_peak" + ("_with_potential" if want_pot else "")] = flops / PEAK_FP32
+        vid, jsplit = nb.tile_lookup("force", prec, n)
+        r["tile"] = "%s, j_split=%d" % (nb.tile_variants("force", prec)[vid], jsplit)
+        res[prec] = r
+    # parity: 20 steps against the oracle (FP64 and compensated FP32)
+    k = 20
+    t0 = time.perf_counter()
+    pr, vr, _ = oracle.lj_kdk(s.pos, s.vel, s.mass, dt, k, box=bx)
+    res["oracle_20_steps_s"] = time.perf_counter() - t0
+    for prec in ("fp64", "fp32c"):
+        pos, vel = x0.clone(), v0.clone()
+        acc, _ = nb.lj_forces(pos, m, precision=prec)
+        nb.lj_rollout(pos, vel, m, acc, dt, k, box=bx, precision=prec)
+        res[prec]["max_abs_pos_err_vs_oracle_20_steps"] = float(np.max(np.abs(pos.cpu().numpy() - pr)))
+        res[prec]["max_abs_vel_err_vs_oracle_20_steps"] = float(np.max(np.abs(vel.cpu().numpy() - vr)))
+    res["paper_context"] = ("the paper reports 19.02 s (best, with the energy reduction) and 8.96 s (best, "
+                            "without) for this size on four A100 GPUs of one node; its box, lattice and dt are "
+                            "not stated, so the workloads match in N and steps only")
     return res
 
 

@@ -15,6 +15,8 @@
  *   force reuse. Energy/momentum per system: KE = 1/2 sum m|v|^2,
  *   PE = 1/2 sum m phi, P = sum m v (all reduced in FP64, deterministically,
  *   without atomics).
+ *   The paper's own Lennard-Jones gas (Eq. (1)) runs through the same tile
+ *   engine: nbody_lj_forces / nbody_lj_rollout at the end of this header.
  *
  * Conventions (all entry points):
  *   - Array pointers are DEVICE pointers owned by the caller, unless a comment
@@ -99,7 +101,8 @@ typedef struct {
 /* Bytes of workspace any call below needs for n particles (in cfg's systems).
  * For nbody_rollout_backward pass its ckpt_every (>= 1; the size grows with it);
  * pass 0 when no backward pass is planned. `steps` must be >= 0. The size depends
- * on cfg->precision, cfg->n_systems/offsets and the tile table.
+ * on cfg->precision, cfg->n_systems/offsets and the tile table (not on G, eps or
+ * the pair law: the same size serves the Lennard-Jones calls).
  * Returns NBODY_OK and writes *bytes. */
 int nbody_workspace_size(const nbody_config *cfg, int64_t n, int64_t steps, int64_t ckpt_every,
                          size_t *bytes);
@@ -136,8 +139,9 @@ int nbody_rollout(const nbody_config *cfg, int64_t n, double dt, int64_t steps, 
                   double *energy_trace);
 
 /* Energy and linear momentum of every system (the energy reduction of Sec. V).
- *   pot  nullable: the per-particle potential from nbody_forces; when NULL it is
- *        computed here with one force pass at cfg->precision.
+ *   pot  nullable: the per-particle potential from nbody_forces (or, for the
+ *        Lennard-Jones gas, from nbody_lj_forces); when NULL it is computed here
+ *        with one gravity force pass at cfg->precision.
  *   out  [n_systems][5] double: KE, PE, Px, Py, Pz. */
 int nbody_energy_momentum(const nbody_config *cfg, int64_t n, const double *pos, const double *vel,
                           const double *mass, const double *pot, double *out);
@@ -157,6 +161,44 @@ int nbody_rollout_backward(const nbody_config *cfg, int64_t n, double dt, int64_
                            int64_t ckpt_every, const double *mass, const double *ckpt,
                            const double *gpos_final, const double *gvel_final, double *gpos0,
                            double *gvel0, double *gmass);
+
+/* ---- the paper's pair law: Lennard-Jones gas (Eq. (1)) ----
+ *
+ *   V(r) = 4 epsilon [(sigma/r)^12 - (sigma/r)^6],
+ *   F_i  = sum_{j != i} 24 epsilon [2 sigma^12 / r^13 - sigma^6 / r^7] r_hat_ji
+ *          (r_hat_ji: unit vector from x_j to x_i; repulsive below 2^{1/6} sigma),
+ *   a_i  = F_i / m_i,   pot_i = (1/m_i) sum_{j != i} V(r_ij)
+ * so that PE = 1/2 sum m pot exactly as for gravity (nbody_energy_momentum with
+ * this pot gives the gas's energy). An optional softening w replaces r^2 by
+ * r^2 + w^2 (w = 0 is the plain law; then no two particles may coincide, and
+ * masses must be nonzero). No cutoff: every pair interacts, as in the paper.
+ * All nbody_config fields apply except G and eps, which these calls ignore. */
+typedef struct {
+  double sigma;      /* > 0 */
+  double epsilon;    /* well depth, finite */
+  double soft;       /* >= 0 (FP32 modes: 0 or soft/sigma >= 1e-10) */
+  int32_t walls;     /* 1: reflective walls at lo/hi, 0: open space */
+  int32_t reserved;  /* must be 0 */
+  double lo[3];      /* box corners when walls == 1: finite, lo[c] < hi[c]; */
+  double hi[3];      /* initial positions should lie inside the box */
+} nbody_lj_params;
+
+/* Lennard-Jones accelerations and (pot != NULL) per-particle potentials of every
+ * system; arguments as in nbody_forces, mass [n] > 0. Pair arithmetic at
+ * cfg->precision on coordinates scaled by 1/sigma; sums and constants in FP64. */
+int nbody_lj_forces(const nbody_config *cfg, const nbody_lj_params *lj, int64_t n, const double *pos,
+                    const double *mass, double *acc, double *pot);
+
+/* `steps` KDK steps of the Lennard-Jones gas (steps >= 0), state in place, with the
+ * boundary check after every drift when lj->walls: a coordinate that left the box
+ * is mirrored back in (x -> 2 lo - x or 2 hi - x) and that velocity component
+ * changes sign (elastic walls).
+ *   acc in: a(x_0) (from nbody_lj_forces), out: a(x_steps)
+ *   energy_trace nullable, [steps + 1][n_systems][5] doubles as in nbody_rollout
+ *         (the energy reduction of every step, fused behind its force pass). */
+int nbody_lj_rollout(const nbody_config *cfg, const nbody_lj_params *lj, int64_t n, double dt,
+                     int64_t steps, double *pos, double *vel, const double *mass, double *acc,
+                     double *energy_trace);
 
 /* ---- tile table (written by the autotuner; built-in defaults otherwise) ---- */
 

@@ -30,7 +30,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPAC
 
 EXPORTED = ("nbody_abi_version", "nbody_last_error", "nbody_workspace_size", "nbody_forces", "nbody_step",
             "nbody_rollout", "nbody_energy_momentum", "nbody_rollout_backward", "nbody_set_tile_table",
-            "nbody_tile_variants", "nbody_tile_lookup")
+            "nbody_tile_variants", "nbody_tile_lookup", "nbody_lj_forces", "nbody_lj_rollout")
 
 
 class NBodyError(RuntimeError):
@@ -52,6 +52,18 @@ class NBodyConfig(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("flags", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+    ]
+
+
+class LJParams(ctypes.Structure):
+    _fields_ = [
+        ("sigma", ctypes.c_double),
+        ("epsilon", ctypes.c_double),
+        ("soft", ctypes.c_double),
+        ("walls", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
     ]
 
 
@@ -94,6 +106,8 @@ def lib():
         "nbody_tile_variants": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
         "nbody_tile_lookup": ([ctypes.c_int32, ctypes.c_int32, I64, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "nbody_lj_forces": ([C, ctypes.POINTER(LJParams), I64, P, P, P, P], ctypes.c_int),
+        "nbody_lj_rollout": ([C, ctypes.POINTER(LJParams), I64, D, I64, P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -319,6 +333,56 @@ def rollout_backward(mass, ckpt, gpos_final, gvel_final, dt, steps, ckpt_every, 
                                         _dptr(gvel_final, "gvel_final", (3, n)), _dptr(gx, "gpos0"),
                                         _dptr(gv, "gvel0"), _dptr(gm, "gmass")))
     return gx, gv, gm
+
+
+# ------------------------------------------------------------------ Lennard-Jones gas (Eq. (1))
+
+def lj_params(sigma=1.0, epsilon=1.0, soft=0.0, box=None) -> LJParams:
+    """Pair-law parameters; box = (lo[3], hi[3]) turns on the reflective walls."""
+    p = LJParams()
+    p.sigma, p.epsilon, p.soft = float(sigma), float(epsilon), float(soft)
+    p.reserved = 0
+    if box is not None:
+        p.walls = 1
+        for c in range(3):
+            p.lo[c] = float(box[0][c])
+            p.hi[c] = float(box[1][c])
+    else:
+        p.walls = 0
+    return p
+
+
+def lj_forces(pos, mass, *, sigma=1.0, epsilon=1.0, soft=0.0, precision="fp32c", want_pot=False, offsets=None,
+              flags=0, out_acc=None, out_pot=None, stream=None):
+    """Lennard-Jones accelerations F_i/m_i (3, n) and optionally potentials per unit mass (n,)."""
+    torch = _torch()
+    n = _n_of(mass)
+    c = _Cfg(precision, 1.0, 1.0, offsets, flags, stream)
+    c.workspace(n, device=mass.device)
+    lj = lj_params(sigma, epsilon, soft)
+    acc = out_acc if out_acc is not None else torch.empty((3, n), dtype=torch.float64, device=mass.device)
+    pot = (out_pot if out_pot is not None else torch.empty(n, dtype=torch.float64, device=mass.device)) \
+        if want_pot else None
+    _check(lib().nbody_lj_forces(ctypes.byref(c.cfg), ctypes.byref(lj), n, _dptr(pos, "pos", (3, n)),
+                                 _dptr(mass, "mass"), _dptr(acc, "acc", (3, n)), _dptr(pot, "pot", (n,))))
+    return acc, pot
+
+
+def lj_rollout(pos, vel, mass, acc, dt, steps, *, sigma=1.0, epsilon=1.0, soft=0.0, box=None,
+               energy_trace=False, precision="fp32c", offsets=None, flags=0, stream=None):
+    """`steps` KDK steps of the Lennard-Jones gas in place (reflective walls when box is
+    given). Returns the energy trace (steps+1, S, 5) or None."""
+    torch = _torch()
+    n = _n_of(mass)
+    c = _Cfg(precision, 1.0, 1.0, offsets, flags, stream)
+    c.workspace(n, device=mass.device)
+    lj = lj_params(sigma, epsilon, soft, box)
+    trace = torch.empty((steps + 1, c.cfg.n_systems, 5), dtype=torch.float64, device=mass.device) \
+        if energy_trace else None
+    _check(lib().nbody_lj_rollout(ctypes.byref(c.cfg), ctypes.byref(lj), n, float(dt), int(steps),
+                                  _dptr(pos, "pos", (3, n)), _dptr(vel, "vel", (3, n)), _dptr(mass, "mass"),
+                                  _dptr(acc, "acc", (3, n)), _dptr(trace, "energy_trace")))
+    return trace
 
 
 from .autograd import NBodyRollout, rollout_fn  # noqa: E402,F401

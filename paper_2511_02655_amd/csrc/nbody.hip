@@ -66,16 +66,16 @@ using AdjFn = void (*)(dim3, hipStream_t, const void* jadj, int64_t i0, int64_t 
 using AdjBatchedFn = void (*)(dim3, hipStream_t, const void* jadj, const WorkUnit* units, int32_t n_units,
                               int32_t* counter, double eps2, const AdjOut&);
 
-template <typename T, int BS, int I, int TJ, bool POT, int MODE>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
 void launch_force(dim3 g, hipStream_t st, const void* jarr, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
                   int64_t jchunk, double eps2, const ForceOut& o) {
-  hipLaunchKernelGGL((force_kernel<T, BS, I, TJ, POT, MODE>), g, dim3(BS), 0, st,
+  hipLaunchKernelGGL((force_kernel<T, BS, I, TJ, POT, MODE, LAW>), g, dim3(BS), 0, st,
                      (const typename Vec4<T>::type*)jarr, i0, i1, j0, j1, jchunk, (T)eps2, o);
 }
-template <typename T, int BS, int I, int TJ, bool POT, int MODE>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
 void launch_force_batched(dim3 g, hipStream_t st, const void* jarr, const WorkUnit* units, int32_t n_units,
                           int32_t* counter, double eps2, const ForceOut& o) {
-  hipLaunchKernelGGL((force_batched_kernel<T, BS, I, TJ, POT, MODE>), g, dim3(BS), 0, st,
+  hipLaunchKernelGGL((force_batched_kernel<T, BS, I, TJ, POT, MODE, LAW>), g, dim3(BS), 0, st,
                      (const typename Vec4<T>::type*)jarr, units, n_units, counter, (T)eps2, o);
 }
 template <typename T, int BS, int I, int TJ, bool COMP>
@@ -92,16 +92,16 @@ void launch_adj_batched(dim3 g, hipStream_t st, const void* jadj, const WorkUnit
 }
 
 // Kernel pointers for occupancy queries of the persistent kernels.
-template <typename T, int BS, int I, int TJ, bool POT, int MODE>
-const void* force_batched_ptr() { return (const void*)&force_batched_kernel<T, BS, I, TJ, POT, MODE>; }
+template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
+const void* force_batched_ptr() { return (const void*)&force_batched_kernel<T, BS, I, TJ, POT, MODE, LAW>; }
 template <typename T, int BS, int I, int TJ, bool COMP>
 const void* adj_batched_ptr() { return (const void*)&adjoint_batched_kernel<T, BS, I, TJ, COMP>; }
 
 struct ForceVariant {
   int bs, i, tj;
-  ForceFn fn[2][3];               // [pot][mode]: plain, compensated, double-float separations
-  ForceBatchedFn bfn[2][3];
-  const void* (*bptr[2][3])();
+  ForceFn fn[2][2][3];            // [law][pot][mode]: plain, compensated, double-float separations
+  ForceBatchedFn bfn[2][2][3];
+  const void* (*bptr[2][2][3])();
 };
 struct AdjVariant {
   int bs, i, tj;
@@ -110,24 +110,23 @@ struct AdjVariant {
   const void* (*bptr[2])();
 };
 
-#define FV32_MODES(F, BS, I, TJ, POT) \
-  { F<float, BS, I, TJ, POT, 0>, F<float, BS, I, TJ, POT, 1>, F<float, BS, I, TJ, POT, 2> }
+#define FV32_MODES(F, BS, I, TJ, POT, LAW) \
+  { F<float, BS, I, TJ, POT, 0, LAW>, F<float, BS, I, TJ, POT, 1, LAW>, F<float, BS, I, TJ, POT, 2, LAW> }
+#define FV32_LAW(F, BS, I, TJ, LAW) \
+  { FV32_MODES(F, BS, I, TJ, false, LAW), FV32_MODES(F, BS, I, TJ, true, LAW) }
 #define FV32(BS, I, TJ)                                                                                    \
   ForceVariant {                                                                                           \
-    BS, I, TJ,                                                                                             \
-        {FV32_MODES(launch_force, BS, I, TJ, false), FV32_MODES(launch_force, BS, I, TJ, true)},           \
-        {FV32_MODES(launch_force_batched, BS, I, TJ, false), FV32_MODES(launch_force_batched, BS, I, TJ, true)}, \
-        {FV32_MODES(force_batched_ptr, BS, I, TJ, false), FV32_MODES(force_batched_ptr, BS, I, TJ, true)} \
+    BS, I, TJ, {FV32_LAW(launch_force, BS, I, TJ, 0), FV32_LAW(launch_force, BS, I, TJ, 1)},              \
+        {FV32_LAW(launch_force_batched, BS, I, TJ, 0), FV32_LAW(launch_force_batched, BS, I, TJ, 1)},     \
+        {FV32_LAW(force_batched_ptr, BS, I, TJ, 0), FV32_LAW(force_batched_ptr, BS, I, TJ, 1)}            \
   }
+#define FV64_LAW(F, BS, I, TJ, LAW) \
+  { {F<double, BS, I, TJ, false, 0, LAW>, nullptr, nullptr}, {F<double, BS, I, TJ, true, 0, LAW>, nullptr, nullptr} }
 #define FV64(BS, I, TJ)                                                                                    \
   ForceVariant {                                                                                           \
-    BS, I, TJ,                                                                                             \
-        {{launch_force<double, BS, I, TJ, false, 0>, nullptr, nullptr},                                   \
-         {launch_force<double, BS, I, TJ, true, 0>, nullptr, nullptr}},                                   \
-        {{launch_force_batched<double, BS, I, TJ, false, 0>, nullptr, nullptr},                           \
-         {launch_force_batched<double, BS, I, TJ, true, 0>, nullptr, nullptr}},                           \
-        {{force_batched_ptr<double, BS, I, TJ, false, 0>, nullptr, nullptr},                              \
-         {force_batched_ptr<double, BS, I, TJ, true, 0>, nullptr, nullptr}}                               \
+    BS, I, TJ, {FV64_LAW(launch_force, BS, I, TJ, 0), FV64_LAW(launch_force, BS, I, TJ, 1)},              \
+        {FV64_LAW(launch_force_batched, BS, I, TJ, 0), FV64_LAW(launch_force_batched, BS, I, TJ, 1)},     \
+        {FV64_LAW(force_batched_ptr, BS, I, TJ, 0), FV64_LAW(force_batched_ptr, BS, I, TJ, 1)}            \
   }
 #define AV32(BS, I, TJ)                                                                                    \
   AdjVariant {                                                                                             \
@@ -151,18 +150,20 @@ const AdjVariant kAdj64[] = {AV64(256, 1, 256), AV64(128, 1, 128), AV64(64, 1, 6
 // Symmetric FP32 force variants (each pair once), indices kNumForce32 + k in the
 // FORCE tile table.
 using SymFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part);
-template <int W, int I, bool POT, int MODE, int ROT>
+template <int W, int I, bool POT, int MODE, int ROT, int LAW>
 void launch_sym(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part) {
-  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE, ROT>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
+  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE, ROT, LAW>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
 }
 struct SymVariant {
-  int w, i, rot;   // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
-  SymFn fn[2][3];  // [pot][mode]
+  int w, i, rot;      // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
+  SymFn fn[2][2][3];  // [law][pot][mode]
 };
+#define SV32_POT(W, I, R, POT, LAW) \
+  { launch_sym<W, I, POT, 0, R, LAW>, launch_sym<W, I, POT, 1, R, LAW>, launch_sym<W, I, POT, 2, R, LAW> }
 #define SV32(W, I, R)                                                                                     \
   SymVariant {                                                                                            \
-    W, I, R, {{launch_sym<W, I, false, 0, R>, launch_sym<W, I, false, 1, R>, launch_sym<W, I, false, 2, R>}, \
-              {launch_sym<W, I, true, 0, R>, launch_sym<W, I, true, 1, R>, launch_sym<W, I, true, 2, R>}}    \
+    W, I, R, {{SV32_POT(W, I, R, false, 0), SV32_POT(W, I, R, true, 0)},                                   \
+              {SV32_POT(W, I, R, false, 1), SV32_POT(W, I, R, true, 1)}}                                   \
   }
 const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4, 2, 0), SV32(2, 4, 0),
                              SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1), SV32(2, 4, 1),
@@ -305,7 +306,9 @@ struct Systems {
   int64_t max_n;
 };
 
-int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys) {
+// law_checks: validate G and eps (gravity calls); the workspace size and the
+// Lennard-Jones calls do not use them.
+int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys, bool law_checks = true) {
   if (!cfg) return fail(NBODY_ERR_INVALID_ARG, "cfg is NULL");
   if (cfg->abi_version != NBODY_ABI_VERSION)
     return fail(NBODY_ERR_INVALID_ARG, "abi_version %d does not match library ABI %d", cfg->abi_version,
@@ -313,11 +316,13 @@ int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys) {
   if (cfg->precision != NBODY_FP64 && cfg->precision != NBODY_FP32 && cfg->precision != NBODY_FP32_COMP &&
       cfg->precision != NBODY_FP32_DS)
     return fail(NBODY_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
-  if (!std::isfinite(cfg->G)) return fail(NBODY_ERR_INVALID_ARG, "G must be finite");
-  if (!(cfg->eps > 0.0) || !std::isfinite(cfg->eps))
-    return fail(NBODY_ERR_INVALID_ARG, "eps must be finite and > 0 (got %g)", cfg->eps);
-  if (cfg->precision != NBODY_FP64 && cfg->eps < 1e-10)
-    return fail(NBODY_ERR_INVALID_ARG, "eps must be >= 1e-10 for the FP32 modes (got %g)", cfg->eps);
+  if (law_checks) {
+    if (!std::isfinite(cfg->G)) return fail(NBODY_ERR_INVALID_ARG, "G must be finite");
+    if (!(cfg->eps > 0.0) || !std::isfinite(cfg->eps))
+      return fail(NBODY_ERR_INVALID_ARG, "eps must be finite and > 0 (got %g)", cfg->eps);
+    if (cfg->precision != NBODY_FP64 && cfg->eps < 1e-10)
+      return fail(NBODY_ERR_INVALID_ARG, "eps must be >= 1e-10 for the FP32 modes (got %g)", cfg->eps);
+  }
   if (cfg->reserved != 0) return fail(NBODY_ERR_INVALID_ARG, "reserved must be 0");
   if (cfg->flags & ~NBODY_FLAG_LOOP_SYSTEMS) return fail(NBODY_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
   if (n < 0) return fail(NBODY_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)n);
@@ -495,6 +500,24 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
   return NBODY_OK;
 }
 
+int check_lj(const nbody_config* cfg, const nbody_lj_params* lj) {
+  if (!lj) return fail(NBODY_ERR_INVALID_ARG, "lj is NULL");
+  if (!(lj->sigma > 0.0) || !std::isfinite(lj->sigma))
+    return fail(NBODY_ERR_INVALID_ARG, "sigma must be finite and > 0 (got %g)", lj->sigma);
+  if (!std::isfinite(lj->epsilon)) return fail(NBODY_ERR_INVALID_ARG, "epsilon must be finite");
+  if (!(lj->soft >= 0.0) || !std::isfinite(lj->soft))
+    return fail(NBODY_ERR_INVALID_ARG, "soft must be finite and >= 0 (got %g)", lj->soft);
+  if (cfg && cfg->precision != NBODY_FP64 && lj->soft > 0.0 && lj->soft / lj->sigma < 1e-10)
+    return fail(NBODY_ERR_INVALID_ARG, "soft/sigma must be 0 or >= 1e-10 for the FP32 modes");
+  if (lj->reserved != 0) return fail(NBODY_ERR_INVALID_ARG, "lj reserved must be 0");
+  if (lj->walls != 0 && lj->walls != 1) return fail(NBODY_ERR_INVALID_ARG, "walls must be 0 or 1");
+  if (lj->walls)
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(lj->lo[c]) || !std::isfinite(lj->hi[c]) || !(lj->lo[c] < lj->hi[c]))
+        return fail(NBODY_ERR_INVALID_ARG, "box: need finite lo[%d] < hi[%d]", c, c);
+  return NBODY_OK;
+}
+
 struct Ctx {
   const nbody_config* cfg;
   Systems sys;
@@ -504,10 +527,43 @@ struct Ctx {
   Plan plan;
   UnitSet uf, ua;
   bool bat, loop;
+  // pair law: LAW_GRAV, or LAW_LJ with coordinates staged in units of sigma
+  int law = LAW_GRAV;
+  double xs = 1.0;    // staging scale of the coordinates
+  double eps2 = 0.0;  // softening^2 in staged units
+  LawScale ls{};      // constants applied to the raw pair sums (mdiv set per call)
+  Walls wl{};
+
+  LawScale ls_at(int64_t b) const {
+    LawScale r = ls;
+    if (r.mdiv) r.mdiv += b;
+    return r;
+  }
 };
 
-int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsigned need) {
-  TRY(check_cfg(cfg, n, c.sys));
+int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsigned need,
+            const nbody_lj_params* lj = nullptr) {
+  TRY(check_cfg(cfg, n, c.sys, lj == nullptr));
+  if (lj) {
+    TRY(check_lj(cfg, lj));
+    c.law = LAW_LJ;
+    c.xs = 1.0 / lj->sigma;
+    c.eps2 = (lj->soft / lj->sigma) * (lj->soft / lj->sigma);
+    c.ls.ca = 24.0 * lj->epsilon / lj->sigma;
+    c.ls.cp = 4.0 * lj->epsilon;
+    c.wl.on = lj->walls;
+    for (int k = 0; k < 3; ++k) {
+      c.wl.lo[k] = lj->lo[k];
+      c.wl.hi[k] = lj->hi[k];
+    }
+  } else {
+    c.law = LAW_GRAV;
+    c.xs = 1.0;
+    c.eps2 = cfg->eps * cfg->eps;
+    c.ls.ca = c.ls.cp = cfg->G;
+    c.ls.mdiv = nullptr;
+    c.wl.on = 0;
+  }
   c.cfg = cfg;
   c.n = n;
   c.st = (hipStream_t)cfg->stream;
@@ -591,11 +647,11 @@ int stage(Ctx& c, const double* pos, const double* mass) {
   TRY(check_jbuf(c, jvec_bytes(c.cfg->precision), "stage_j"));
   void* j = c.ws + c.plan.off_jbuf;
   if (is_fp64(c.cfg->precision))
-    hipLaunchKernelGGL((stage_j<double, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (D4*)j);
+    hipLaunchKernelGGL((stage_j<double, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, c.xs, (D4*)j);
   else if (is_ds(c.cfg->precision))
-    hipLaunchKernelGGL((stage_j<float, true>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (float4*)j);
+    hipLaunchKernelGGL((stage_j<float, true>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, c.xs, (float4*)j);
   else
-    hipLaunchKernelGGL((stage_j<float, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, (float4*)j);
+    hipLaunchKernelGGL((stage_j<float, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, pos, mass, c.xs, (float4*)j);
   LAUNCH_CHECK("stage_j");
   return NBODY_OK;
 }
@@ -605,13 +661,13 @@ int kick_drift(Ctx& c, double dt, double* pos, double* vel, const double* acc, c
   void* j = c.ws + c.plan.off_jbuf;
   if (is_fp64(c.cfg->precision))
     hipLaunchKernelGGL((kick_drift_stage<double, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel,
-                       acc, mass, (D4*)j);
+                       acc, mass, c.xs, c.wl, (D4*)j);
   else if (is_ds(c.cfg->precision))
     hipLaunchKernelGGL((kick_drift_stage<float, true>), grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel,
-                       acc, mass, (float4*)j);
+                       acc, mass, c.xs, c.wl, (float4*)j);
   else
     hipLaunchKernelGGL((kick_drift_stage<float, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel,
-                       acc, mass, (float4*)j);
+                       acc, mass, c.xs, c.wl, (float4*)j);
   LAUNCH_CHECK("kick_drift_stage");
   return NBODY_OK;
 }
@@ -630,7 +686,8 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
   const int prec = c.cfg->precision;
   const int mode = force_mode(prec);
   const int pot_on = pot != nullptr;
-  const double eps2 = c.cfg->eps * c.cfg->eps;
+  const int law = c.law;
+  const double eps2 = c.eps2;
   const void* jarr = c.ws + c.plan.off_jbuf;
   double* part = (double*)(c.ws + c.plan.off_part);
   const int64_t n = c.n;
@@ -646,9 +703,10 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
       if (tiles > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many symmetric tiles");
       TRY(check_part(c, (size_t)nb * 4 * ns * sizeof(float), "force_sym_kernel"));
       float* pf = (float*)(c.ws + c.plan.off_part);
-      sv.fn[pot_on][mode](dim3((unsigned)tiles), c.st, (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b, ns, (int32_t)nb, (float)eps2, pf);
+      sv.fn[law][pot_on][mode](dim3((unsigned)tiles), c.st, (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b, ns,
+                               (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("force_sym_kernel");
-      hipLaunchKernelGGL(reduce_sym, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)nb, (const float*)pf, c.cfg->G,
+      hipLaunchKernelGGL(reduce_sym, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)nb, (const float*)pf, c.ls_at(b),
                          acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh);
       LAUNCH_CHECK("reduce_sym");
       return NBODY_OK;
@@ -657,7 +715,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
     split_geometry(t, ns, S, jc);
     const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
     ForceOut o{};
-    o.G = c.cfg->G;
+    o.ls = c.ls;  // direct stores index particles globally (i in [b, e))
     o.n_plane = n;
     dim3 g((unsigned)cdiv(ns, (int64_t)t.bs * t.i), (unsigned)S);
     if (S == 1) {
@@ -666,11 +724,11 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
       TRY(check_part(c, (size_t)S * 4 * n * sizeof(double), "force_kernel"));
       o.part = part;
     }
-    fv.fn[pot_on][mode](g, c.st, jarr, b, e, b, e, jc, eps2, o);
+    fv.fn[law][pot_on][mode](g, c.st, jarr, b, e, b, e, jc, eps2, o);
     LAUNCH_CHECK("force_kernel");
     if (S > 1) {
       // reduce only this system's particle range: offset pointers into the planes
-      hipLaunchKernelGGL(reduce_splits, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)S, part + b, c.cfg->G,
+      hipLaunchKernelGGL(reduce_splits, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)S, part + b, c.ls_at(b),
                          acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, (int64_t)0,
                          (const int64_t*)nullptr, (const int32_t*)nullptr);
       LAUNCH_CHECK("reduce_splits");
@@ -691,15 +749,15 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)2, 0);
   LAUNCH_CHECK("fill_i32");
   unsigned grid;
-  persistent_grid(fv.bptr[pot_on][mode](), t.bs, c.plan.n_units_force, grid);
+  persistent_grid(fv.bptr[law][pot_on][mode](), t.bs, c.plan.n_units_force, grid);
   ForceOut o{};
-  o.G = c.cfg->G;
+  o.ls = c.ls;
   o.n_plane = n;
   o.part = part;
-  fv.bfn[pot_on][mode](dim3(grid), c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
-                       (int32_t)c.plan.n_units_force, counter, eps2, o);
+  fv.bfn[law][pot_on][mode](dim3(grid), c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
+                            (int32_t)c.plan.n_units_force, counter, eps2, o);
   LAUNCH_CHECK("force_batched_kernel");
-  hipLaunchKernelGGL(reduce_splits, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, c.cfg->G, acc, pot, vel, hh,
+  hipLaunchKernelGGL(reduce_splits, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, c.ls, acc, pot, vel, hh,
                      c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit));
   LAUNCH_CHECK("reduce_splits");
   return NBODY_OK;
@@ -839,7 +897,7 @@ __attribute__((visibility("default"))) int nbody_workspace_size(const nbody_conf
   g_err.clear();
   if (!bytes) return fail(NBODY_ERR_INVALID_ARG, "bytes is NULL");
   Systems sys;
-  TRY(check_cfg(cfg, n, sys));
+  TRY(check_cfg(cfg, n, sys, false));  // the size does not depend on the pair law's constants
   if (steps < 0) return fail(NBODY_ERR_INVALID_ARG, "steps must be >= 0");
   if (ckpt_every < 0) return fail(NBODY_ERR_INVALID_ARG, "ckpt_every must be >= 0");
   Plan p;
@@ -875,13 +933,13 @@ __attribute__((visibility("default"))) int nbody_step(const nbody_config* cfg, i
   return force_pass(c, acc, pot, vel, 0.5 * dt);
 }
 
-__attribute__((visibility("default"))) int nbody_rollout(const nbody_config* cfg, int64_t n, double dt, int64_t steps,
-                                                         int64_t ckpt_every, double* pos, double* vel,
-                                                         const double* mass, double* acc, double* ckpt,
-                                                         double* energy_trace) {
-  g_err.clear();
-  Ctx c;
-  TRY(prepare(c, cfg, n, 1, NEED_FORCE | NEED_ROLLOUT));
+}  // extern "C"
+
+namespace {
+
+// The KDK loop shared by both pair laws (c prepared with NEED_FORCE | NEED_ROLLOUT).
+int rollout_impl(Ctx& c, int64_t n, double dt, int64_t steps, int64_t ckpt_every, double* pos, double* vel,
+                 const double* mass, double* acc, double* ckpt, double* energy_trace) {
   if (!std::isfinite(dt)) return fail(NBODY_ERR_INVALID_ARG, "dt must be finite");
   if (steps < 0) return fail(NBODY_ERR_INVALID_ARG, "steps must be >= 0");
   if (ckpt && ckpt_every < 1) return fail(NBODY_ERR_INVALID_ARG, "ckpt_every must be >= 1 when ckpt is given");
@@ -912,6 +970,45 @@ __attribute__((visibility("default"))) int nbody_rollout(const nbody_config* cfg
     }
   }
   return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+__attribute__((visibility("default"))) int nbody_rollout(const nbody_config* cfg, int64_t n, double dt, int64_t steps,
+                                                         int64_t ckpt_every, double* pos, double* vel,
+                                                         const double* mass, double* acc, double* ckpt,
+                                                         double* energy_trace) {
+  g_err.clear();
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_FORCE | NEED_ROLLOUT));
+  return rollout_impl(c, n, dt, steps, ckpt_every, pos, vel, mass, acc, ckpt, energy_trace);
+}
+
+__attribute__((visibility("default"))) int nbody_lj_forces(const nbody_config* cfg, const nbody_lj_params* lj,
+                                                           int64_t n, const double* pos, const double* mass,
+                                                           double* acc, double* pot) {
+  g_err.clear();
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_FORCE, lj));
+  if (n == 0) return NBODY_OK;
+  if (!pos || !mass || !acc) return fail(NBODY_ERR_INVALID_ARG, "pos, mass and acc must be non-NULL");
+  c.ls.mdiv = mass;
+  TRY(upload_meta(c));
+  TRY(stage(c, pos, mass));
+  return force_pass(c, acc, pot, nullptr, 0.0);
+}
+
+__attribute__((visibility("default"))) int nbody_lj_rollout(const nbody_config* cfg, const nbody_lj_params* lj,
+                                                            int64_t n, double dt, int64_t steps, double* pos,
+                                                            double* vel, const double* mass, double* acc,
+                                                            double* energy_trace) {
+  g_err.clear();
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_FORCE | NEED_ROLLOUT, lj));
+  c.ls.mdiv = mass;
+  return rollout_impl(c, n, dt, steps, 0, pos, vel, mass, acc, nullptr, energy_trace);
 }
 
 __attribute__((visibility("default"))) int nbody_energy_momentum(const nbody_config* cfg, int64_t n,

@@ -1,8 +1,15 @@
 // Device kernels of the all-pairs N-body hot path for gfx950 (CDNA4).
 //
-// Pair law (softened gravity standing in for the Lennard-Jones law of Eq. (1);
-// all-pairs structure of Sec. IV-B):
-//   d = x_j - x_i, s = |d|^2 + eps^2, a_i = G sum_j m_j d s^{-3/2}, phi_i = -G sum_j m_j s^{-1/2}.
+// Pair laws (all-pairs structure of Sec. IV-B), chosen at compile time (LAW):
+//   LAW_GRAV  softened gravity: d = x_j - x_i, s = |d|^2 + eps^2,
+//             a_i = G sum_j m_j d s^{-3/2}, phi_i = -G sum_j m_j s^{-1/2};
+//   LAW_LJ    the Lennard-Jones law of Eq. (1) on coordinates staged in units of
+//             sigma (x' = x / sigma) with optional softening w' = w / sigma:
+//             u = 1 / (|d'|^2 + w'^2), q = u^3 = (sigma/r)^6,
+//             a_i = (24 eps / sigma) / m_i sum_j u q (1 - 2 q) d',
+//             pot_i = 4 eps / m_i sum_j (q^2 - q)   (= (1/m_i) sum_j V(r_ij)).
+//   The kernels accumulate the law's sums without its constants; the reduce /
+//   store step applies them (G, or 24 eps / sigma and 4 eps with the 1/m_i).
 //
 // Execution model of the pair kernels:
 //   * a block owns BS*I consecutive i-particles; lane t keeps particles
@@ -17,10 +24,15 @@
 //     cycle, which halves the FP32 issue rate of the loop;
 //   * no atomics in any arithmetic; every sum runs in a fixed order.
 //
-// Self pair: d = 0 exactly (both sides read the same stored coordinates), so it
-// adds exactly 0 to the acceleration. It must be excluded from the potential
-// and from the adjoint, so tiles that overlap the block's own i-range take a
+// Self pair: d = 0 exactly (both sides read the same stored coordinates), so under
+// gravity it adds exactly 0 to the acceleration. It must be excluded from the
+// potential, from the adjoint and (its u is infinite without softening) from the
+// whole Lennard-Jones pair, so tiles that overlap the block's own i-range take a
 // masked copy of the inner loop; all other tiles take the unmasked one.
+//
+// Padding: j-slots past the end of a range hold a particle that contributes exactly
+// zero - massless at the origin under gravity, and under Lennard-Jones a particle so
+// far away (1e30 in float, 1e150 in double) that u^3 underflows to 0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -83,6 +95,34 @@ __device__ __forceinline__ typename Vec4<T>::type zero4() {
   return v;
 }
 
+enum { LAW_GRAV = 0, LAW_LJ = 1 };
+
+// j-slot padding that adds exactly zero under the pair law (see the header comment).
+template <typename T, int LAW>
+__device__ __forceinline__ typename Vec4<T>::type pad4() {
+  typename Vec4<T>::type v = zero4<T>();
+  if constexpr (LAW == LAW_LJ) v.x = v.y = v.z = sizeof(T) == 4 ? T(1e30f) : T(1e150);
+  return v;
+}
+
+// 1/s in double: hardware estimate refined by two Newton-Raphson steps y <- y + y (1 - s y).
+__device__ __forceinline__ double rcp_f64(double s) {
+  double y = __builtin_amdgcn_rcp(s);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    double e = __builtin_fma(-s, y, 1.0);
+    y = __builtin_fma(y, e, y);
+  }
+  return y;
+}
+
+template <typename T>
+__device__ __forceinline__ T pair_rcp(T s);
+template <>
+__device__ __forceinline__ float pair_rcp<float>(float s) { return __builtin_amdgcn_rcpf(s); }
+template <>
+__device__ __forceinline__ double pair_rcp<double>(double s) { return rcp_f64(s); }
+
 template <typename T>
 __device__ __forceinline__ T pair_rsqrt(T s);
 template <>
@@ -97,9 +137,11 @@ __device__ __forceinline__ double pair_rsqrt<double>(double s) { return rsqrt_f6
 // (lo_x, lo_y, lo_z, 0) with hi = fl32(x), lo = fl32(x - hi), so hi + lo carries x to
 // about 48 bits and a separation (hi_j - hi_i) + (lo_j - lo_i) is exact to float
 // rounding of the separation itself, not of the coordinates.
+// xs scales the staged coordinates (1 under gravity, 1/sigma under Lennard-Jones).
 template <typename T, bool DS>
-__device__ __forceinline__ void put_j(typename Vec4<T>::type* __restrict__ jarr, int64_t i, const double x[3],
-                                      double m) {
+__device__ __forceinline__ void put_j(typename Vec4<T>::type* __restrict__ jarr, int64_t i, const double x_in[3],
+                                      double m, double xs) {
+  const double x[3] = {x_in[0] * xs, x_in[1] * xs, x_in[2] * xs};
   if constexpr (DS) {
     float4 h, l;
     h.x = (float)x[0]; h.y = (float)x[1]; h.z = (float)x[2]; h.w = (float)m;
@@ -117,40 +159,70 @@ __device__ __forceinline__ void put_j(typename Vec4<T>::type* __restrict__ jarr,
 }
 
 template <typename T, bool DS>
-__global__ void stage_j(int64_t n, const double* __restrict__ pos, const double* __restrict__ mass,
+__global__ void stage_j(int64_t n, const double* __restrict__ pos, const double* __restrict__ mass, double xs,
                         typename Vec4<T>::type* __restrict__ jarr) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double x[3] = {pos[i], pos[n + i], pos[2 * n + i]};
-  put_j<T, DS>(jarr, i, x, mass[i]);
+  put_j<T, DS>(jarr, i, x, mass[i], xs);
 }
 
+// Reflective walls of the box [lo, hi]^3, applied after the drift (the boundary
+// check of the paper's miniapp): a coordinate past a wall is mirrored back into
+// the box and that velocity component changes sign. on == 0: open space.
+struct Walls {
+  int32_t on;
+  int32_t pad;
+  double lo[3], hi[3];
+};
+
 // First half of a KDK step fused with the staging of the new positions:
-//   v += hh a;  x += h v;  jarr = (x, m) in pair precision.
+//   v += hh a;  x += h v;  (walls);  jarr = (xs x, m) in pair precision.
 template <typename T, bool DS>
 __global__ void kick_drift_stage(int64_t n, double hh, double h, double* __restrict__ pos,
                                  double* __restrict__ vel, const double* __restrict__ acc,
-                                 const double* __restrict__ mass, typename Vec4<T>::type* __restrict__ jarr) {
+                                 const double* __restrict__ mass, double xs, Walls wl,
+                                 typename Vec4<T>::type* __restrict__ jarr) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double x[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     double v = vel[c * n + i] + hh * acc[c * n + i];
+    double xc = pos[c * n + i] + h * v;
+    if (wl.on) {
+      if (xc < wl.lo[c]) {
+        xc = 2.0 * wl.lo[c] - xc;
+        v = -v;
+      } else if (xc > wl.hi[c]) {
+        xc = 2.0 * wl.hi[c] - xc;
+        v = -v;
+      }
+    }
     vel[c * n + i] = v;
-    x[c] = pos[c * n + i] + h * v;
-    pos[c * n + i] = x[c];
+    pos[c * n + i] = xc;
+    x[c] = xc;
   }
-  put_j<T, DS>(jarr, i, x, mass[i]);
+  put_j<T, DS>(jarr, i, x, mass[i], xs);
 }
 
-// Sum of j-split partials (fixed order p = 0..S-1), scaled by G; optional potential
-// and optional closing half-kick v += hh a.
+// Constants of the pair law applied to the kernels' raw sums:
+//   acc = ca * sum / m_i, pot = cp * sum / m_i (mdiv = masses), or without the 1/m_i
+//   when mdiv == nullptr (gravity: ca = cp = G).
+struct LawScale {
+  double ca, cp;
+  const double* mdiv;
+};
+
+__device__ __forceinline__ double law_div(const LawScale& ls, int64_t i) { return ls.mdiv ? ls.mdiv[i] : 1.0; }
+
+// Sum of j-split partials (fixed order p = 0..S-1), scaled by the law's constants;
+// optional potential and optional closing half-kick v += hh a.
 //   part [S][4][n]: planes ax, ay, az, phi of every split.
 // Batched form: sys_off (device, n_sys+1) and nsplit (device, n_sys) give the split
 // count of the system that owns particle i; single-system form passes n_sys = 0.
 // count particles starting at the given pointers; stride = plane stride of part/acc/vel.
-__global__ void reduce_splits(int64_t count, int64_t stride, int32_t S, const double* __restrict__ part, double G,
+__global__ void reduce_splits(int64_t count, int64_t stride, int32_t S, const double* __restrict__ part, LawScale ls,
                               double* __restrict__ acc, double* __restrict__ pot,
                               double* __restrict__ vel, double hh, int64_t n_sys,
                               const int64_t* __restrict__ sys_off, const int32_t* __restrict__ nsplit) {
@@ -170,25 +242,26 @@ __global__ void reduce_splits(int64_t count, int64_t stride, int32_t S, const do
   for (int32_t p = 0; p < s_cnt; ++p)
 #pragma unroll
     for (int c = 0; c < 4; ++c) a[c] += part[((int64_t)p * 4 + c) * n + i];
+  const double md = law_div(ls, i);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double ac = G * a[c];
+    double ac = ls.ca * a[c] / md;
     acc[c * n + i] = ac;
     if (vel) vel[c * n + i] += hh * ac;
   }
-  if (pot) pot[i] = G * a[3];
+  if (pot) pot[i] = ls.cp * a[3] / md;
 }
 
 // ----------------------------------------------------------------- force pair pass
 
 // Launch geometry shared by the single-system and batched drivers.
 struct ForceOut {
-  // direct mode (part == nullptr): acc = G*sum, pot = G*sum (if pot), vel += hh*acc (if vel)
+  // direct mode (part == nullptr): acc = ca*sum/m, pot = cp*sum/m (if pot), vel += hh*acc (if vel)
   double* acc;
   double* pot;
   double* vel;
   double hh;
-  double G;
+  LawScale ls;
   // partial mode: part[(slot*4 + c)*n_plane + i] = sum (unscaled)
   double* part;
   int64_t n_plane;
@@ -200,7 +273,7 @@ enum { MODE_PLAIN = 0, MODE_COMP = 1, MODE_DS = 2 };
 
 // One block's work: i in [ib, ie) (ie - ib <= BS*I) against j in [jb, je).
 // Returns the unscaled sums of every component in res[c][u] (c = ax, ay, az, phi).
-template <typename T, int BS, int I, int TJ, bool POT, int MODE>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
 __device__ __forceinline__ void force_block(const typename Vec4<T>::type* __restrict__ jarr,
                                             int64_t ib, int64_t ie, int64_t jb, int64_t je, T eps2_arg,
                                             typename Vec4<T>::type* tile /* [TJ * (DS ? 2 : 1)] */,
@@ -243,7 +316,7 @@ __device__ __forceinline__ void force_block(const typename Vec4<T>::type* __rest
   for (int k = 0; k < PER; ++k) {
     int64_t j = jb + t + (int64_t)k * BS;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) pre[NV * k + v] = j < je ? jarr[NV * j + v] : zero4<T>();  // zero mass adds 0
+    for (int v = 0; v < NV; ++v) pre[NV * k + v] = j < je ? jarr[NV * j + v] : (v ? zero4<T>() : pad4<T, LAW>());
   }
 
   for (int64_t j0 = jb; j0 < je; j0 += TJ) {
@@ -258,10 +331,10 @@ __device__ __forceinline__ void force_block(const typename Vec4<T>::type* __rest
       for (int k = 0; k < PER; ++k) {
         int64_t j = j0 + TJ + t + (int64_t)k * BS;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) pre[NV * k + v] = j < je ? jarr[NV * j + v] : zero4<T>();
+        for (int v = 0; v < NV; ++v) pre[NV * k + v] = j < je ? jarr[NV * j + v] : (v ? zero4<T>() : pad4<T, LAW>());
       }
     }
-    const bool diag = POT && (j0 < ie) && (j0 + TJ > ib);
+    const bool diag = (POT || LAW == LAW_LJ) && (j0 < ie) && (j0 + TJ > ib);
 #define NBODY_FORCE_PAIR(MASKED)                                                          \
     {                                                                                     \
       const V q = tile[NV * jj];                                                          \
@@ -275,14 +348,30 @@ __device__ __forceinline__ void force_block(const typename Vec4<T>::type* __rest
           dz += ql.z - zl[u];                                                             \
         }                                                                                 \
         T r2 = fmaT(dx, dx, fmaT(dy, dy, fmaT(dz, dz, eps2)));                            \
-        T ri = pair_rsqrt<T>(r2);                                                         \
-        T mr = q.w * ri;                                                                  \
-        T s = (mr * ri) * ri;                                                             \
-        acc_t[0][u] = fmaT(s, dx, acc_t[0][u]);                                           \
-        acc_t[1][u] = fmaT(s, dy, acc_t[1][u]);                                           \
-        acc_t[2][u] = fmaT(s, dz, acc_t[2][u]);                                           \
-        if (MASKED) acc_t[3][u] -= (j0 + jj == my_i[u]) ? T(0) : mr;                      \
-        else if (POT) acc_t[3][u] -= mr;                                                  \
+        if constexpr (LAW == LAW_LJ) {                                                    \
+          const T iv = pair_rcp<T>(r2);                                                   \
+          const T q6 = (iv * iv) * iv;                                                    \
+          T s = (iv * q6) * fmaT(T(-2), q6, T(1));                                        \
+          T pv = fmaT(q6, q6, -q6);                                                       \
+          if (MASKED) {                                                                   \
+            const bool self = (j0 + jj == my_i[u]);                                       \
+            s = self ? T(0) : s;                                                          \
+            pv = self ? T(0) : pv;                                                        \
+          }                                                                               \
+          acc_t[0][u] = fmaT(s, dx, acc_t[0][u]);                                         \
+          acc_t[1][u] = fmaT(s, dy, acc_t[1][u]);                                         \
+          acc_t[2][u] = fmaT(s, dz, acc_t[2][u]);                                         \
+          if (POT) acc_t[3][u] += pv;                                                     \
+        } else {                                                                          \
+          T ri = pair_rsqrt<T>(r2);                                                       \
+          T mr = q.w * ri;                                                                \
+          T s = (mr * ri) * ri;                                                           \
+          acc_t[0][u] = fmaT(s, dx, acc_t[0][u]);                                         \
+          acc_t[1][u] = fmaT(s, dy, acc_t[1][u]);                                         \
+          acc_t[2][u] = fmaT(s, dz, acc_t[2][u]);                                         \
+          if (MASKED) acc_t[3][u] -= (j0 + jj == my_i[u]) ? T(0) : mr;                    \
+          else if (POT) acc_t[3][u] -= mr;                                                \
+        }                                                                                 \
       }                                                                                   \
     }
     if (!diag) {
@@ -323,13 +412,14 @@ __device__ __forceinline__ void force_store(const ForceOut& o, int64_t ib, int64
 #pragma unroll
       for (int c = 0; c < 4; ++c) o.part[((int64_t)slot * 4 + c) * o.n_plane + i] = res[c][u];
     } else {
+      const double md = law_div(o.ls, i);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        double a = o.G * res[c][u];
+        double a = o.ls.ca * res[c][u] / md;
         o.acc[c * o.n_plane + i] = a;
         if (o.vel) o.vel[c * o.n_plane + i] += o.hh * a;
       }
-      if (pot_on && o.pot) o.pot[i] = o.G * res[3][u];
+      if (pot_on && o.pot) o.pot[i] = o.ls.cp * res[3][u] / md;
     }
   }
 }
@@ -337,7 +427,7 @@ __device__ __forceinline__ void force_store(const ForceOut& o, int64_t ib, int64
 // Single system (or one i-range of it): grid (ceil(ni / (BS*I)), S).
 // Block (bx, by) takes i-range [i0 + bx*BS*I, ...) and the by-th of S j-ranges
 // of length jchunk (a multiple of TJ) inside [j0, j1).
-template <typename T, int BS, int I, int TJ, bool POT, int MODE>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
 __global__ __launch_bounds__(BS) void force_kernel(const typename Vec4<T>::type* __restrict__ jarr,
                                                    int64_t i0, int64_t i1, int64_t j0, int64_t j1,
                                                    int64_t jchunk, T eps2, ForceOut o) {
@@ -347,7 +437,7 @@ __global__ __launch_bounds__(BS) void force_kernel(const typename Vec4<T>::type*
   const int64_t jb = j0 + (int64_t)blockIdx.y * jchunk;
   const int64_t je = jb + jchunk < j1 ? jb + jchunk : j1;
   double res[4][I];
-  force_block<T, BS, I, TJ, POT, MODE>(jarr, ib, ie, jb, je, eps2, tile, res);
+  force_block<T, BS, I, TJ, POT, MODE, LAW>(jarr, ib, ie, jb, je, eps2, tile, res);
   force_store<I>(o, ib, ie, blockIdx.y, res, POT, BS);
 }
 
@@ -388,6 +478,8 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 // Each unordered pair once: a_i += m_j r3 d and a_j -= m_i r3 d (r3 = s^{-3/2}), with
 // phi_i -= m_j s^{-1/2}, phi_j -= m_i s^{-1/2} - the action-reaction symmetry of the
 // pair force halves the separations, square roots and scale factors per interaction.
+// Under Lennard-Jones the pair factor k = u q (1 - 2q) carries no mass (the 1/m is
+// applied at the end), so a_i += k d and a_j -= k d, and both potentials add q^2 - q.
 //
 // Blocks of BI = W*64*I consecutive particles; one workgroup per tile (A, B), A <= B.
 // Wave w keeps i-particles A*BI + w*64*I + u*64 + lane (u < I) in registers. Block B
@@ -401,7 +493,7 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 // Output: float partial sums part[(slot*4 + c)*n + p], c = ax, ay, az, phi: the
 // i-side of tile (A, B) goes to slot B, the j-side to slot A, so every particle owns
 // exactly nb slots, summed in double (fixed order) by reduce_sym.
-template <int W, int I, bool POT, int MODE, int ROT>
+template <int W, int I, bool POT, int MODE, int ROT, int LAW>
 __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restrict__ jarr, int64_t n, int32_t nb,
                                                            float eps2_arg, float* __restrict__ part) {
   constexpr bool COMP = MODE != MODE_PLAIN;
@@ -420,6 +512,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
   const int64_t Abase = (int64_t)A * BI, Bbase = (int64_t)B * BI;
   const float eps2 = in_vgpr(eps2_arg);
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 jpad = pad4<float, LAW>();
 
   float xi[I], yi[I], zi[I], mi[I], xl[I], yl[I], zl[I];
   float ai[NC][I], hi[NC][I], lo[NC][I];
@@ -427,11 +520,12 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
   for (int u = 0; u < I; ++u) {
     const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
     const int64_t ic = i < n ? i : n - 1;
-    const float4 p = jarr[NV * ic];
+    // padding lanes have no j-side effect: no mass (gravity), far away (Lennard-Jones)
+    const float4 p = (LAW == LAW_LJ && i >= n) ? jpad : jarr[NV * ic];
     xi[u] = in_vgpr(p.x);
     yi[u] = in_vgpr(p.y);
     zi[u] = in_vgpr(p.z);
-    mi[u] = in_vgpr(i < n ? p.w : 0.f);  // padding lanes carry no mass: no j-side effect
+    mi[u] = in_vgpr(i < n ? p.w : 0.f);
     if constexpr (DS) {
       const float4 pl = jarr[NV * ic + 1];
       xl[u] = in_vgpr(pl.x);
@@ -445,14 +539,14 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
   float4 nxt, nxtl = zero;
   {
     const int64_t j = Bbase + lane;
-    nxt = j < n ? jarr[NV * j] : zero;
+    nxt = j < n ? jarr[NV * j] : jpad;
     if constexpr (DS) nxtl = j < n ? jarr[NV * j + 1] : zero;
   }
   for (int sb = 0; sb < NSUB; ++sb) {
     const float4 q = nxt, ql = nxtl;
     if (sb + 1 < NSUB) {
       const int64_t j = Bbase + (int64_t)(sb + 1) * 64 + lane;
-      nxt = j < n ? jarr[NV * j] : zero;
+      nxt = j < n ? jarr[NV * j] : jpad;
       if constexpr (DS) nxtl = j < n ? jarr[NV * j + 1] : zero;
     }
     float xj = q.x, yj = q.y, zj = q.z, mj = q.w, xjl = ql.x, yjl = ql.y, zjl = ql.z;
@@ -468,13 +562,25 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
             dz += zjl - zl[u];
           }
           const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
-          const float ri = __builtin_amdgcn_rsqf(r2);
-          const float mr = mj * ri;
-          const float s = (mr * ri) * ri;
-          ai[0][u] = __builtin_fmaf(s, dx, ai[0][u]);
-          ai[1][u] = __builtin_fmaf(s, dy, ai[1][u]);
-          ai[2][u] = __builtin_fmaf(s, dz, ai[2][u]);
-          if (POT) ai[3][u] -= (k == 0 && sb == w * I + u) ? 0.f : mr;
+          if constexpr (LAW == LAW_LJ) {
+            const bool self = (k == 0 && sb == w * I + u);
+            const float iv = __builtin_amdgcn_rcpf(r2);
+            const float q6 = (iv * iv) * iv;
+            float s = (iv * q6) * __builtin_fmaf(-2.f, q6, 1.f);
+            s = self ? 0.f : s;
+            ai[0][u] = __builtin_fmaf(s, dx, ai[0][u]);
+            ai[1][u] = __builtin_fmaf(s, dy, ai[1][u]);
+            ai[2][u] = __builtin_fmaf(s, dz, ai[2][u]);
+            if constexpr (POT) ai[3][u] += self ? 0.f : __builtin_fmaf(q6, q6, -q6);
+          } else {
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float mr = mj * ri;
+            const float s = (mr * ri) * ri;
+            ai[0][u] = __builtin_fmaf(s, dx, ai[0][u]);
+            ai[1][u] = __builtin_fmaf(s, dy, ai[1][u]);
+            ai[2][u] = __builtin_fmaf(s, dz, ai[2][u]);
+            if (POT) ai[3][u] -= (k == 0 && sb == w * I + u) ? 0.f : mr;
+          }
         }
         xj = rotate1<ROT>(xj, rot_src);
         yj = rotate1<ROT>(yj, rot_src);
@@ -507,9 +613,25 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
           ri[u] = __builtin_fmaf(dx[u], dx[u], __builtin_fmaf(dy[u], dy[u], __builtin_fmaf(dz[u], dz[u], eps2)));
         }
 #pragma unroll
-        for (int u = 0; u < I; ++u) ri[u] = __builtin_amdgcn_rsqf(ri[u]);
+        for (int u = 0; u < I; ++u) ri[u] = LAW == LAW_LJ ? __builtin_amdgcn_rcpf(ri[u]) : __builtin_amdgcn_rsqf(ri[u]);
 #pragma unroll
         for (int u = 0; u < I; ++u) {
+          if constexpr (LAW == LAW_LJ) {
+            const float q6 = (ri[u] * ri[u]) * ri[u];
+            const float kf = (ri[u] * q6) * __builtin_fmaf(-2.f, q6, 1.f);
+            if constexpr (POT) {
+              const float pv = __builtin_fmaf(q6, q6, -q6);
+              ai[3][u] += pv;
+              aj[3] += pv;
+            }
+            ai[0][u] = __builtin_fmaf(kf, dx[u], ai[0][u]);
+            ai[1][u] = __builtin_fmaf(kf, dy[u], ai[1][u]);
+            ai[2][u] = __builtin_fmaf(kf, dz[u], ai[2][u]);
+            aj[0] = __builtin_fmaf(-kf, dx[u], aj[0]);
+            aj[1] = __builtin_fmaf(-kf, dy[u], aj[1]);
+            aj[2] = __builtin_fmaf(-kf, dz[u], aj[2]);
+            continue;
+          }
           // the acceleration terms round identically with and without the potential,
           // so both variants give bitwise-equal accelerations (trajectories must not
           // depend on whether an energy trace is taken)
@@ -575,10 +697,10 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
   }
 }
 
-// Sum of the nb float slots of every particle in double (fixed order), scaled by G;
-// optional potential and closing half-kick.
+// Sum of the nb float slots of every particle in double (fixed order), scaled by the
+// law's constants; optional potential and closing half-kick.
 // n: particles of the system (partial plane stride); stride: plane stride of acc/vel.
-__global__ void reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* __restrict__ part, double G,
+__global__ void reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* __restrict__ part, LawScale ls,
                            double* __restrict__ acc, double* __restrict__ pot, double* __restrict__ vel, double hh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -586,13 +708,14 @@ __global__ void reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* _
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   for (int32_t s = 0; s < nb; ++s)
     for (int c = 0; c < nc; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
+  const double md = law_div(ls, i);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double ac = G * a[c];
+    const double ac = ls.ca * a[c] / md;
     acc[c * stride + i] = ac;
     if (vel) vel[c * stride + i] += hh * ac;
   }
-  if (pot) pot[i] = G * a[3];
+  if (pot) pot[i] = ls.cp * a[3] / md;
 }
 
 // ----------------------------------------------------------------- batched persistent force pass
@@ -609,7 +732,7 @@ struct WorkUnit {
 // is exhausted (units are sorted by decreasing cost on the host). Each unit writes
 // its own partial slot, so the result does not depend on which block ran it.
 // counter must be 0 at launch.
-template <typename T, int BS, int I, int TJ, bool POT, int MODE>
+template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
 __global__ __launch_bounds__(BS) void force_batched_kernel(const typename Vec4<T>::type* __restrict__ jarr,
                                                            const WorkUnit* __restrict__ units, int32_t n_units,
                                                            int32_t* __restrict__ counter, T eps2, ForceOut o) {
@@ -623,7 +746,7 @@ __global__ __launch_bounds__(BS) void force_batched_kernel(const typename Vec4<T
     if (u >= n_units) break;
     const WorkUnit w = units[u];
     double res[4][I];
-    force_block<T, BS, I, TJ, POT, MODE>(jarr, w.ib, w.ie, w.jb, w.je, eps2, tile, res);
+    force_block<T, BS, I, TJ, POT, MODE, LAW>(jarr, w.ib, w.ie, w.jb, w.je, eps2, tile, res);
     force_store<I>(o, w.ib, w.ie, w.slot, res, POT, BS);
   }
 }

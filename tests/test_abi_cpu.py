@@ -157,3 +157,50 @@ def test_tile_table_validation(nb):
     nb.set_tile_table([])
     v, s = nb.tile_lookup("force", "fp32c", 1 << 20)
     assert v >= 0 and s >= 1
+
+
+def _lj(nb, **kw):
+    p = nb.lj_params(kw.get("sigma", 1.0), kw.get("epsilon", 1.0), kw.get("soft", 0.0), kw.get("box"))
+    if "reserved" in kw:
+        p.reserved = kw["reserved"]
+    if "walls" in kw:
+        p.walls = kw["walls"]
+    return p
+
+
+def test_lj_params_layout(nb):
+    """nbody_lj_params: 3 doubles, 2 int32, 6 doubles = 80 bytes, no padding."""
+    assert ctypes.sizeof(nb.LJParams) == 80
+    assert nb.LJParams.lo.offset == 32 and nb.LJParams.hi.offset == 56
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(sigma=0.0), "sigma"),
+    (dict(sigma=float("nan")), "sigma"),
+    (dict(epsilon=float("inf")), "epsilon"),
+    (dict(soft=-0.1), "soft"),
+    (dict(soft=1e-12), "soft/sigma"),
+    (dict(reserved=3), "reserved"),
+    (dict(walls=2), "walls"),
+    (dict(box=([0, 0, 0], [1, 1, 0])), "box"),
+    (dict(box=([0, 0, float("nan")], [1, 1, 1])), "box"),
+])
+def test_lj_argument_errors_cpu(nb, kw, needle):
+    c = _cfg(nb, ws=0x1000, ws_bytes=1 << 40)
+    lj = _lj(nb, **kw)
+    rc = nb.lib().nbody_lj_rollout(ctypes.byref(c), ctypes.byref(lj), 10, 1e-3, 1, FAKE, FAKE, FAKE, FAKE, None)
+    assert rc == 1
+    assert needle in nb.lib().nbody_last_error().decode()
+
+
+def test_lj_ignores_gravity_constants(nb):
+    """G and eps are not used by the Lennard-Jones calls, so they are not checked there
+    (n == 0 returns before any device work); the workspace size ignores them too."""
+    c = _cfg(nb, eps=0.0, G=float("nan"))
+    assert nb.lib().nbody_lj_forces(ctypes.byref(c), ctypes.byref(_lj(nb)), 0, None, None, None, None) == 0
+    assert nb.lib().nbody_lj_forces(None, ctypes.byref(_lj(nb)), 0, None, None, None, None) == 1
+    assert nb.lib().nbody_lj_forces(ctypes.byref(c), None, 0, None, None, None, None) == 1
+    rc, b = _ws_size(nb, c, 1000)
+    assert rc == 0 and b > 0
+    rc, b2 = _ws_size(nb, _cfg(nb), 1000)
+    assert b == b2

@@ -1,0 +1,277 @@
+"""GPU parity of the Lennard-Jones gas (the paper's pair law, Eq. (1)) against the oracle.
+
+The LJ force has no natural per-particle scale (on a lattice site it cancels to ~0),
+so errors are bounded per particle by what the arithmetic can guarantee, from the
+sum of the magnitudes of the pair terms: with t12 = 48 eps sigma^12 / r^13 and
+t6 = 24 eps sigma^6 / r^7 (the repulsive and attractive parts of |F_ij|),
+  B_i = (1/m_i) sum_j [ c u (t12 + t6)  +  (13 t12 + 7 t6) / r * dd_ij ]
+where u is the unit roundoff of the pair arithmetic, c = 16 covers the pair
+operations and the compensated accumulation (plain float accumulation adds a
+statistical sqrt(n) u (t12 + t6); in FP64 both the kernel's and the oracle's
+running sums are charged the worst case (n - 1) u sum |term| of recursive
+summation, 2n u in all), (13 t12 + 7 t6) / r bounds the Jacobian of the pair force
+with respect to the separation, and dd_ij = sqrt(3) u (|x_i| + |x_j|) is the
+separation error from rounding the coordinates (sqrt(3) u r with double-float
+coordinates). The potential is bounded the same way with 4 eps (s^12 + s^6)
+and the slope |dV/dr| <= t12 + t6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2511_02655_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "fp32c": 2.0 ** -24, "fp32ds": 2.0 ** -24}
+PRECS = ["fp64", "fp32", "fp32c", "fp32ds"]
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_02655_amd as nb
+    nb.lib()
+    return nb
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def lj_bound(pos, mass, prec, idx=None, sigma=1.0, epsilon=1.0, soft=0.0):
+    """Per-particle error bounds (acceleration, potential) of the pair path at `prec`."""
+    u = U[prec]
+    n = mass.shape[0]
+    idx = np.arange(n) if idx is None else np.asarray(idx)
+    xn = np.sqrt(np.sum(pos ** 2, axis=0))
+    Ba = np.empty(idx.shape[0])
+    Bp = np.empty(idx.shape[0])
+    for k0 in range(0, idx.shape[0], 256):
+        ii = idx[k0:k0 + 256]
+        d = pos[:, None, :] - pos[:, ii, None]
+        r2 = np.sum(d * d, axis=0) + soft * soft
+        self_mask = ii[:, None] == np.arange(n)[None, :]
+        r2 = np.where(self_mask, 1.0, r2)
+        r = np.sqrt(r2)
+        s6 = (sigma * sigma / r2) ** 3
+        t12 = 48 * epsilon * s6 * s6 / r
+        t6 = 24 * epsilon * s6 / r
+        T = np.where(self_mask, 0.0, t12 + t6)
+        J = np.where(self_mask, 0.0, (13 * t12 + 7 * t6) / r)
+        P = np.where(self_mask, 0.0, 4 * epsilon * (s6 * s6 + s6))
+        if prec == "fp32ds":
+            dd = math.sqrt(3.0) * u * r
+        else:
+            dd = math.sqrt(3.0) * u * (xn[ii, None] + xn[None, :])
+        c = 16.0 + {"fp64": 2.0 * n, "fp32": math.sqrt(n)}.get(prec, 0.0)
+        Ba[k0:k0 + 256] = np.sum(c * u * T + J * dd, axis=1) / mass[ii]
+        Bp[k0:k0 + 256] = np.sum(c * u * P + T * dd, axis=1) / mass[ii]
+    return Ba, Bp
+
+
+def check_lj(acc, pot, acc_ref, pot_ref, pos, mass, prec, idx=None, bounds=None, **law):
+    Ba, Bp = bounds if bounds is not None else lj_bound(pos, mass, prec, idx, **law)
+    def ratio(err, B):  # err / B, with 0 / 0 (a lone particle: no pair terms) read as 0
+        return np.where(err == 0, 0.0, err / np.where(B > 0, B, 1e-300))
+    ea = ratio(np.sqrt(np.sum((acc - acc_ref) ** 2, axis=0)), Ba)
+    worst = float(np.max(ea)) if ea.size else 0.0
+    assert worst <= 1.0, "%s: acceleration error exceeds the bound by %.3g" % (prec, worst)
+    if pot is not None:
+        ep = ratio(np.abs(pot - pot_ref), Bp)
+        assert float(np.max(ep)) <= 1.0, "%s: potential error exceeds the bound by %.3g" % (prec, float(np.max(ep)))
+    return worst
+
+
+def _gas(n, seed, spacing=1.2, jitter=0.08, mass_spread=True):
+    s, box = inputs.lj_gas(n, seed, spacing=spacing)
+    g = np.random.Generator(np.random.PCG64(seed + 77))
+    pos = s.pos + g.uniform(-jitter, jitter, s.pos.shape)
+    mass = g.uniform(0.5, 2.0, n) if mass_spread else s.mass
+    return pos, mass, s.vel, box
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n", [2, 7, 100, 257, 1000, 4097])
+def test_lj_forces_vs_oracle(nb, oracle, prec, n):
+    """Every precision mode on sizes below, at and across tile edges (ragged tails pad
+    with far-away particles that must add exactly nothing)."""
+    pos, mass, _, _ = _gas(n, 40 + n)
+    sigma, epsilon = 1.1, 0.7
+    acc_ref, pot_ref = oracle.lj_forces(pos, mass, sigma, epsilon)
+    acc, pot = nb.lj_forces(dev(pos), dev(mass), sigma=sigma, epsilon=epsilon, precision=prec, want_pot=True)
+    acc, pot = host(acc), host(pot)
+    assert np.all(np.isfinite(acc)) and np.all(np.isfinite(pot))
+    check_lj(acc, pot, acc_ref, pot_ref, pos, mass, prec, sigma=sigma, epsilon=epsilon)
+    acc2, _ = nb.lj_forces(dev(pos), dev(mass), sigma=sigma, epsilon=epsilon, precision=prec, want_pot=False)
+    assert np.array_equal(host(acc2), acc)  # the potential does not change the accelerations
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_lj_softened(nb, oracle, prec):
+    pos, mass, _, _ = _gas(500, 9, spacing=0.9, jitter=0.3)
+    acc_ref, pot_ref = oracle.lj_forces(pos, mass, 1.0, 1.0, 0.25)
+    acc, pot = nb.lj_forces(dev(pos), dev(mass), soft=0.25, precision=prec, want_pot=True)
+    check_lj(host(acc), host(pot), acc_ref, pot_ref, pos, mass, prec, soft=0.25)
+
+
+def test_lj_single_particle_and_dimer_landmarks(nb):
+    """One particle feels nothing (its own pair is masked, not 0 * inf); a dimer at
+    r_min = 2^{1/6} sigma feels (almost) no force and has energy -eps."""
+    for prec in PRECS:
+        acc, pot = nb.lj_forces(dev(np.array([[0.0], [0.0], [0.0]])), dev(np.ones(1)), precision=prec, want_pot=True)
+        assert np.all(host(acc) == 0) and np.all(host(pot) == 0)
+    rmin = 2.0 ** (1.0 / 6.0)
+    pos = np.array([[0.0, rmin], [0.0, 0.0], [0.0, 0.0]])
+    acc, pot = nb.lj_forces(dev(pos), dev(np.ones(2)), precision="fp64", want_pot=True)
+    assert np.max(np.abs(host(acc))) < 1e-13
+    assert 0.5 * np.sum(host(pot)) == pytest.approx(-1.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lj_newton_third_law(nb, prec):
+    pos, mass, _, _ = _gas(3000, 21)
+    acc, _ = nb.lj_forces(dev(pos), dev(mass), precision=prec)
+    F = host(acc) * mass
+    Ba, _ = lj_bound(pos, mass, prec)
+    assert np.max(np.abs(F.sum(axis=1))) <= np.sum(Ba * mass)
+
+
+def _sym_variants(nb):
+    return [k for k, d in enumerate(nb.tile_variants("force", "fp32c")) if "sym=" in d]
+
+
+@pytest.mark.parametrize("n", [1, 2, 100, 1025, 2049, 5000])
+def test_lj_symmetric_kernel_vs_oracle(nb, oracle, n):
+    """The action-reaction pass with the Lennard-Jones pair factor, every variant, across
+    block edges (padding lanes sit far away and must not leak into real particles)."""
+    pos, mass, _, _ = _gas(n, 500 + n)
+    acc_ref, pot_ref = oracle.lj_forces(pos, mass)
+    bounds = {p: lj_bound(pos, mass, p) for p in ("fp32", "fp32c", "fp32ds")}
+    try:
+        for v in _sym_variants(nb):
+            nb.set_tile_table([dict(kernel="force", precision=p, n_min=0, n_max=1 << 40, variant=v, j_split=1)
+                               for p in ("fp32", "fp32c", "fp32ds")])
+            for prec in ("fp32", "fp32c", "fp32ds"):
+                acc, pot = nb.lj_forces(dev(pos), dev(mass), precision=prec, want_pot=True)
+                acc, pot = host(acc), host(pot)
+                if n == 1:
+                    assert np.all(acc == 0) and np.all(pot == 0)
+                    continue
+                check_lj(acc, pot, acc_ref, pot_ref, pos, mass, prec, bounds=bounds[prec])
+    finally:
+        nb.set_tile_table([])
+
+
+def test_lj10k_sampled_default_tiles(nb, oracle):
+    """The paper-size gas (10 000 particles on the lattice) with the library's own tiles."""
+    s, box = inputs.make("lj10k")
+    acc_ref, pot_ref = oracle.lj_forces(s.pos, s.mass)
+    for prec in PRECS:
+        acc, pot = nb.lj_forces(dev(s.pos), dev(s.mass), precision=prec, want_pot=True)
+        check_lj(host(acc), host(pot), acc_ref, pot_ref, s.pos, s.mass, prec)
+
+
+def test_lj_large_symmetric_path(nb, oracle):
+    """Above the symmetric threshold (here 40 000 particles) the default FP32 path is the
+    action-reaction kernel; sampled particles against the oracle."""
+    pos, mass, _, _ = _gas(40000, 8)
+    acc_ref, pot_ref = oracle.lj_forces(pos, mass)
+    idx = np.random.Generator(np.random.PCG64(1)).choice(40000, 600, replace=False)
+    for prec in ("fp32c", "fp32ds"):
+        acc, pot = nb.lj_forces(dev(pos), dev(mass), precision=prec, want_pot=True)
+        check_lj(host(acc)[:, idx], host(pot)[idx], acc_ref[:, idx], pot_ref[idx], pos, mass, prec, idx=idx)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32c", 1e-4), ("fp32ds", 1e-5)])
+def test_lj_rollout_with_walls_vs_oracle(nb, oracle, prec, tol):
+    """KDK with the reflective-wall check after every drift, against the oracle, with the
+    fused energy trace; particles must stay in the box."""
+    s, box = inputs.lj_gas(1000, 31, spacing=1.2, temperature=2.0)
+    dt, steps = 2e-3, 60
+    pos_ref, vel_ref, en_ref = oracle.lj_kdk(s.pos, s.vel, s.mass, dt, steps, box=(box.lo, box.hi),
+                                             want_energy=True)
+    pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+    acc, _ = nb.lj_forces(pos, mass, precision=prec)
+    tr = nb.lj_rollout(pos, vel, mass, acc, dt, steps, box=(box.lo, box.hi), energy_trace=True, precision=prec)
+    pos, vel, tr = host(pos), host(vel), host(tr)[:, 0, :]
+    L = box.hi - box.lo
+    assert np.max(np.abs(pos - pos_ref)) <= tol * L.max()
+    assert np.max(np.abs(vel - vel_ref)) <= tol * 10 * np.max(np.abs(vel_ref))
+    E, E_ref = tr[:, 0] + tr[:, 1], en_ref[:, 0] + en_ref[:, 1]
+    assert np.max(np.abs(E - E_ref)) <= tol * 10 * np.max(np.abs(en_ref[:, 0]))
+    assert np.all(pos >= box.lo[:, None]) and np.all(pos <= box.hi[:, None])
+    # the walls were exercised: some velocity component flipped sign at a wall
+    assert np.any(np.sign(vel_ref) != np.sign(s.vel))
+
+
+def test_lj_free_flight_between_walls(nb):
+    """A lone particle bounces between the walls: closed-form triangle wave."""
+    lo, hi = np.array([0.0, -1.0, 2.0]), np.array([3.0, 4.0, 2.5])
+    x0 = np.array([[1.0], [0.5], [2.1]])
+    v0 = np.array([[2.3], [-1.7], [0.9]])
+    dt, steps = 0.01, 737
+    pos, vel, mass = dev(x0), dev(v0), dev(np.ones(1))
+    acc, _ = nb.lj_forces(pos, mass, precision="fp64")
+    nb.lj_rollout(pos, vel, mass, acc, dt, steps, box=(lo, hi), precision="fp64")
+    pos, vel = host(pos), host(vel)
+    t = dt * steps
+    for c in range(3):
+        Lc = hi[c] - lo[c]
+        y = (x0[c, 0] - lo[c] + v0[c, 0] * t) % (2 * Lc)
+        assert pos[c, 0] == pytest.approx(lo[c] + (y if y <= Lc else 2 * Lc - y), abs=1e-11)
+        assert vel[c, 0] == pytest.approx(v0[c, 0] * (1 if y <= Lc else -1), rel=1e-15)
+
+
+def test_lj_energy_conservation_paper_size(nb):
+    """The 10 000-particle gas over 500 steps of dt = 0.002 in its box: the total energy
+    stays within 1e-4 of the kinetic energy scale in FP64 and the compensated mode."""
+    s, box = inputs.make("lj10k")
+    for prec in ("fp64", "fp32c"):
+        pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+        acc, _ = nb.lj_forces(pos, mass, precision=prec)
+        tr = host(nb.lj_rollout(pos, vel, mass, acc, 2e-3, 500, box=(box.lo, box.hi), energy_trace=True,
+                                precision=prec))[:, 0, :]
+        E = tr[:, 0] + tr[:, 1]
+        assert np.max(np.abs(E - E[0])) < 1e-4 * tr[0, 0], prec
+
+
+def test_lj_batched_vs_oracle_and_loop(nb, oracle):
+    """Independent gases of uneven sizes in one persistent launch and in a per-system loop."""
+    sizes = [64, 300, 1, 0, 1500, 700]
+    parts = [_gas(k, 900 + i) if k else (np.zeros((3, 0)), np.zeros(0), None, None) for i, k in enumerate(sizes)]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    pos = np.concatenate([p[0] for p in parts], axis=1)
+    mass = np.concatenate([p[1] for p in parts])
+    for prec in ("fp64", "fp32c"):
+        acc, pot = nb.lj_forces(dev(pos), dev(mass), precision=prec, want_pot=True, offsets=off)
+        accl, potl = nb.lj_forces(dev(pos), dev(mass), precision=prec, want_pot=True, offsets=off,
+                                  flags=nb.FLAG_LOOP_SYSTEMS)
+        acc, pot, accl, potl = host(acc), host(pot), host(accl), host(potl)
+        for s in range(len(sizes)):
+            sl = slice(off[s], off[s + 1])
+            if off[s + 1] == off[s]:
+                continue
+            a_ref, p_ref = oracle.lj_forces(pos[:, sl], mass[sl])
+            check_lj(acc[:, sl], pot[sl], a_ref, p_ref, pos[:, sl], mass[sl], prec)
+            check_lj(accl[:, sl], potl[sl], a_ref, p_ref, pos[:, sl], mass[sl], prec)
+
+
+def test_lj_argument_errors(nb):
+    pos, mass = dev(np.zeros((3, 4))), dev(np.ones(4))
+    with pytest.raises(nb.NBodyError, match="sigma"):
+        nb.lj_forces(pos, mass, sigma=0.0)
+    with pytest.raises(nb.NBodyError, match="soft"):
+        nb.lj_forces(pos, mass, soft=-1.0)
+    acc = dev(np.zeros((3, 4)))
+    with pytest.raises(nb.NBodyError, match="box"):
+        nb.lj_rollout(pos, dev(np.zeros((3, 4))), mass, acc, 1e-3, 1, box=([0, 0, 0], [1, 0, 1]))
