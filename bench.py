@@ -44,11 +44,12 @@ def log(*a):
 
 
 SYM_BEGIN = "// ----------------------------------------------------------------- symmetric force pass (FP32)"
-SYM_END = "// ----------------------------------------------------------------- batched persistent force pass"
+SYM_END = "// ----------------------------------------------------------------- symmetric pass: per-particle reduction"
 
 
 def kernel_hash():
-    """Hash of the symmetric force pass's source (the kernel the stored counters describe)."""
+    """Hash of the symmetric force kernel's source (lane rotation, tile mapping and
+    force_sym_kernel: the kernel the stored counters describe)."""
     with open(KERNEL_SRC) as f:
         src = f.read()
     if SYM_BEGIN in src and SYM_END in src:
@@ -528,8 +529,8 @@ def lj_leg(nb, torch, np, inputs, dev):
             flops = LJ_FLOP_PER_INTERACTION * float(n) * n / (ms * 1e-3)
             r["force_call_us" + ("_with_potential" if want_pot else "")] = ms * 1e3
             r["force_frac_fp32_peak" + ("_with_potential" if want_pot else "")] = flops / PEAK_FP32
-        vid, jsplit = nb.tile_lookup("force", prec, n)
-        r["tile"] = "%s, j_split=%d" % (nb.tile_variants("force", prec)[vid], jsplit)
+        vid, jsplit = nb.tile_lookup("lj_force", prec, n)
+        r["tile"] = "%s, j_split=%d" % (nb.tile_variants("lj_force", prec)[vid], jsplit)
         res[prec] = r
     # parity: 20 steps against the oracle (FP64 and compensated FP32)
     k = 20

@@ -206,7 +206,11 @@ typedef enum {
   NBODY_KERNEL_FORCE = 0,   /* single-system force pass */
   NBODY_KERNEL_ADJOINT = 1, /* single-system adjoint pass */
   NBODY_KERNEL_FORCE_BATCHED = 2,
-  NBODY_KERNEL_ADJOINT_BATCHED = 3
+  NBODY_KERNEL_ADJOINT_BATCHED = 3,
+  /* Lennard-Jones force passes: the same variants as NBODY_KERNEL_FORCE(_BATCHED);
+     without an entry of their own they run with that kernel's entry (or default) */
+  NBODY_KERNEL_LJ_FORCE = 4,
+  NBODY_KERNEL_LJ_FORCE_BATCHED = 5
 } nbody_kernel;
 
 typedef struct {

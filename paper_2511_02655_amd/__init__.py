@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_PKG, "libnbody.so")
 
 NBODY_ABI_VERSION = 1
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32ds": 3}
-KERNELS = {"force": 0, "adjoint": 1, "force_batched": 2, "adjoint_batched": 3}
+KERNELS = {"force": 0, "adjoint": 1, "force_batched": 2, "adjoint_batched": 3, "lj_force": 4,
+           "lj_force_batched": 5}
 FLAG_LOOP_SYSTEMS = 1
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPACE"}
 

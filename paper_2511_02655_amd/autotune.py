@@ -23,8 +23,10 @@ import time
 import numpy as np
 
 FORCE_BUCKETS = [1024, 4096, 16384, 65536, 262144, 1048576]
+LJ_BUCKETS = [1024, 4096, 10000, 32768, 131072]
+SYM_PART_LIMIT = 16.0 * 2 ** 30  # workspace bytes a symmetric tile may ask for
 ADJ_BUCKETS = [1024, 4096, 16384, 65536]
-J_SPLITS = [1, 2, 4, 8, 16, 32]
+J_SPLITS = [1, 2, 4, 8, 16, 32, 64]
 BATCH_JCHUNK = [512, 1024, 2048, 4096]
 
 
@@ -68,35 +70,47 @@ def _pick(cands, descs, slack=0.01):
     return max(near, key=lambda c: (_sym_edge(descs[c[1]]), -c[0]))
 
 
-def tune_force(nb, torch, precision, buckets, log):
+def tune_force(nb, torch, precision, buckets, log, law="gravity"):
+    """Single-system force pass: gravity on Plummer spheres, or (law="lj") the
+    Lennard-Jones gas on its lattice (tile-table kernel "lj_force")."""
     from . import inputs
     entries = []
-    nvar = len(nb.tile_variants("force", precision))
+    kname = "lj_force" if law == "lj" else "force"
+    nvar = len(nb.tile_variants(kname, precision))
     for k, n in enumerate(buckets):
-        s = inputs.plummer(n, 100 + k)
+        if law == "lj":
+            s = inputs.lj_gas(n, 100 + k)[0]
+        else:
+            s = inputs.plummer(n, 100 + k)
         pos = torch.from_numpy(s.pos).cuda()
         mass = torch.from_numpy(s.mass).cuda()
         acc = torch.empty((3, n), dtype=torch.float64, device="cuda")
         reps = _reps_for(n)
         cands = []
-        descs = nb.tile_variants("force", precision)
+        descs = nb.tile_variants(kname, precision)
+        if law == "lj":
+            call = lambda: nb.lj_forces(pos, mass, precision=precision, out_acc=acc)
+        else:
+            call = lambda: nb.forces(pos, mass, eps=1e-2, precision=precision, out_acc=acc)
         for v in range(nvar):
             sym = "sym=" in descs[v]
             if sym and n < 4096:
                 continue
+            if sym and -(-n // _sym_edge(descs[v])) * 16.0 * n > SYM_PART_LIMIT:
+                continue  # float partials of nb slots x 4 components per particle
             for js in ([1] if sym else J_SPLITS):
                 if js > 1 and n >= 262144:
                     continue
-                nb.set_tile_table([dict(kernel="force", precision=precision, n_min=0, n_max=1 << 40, variant=v,
+                nb.set_tile_table([dict(kernel=kname, precision=precision, n_min=0, n_max=1 << 40, variant=v,
                                         j_split=js)])
-                t = _time(lambda: nb.forces(pos, mass, eps=1e-2, precision=precision, out_acc=acc), reps)
+                t = _time(call, reps)
                 rate = float(n) * n / (t * 1e-3)
-                log("force %s n=%d variant %d (%s) j_split %d: %.3f ms  %.3e inter/s" % (precision, n, v, descs[v], js,
-                                                                                      t, rate))
+                log("%s %s n=%d variant %d (%s) j_split %d: %.3f ms  %.3e inter/s" % (kname, precision, n, v, descs[v],
+                                                                                   js, t, rate))
                 cands.append((t, v, js, rate))
         best = _pick(cands, descs)
         lo, hi = _bounds(buckets, k)
-        entries.append(dict(kernel="force", precision=precision, n_min=lo, n_max=hi, variant=best[1],
+        entries.append(dict(kernel=kname, precision=precision, n_min=lo, n_max=hi, variant=best[1],
                             j_split=best[2], tuned_n=n, ms=best[0], interactions_per_s=best[3]))
         nb.set_tile_table([])
     return entries
@@ -175,7 +189,8 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--quick", action="store_true", help="FP32-compensated force buckets only")
     ap.add_argument("--precisions", default=None, help="comma list (default: all)")
-    ap.add_argument("--kernels", default="force,adjoint,batched", help="comma list of force, adjoint, batched")
+    ap.add_argument("--kernels", default="force,adjoint,batched,lj_force",
+                    help="comma list of force, adjoint, batched, lj_force")
     ap.add_argument("--merge", default=None, help="existing table: keep its entries for everything not re-tuned")
     ap.add_argument("--force-buckets", default=None, help="comma list of particle counts for the force buckets")
     args = ap.parse_args()
@@ -204,6 +219,10 @@ def main():
     if "batched" in kernels:
         for p in precs:
             entries += tune_batched(nb, torch, p, log)
+    if "lj_force" in kernels:
+        lb = [int(x) for x in args.force_buckets.split(",")] if args.force_buckets else LJ_BUCKETS
+        for p in precs:
+            entries += tune_force(nb, torch, p, lb, log, law="lj")
     if args.merge and os.path.exists(args.merge):
         with open(args.merge) as f:
             old = json.load(f).get("entries", [])

@@ -185,7 +185,20 @@ int adj_comp(int prec) { return prec == NBODY_FP32_COMP || prec == NBODY_FP32_DS
 size_t jvec_bytes(int prec) { return is_fp64(prec) ? 32 : is_ds(prec) ? 32 : 16; }
 size_t jadj_bytes(int prec) { return is_fp64(prec) ? 64 : 32; }
 
+// The Lennard-Jones force kernels share the gravity kernels' variants (the pair law
+// is a template parameter of the same tiles); only their tile-table entries differ.
+int base_kernel(int kernel) {
+  return kernel == NBODY_KERNEL_LJ_FORCE ? NBODY_KERNEL_FORCE
+         : kernel == NBODY_KERNEL_LJ_FORCE_BATCHED ? NBODY_KERNEL_FORCE_BATCHED : kernel;
+}
+int force_kernel_id(int law, bool batched) {
+  if (law == LAW_LJ) return batched ? NBODY_KERNEL_LJ_FORCE_BATCHED : NBODY_KERNEL_LJ_FORCE;
+  return batched ? NBODY_KERNEL_FORCE_BATCHED : NBODY_KERNEL_FORCE;
+}
+constexpr int kNumKernels = 6;
+
 int num_variants(int kernel, int prec) {
+  kernel = base_kernel(kernel);
   bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
   if (kernel == NBODY_KERNEL_FORCE && !is_fp64(prec)) return kNumForce32 + kNumSym32;
   if (f) return is_fp64(prec) ? kNumForce64 : kNumForce32;
@@ -194,11 +207,13 @@ int num_variants(int kernel, int prec) {
 
 // Symmetric variant index (or -1) of a FORCE tile variant.
 int sym_index(int kernel, int prec, int v) {
+  kernel = base_kernel(kernel);
   if (kernel != NBODY_KERNEL_FORCE || is_fp64(prec) || v < kNumForce32) return -1;
   return v - kNumForce32;
 }
 
 void variant_shape(int kernel, int prec, int v, int& bs, int& i, int& tj) {
+  kernel = base_kernel(kernel);
   bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
   int sv = sym_index(kernel, prec, v);
   if (sv >= 0) {
@@ -243,6 +258,7 @@ int num_cu() {
 // Built-in defaults: one lane per i-particle; the j-range is split until the grid
 // holds about 8 blocks per CU; batched j-chunks of 1024.
 Tile default_tile(int kernel, int prec, int64_t n) {
+  kernel = base_kernel(kernel);
   Tile t{};
   bool batched = kernel == NBODY_KERNEL_FORCE_BATCHED || kernel == NBODY_KERNEL_ADJOINT_BATCHED;
   t.variant = 0;
@@ -271,7 +287,20 @@ Tile default_tile(int kernel, int prec, int64_t n) {
   return t;
 }
 
+Tile lookup_tile(int kernel, int prec, int64_t n);
+
+// Entry of the table for exactly this kernel id (no fallback); false when none matches.
+bool find_entry(int kernel, int prec, int64_t n, Tile& out);
+
 Tile lookup_tile(int kernel, int prec, int64_t n) {
+  Tile t;
+  if (find_entry(kernel, prec, n, t)) return t;
+  // a Lennard-Jones kernel without its own entry runs with the gravity kernel's tile
+  if (base_kernel(kernel) != kernel && find_entry(base_kernel(kernel), prec, n, t)) return t;
+  return default_tile(kernel, prec, n);
+}
+
+bool find_entry(int kernel, int prec, int64_t n, Tile& out) {
   std::lock_guard<std::mutex> lk(g_table_mu);
   for (const auto& e : g_table) {
     if (e.kernel == kernel && e.precision == prec && n >= e.n_min && n <= e.n_max &&
@@ -281,12 +310,14 @@ Tile lookup_tile(int kernel, int prec, int64_t n) {
       t.sym = sym_index(kernel, prec, t.variant);
       variant_shape(kernel, prec, t.variant, t.bs, t.i, t.tj);
       t.j_split = t.sym >= 0 ? 1 : e.j_split;
-      bool batched = kernel == NBODY_KERNEL_FORCE_BATCHED || kernel == NBODY_KERNEL_ADJOINT_BATCHED;
+      const int bk = base_kernel(kernel);
+      bool batched = bk == NBODY_KERNEL_FORCE_BATCHED || bk == NBODY_KERNEL_ADJOINT_BATCHED;
       if (batched) t.j_split = std::max<int64_t>(t.tj, cdiv(t.j_split, t.tj) * t.tj);
-      return t;
+      out = t;
+      return true;
     }
   }
-  return default_tile(kernel, prec, n);
+  return false;
 }
 
 // Effective number of j-ranges and their length (a multiple of TJ).
@@ -409,8 +440,11 @@ int64_t max_nsplit(const UnitSet& us) {
 
 enum Need : unsigned { NEED_FORCE = 1, NEED_ENERGY = 2, NEED_ROLLOUT = 4, NEED_BACKWARD = 8 };
 
+// Workspace layout of a call. The force regions are sized for the larger of the two
+// pair laws' tiles, so one size (nbody_workspace_size) serves both; the batched work
+// units are those of `law`.
 int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ckpt_every, unsigned need,
-              Plan& p, UnitSet* uf, UnitSet* ua) {
+              Plan& p, UnitSet* uf, UnitSet* ua, int law = LAW_GRAV) {
   const int prec = cfg->precision;
   const bool bat = sys.S > 1;
   const bool loop = bat && (cfg->flags & NBODY_FLAG_LOOP_SYSTEMS);
@@ -442,10 +476,15 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     split_geometry(t, ns, S, jc);
     return S > 1 ? (size_t)S * 8 * nd : 0;
   };
+  int64_t units_cap = 0;  // work-unit slots reserved for the force pass (either law)
   if (bat && !loop) {
-    Tile tf = lookup_tile(NBODY_KERNEL_FORCE_BATCHED, prec, sys.max_n);
-    build_units(sys, tf, ufs);
-    force_S = max_nsplit(ufs);
+    for (int lw : {LAW_GRAV, LAW_LJ}) {
+      UnitSet tmp;
+      build_units(sys, lookup_tile(force_kernel_id(lw, true), prec, sys.max_n), tmp);
+      force_S = std::max(force_S, max_nsplit(tmp));
+      units_cap = std::max<int64_t>(units_cap, (int64_t)tmp.units.size());
+      if (lw == law) ufs = std::move(tmp);
+    }
     force_part = (size_t)force_S * 4 * nd;  // the persistent kernels always write partials
     p.n_units_force = (int64_t)ufs.units.size();
     if (need & NEED_BACKWARD) {
@@ -458,19 +497,21 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     p.off_meta = off;
     p.off_sysoff = take((sys.S + 1) * sizeof(int64_t));
     p.off_nsplit = take(2 * sys.S * sizeof(int32_t));  // force then adjoint split counts
-    p.off_units = take((size_t)(p.n_units_force + p.n_units_adj) * sizeof(WorkUnit));
+    p.off_units = take((size_t)(units_cap + p.n_units_adj) * sizeof(WorkUnit));
     p.off_counter = take(2 * sizeof(int32_t));
     p.sz_meta = off - p.off_meta;
   } else if (loop) {
     for (int64_t s = 0; s < sys.S; ++s) {
       int64_t ns = sys.off[s + 1] - sys.off[s];
       if (ns == 0) continue;
-      force_part = std::max(force_part, single_force_part(lookup_tile(NBODY_KERNEL_FORCE, prec, ns), ns));
+      for (int lw : {LAW_GRAV, LAW_LJ})
+        force_part = std::max(force_part, single_force_part(lookup_tile(force_kernel_id(lw, false), prec, ns), ns));
       if (need & NEED_BACKWARD)
         adj_part = std::max(adj_part, single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns), ns));
     }
   } else {
-    force_part = single_force_part(lookup_tile(NBODY_KERNEL_FORCE, prec, n), n);
+    for (int lw : {LAW_GRAV, LAW_LJ})
+      force_part = std::max(force_part, single_force_part(lookup_tile(force_kernel_id(lw, false), prec, n), n));
     if (need & NEED_BACKWARD) adj_part = single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, n), n);
   }
   p.sz_jbuf = (size_t)n * std::max(jvec_bytes(prec), (need & NEED_BACKWARD) ? jadj_bytes(prec) : (size_t)0);
@@ -569,7 +610,7 @@ int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsi
   c.st = (hipStream_t)cfg->stream;
   c.bat = c.sys.S > 1;
   c.loop = c.bat && (cfg->flags & NBODY_FLAG_LOOP_SYSTEMS);
-  TRY(make_plan(cfg, c.sys, n, ckpt_every, need, c.plan, &c.uf, &c.ua));
+  TRY(make_plan(cfg, c.sys, n, ckpt_every, need, c.plan, &c.uf, &c.ua, c.law));
   if (n == 0) return NBODY_OK;
   if (!cfg->workspace) return fail(NBODY_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", c.plan.total);
   if (((uintptr_t)cfg->workspace) % kAlign)
@@ -695,7 +736,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
   auto single = [&](int64_t b, int64_t e) -> int {
     const int64_t ns = e - b;
     if (ns == 0) return NBODY_OK;
-    Tile t = lookup_tile(NBODY_KERNEL_FORCE, prec, ns);
+    Tile t = lookup_tile(force_kernel_id(law, false), prec, ns);
     if (t.sym >= 0) {
       const SymVariant& sv = kSym32[t.sym];
       const int64_t nb = cdiv(ns, (int64_t)t.tj);
@@ -742,7 +783,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
     return NBODY_OK;
   }
   // batched persistent launch
-  Tile t = lookup_tile(NBODY_KERNEL_FORCE_BATCHED, prec, c.sys.max_n);
+  Tile t = lookup_tile(force_kernel_id(law, true), prec, c.sys.max_n);
   const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
   TRY(check_part(c, (size_t)max_nsplit(c.uf) * 4 * n * sizeof(double), "force_batched_kernel"));
   int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter);
@@ -1104,7 +1145,7 @@ __attribute__((visibility("default"))) int nbody_set_tile_table(const nbody_tile
   if (count < 0 || (count > 0 && !entries)) return fail(NBODY_ERR_INVALID_ARG, "bad tile table");
   for (int64_t k = 0; k < count; ++k) {
     const auto& e = entries[k];
-    if (e.kernel < 0 || e.kernel > 3) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad kernel", (long long)k);
+    if (e.kernel < 0 || e.kernel >= kNumKernels) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad kernel", (long long)k);
     if (e.precision < 0 || e.precision > 3) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad precision", (long long)k);
     if (e.variant < 0 || e.variant >= num_variants(e.kernel, e.precision))
       return fail(NBODY_ERR_INVALID_ARG, "entry %lld: variant %d out of range", (long long)k, e.variant);
@@ -1118,7 +1159,7 @@ __attribute__((visibility("default"))) int nbody_set_tile_table(const nbody_tile
 __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, int32_t precision, char* buf,
                                                                size_t cap) {
   g_err.clear();
-  if (kernel < 0 || kernel > 3 || precision < 0 || precision > 3) {
+  if (kernel < 0 || kernel >= kNumKernels || precision < 0 || precision > 3) {
     fail(NBODY_ERR_INVALID_ARG, "bad kernel/precision");
     return -1;
   }
@@ -1144,7 +1185,7 @@ __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, i
 __attribute__((visibility("default"))) int nbody_tile_lookup(int32_t kernel, int32_t precision, int64_t n,
                                                              int32_t* variant, int32_t* j_split) {
   g_err.clear();
-  if (kernel < 0 || kernel > 3 || precision < 0 || precision > 3 || !variant || !j_split)
+  if (kernel < 0 || kernel >= kNumKernels || precision < 0 || precision > 3 || !variant || !j_split)
     return fail(NBODY_ERR_INVALID_ARG, "bad arguments");
   Tile t = lookup_tile(kernel, precision, n);
   *variant = t.variant;

@@ -697,6 +697,8 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
   }
 }
 
+// ----------------------------------------------------------------- symmetric pass: per-particle reduction
+
 // Sum of the nb float slots of every particle in double (fixed order), scaled by the
 // law's constants; optional potential and closing half-kick.
 // n: particles of the system (partial plane stride); stride: plane stride of acc/vel.
