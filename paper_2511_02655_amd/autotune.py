@@ -167,7 +167,7 @@ def tune_batched(nb, torch, precision, log, n_systems=512):
                                  offsets=off)
             g = torch.ones_like(pos)
         for v in range(len(descs)):
-            for jc in BATCH_JCHUNK:
+            for jc in ([1] if "sym=" in descs[v] else BATCH_JCHUNK):  # symmetric units: whole tiles
                 nb.set_tile_table([dict(kernel=kernel, precision=precision, n_min=0, n_max=1 << 40, variant=v,
                                         j_split=jc)])
                 if kernel == "force_batched":

@@ -154,17 +154,28 @@ template <int W, int I, bool POT, int MODE, int ROT, int LAW>
 void launch_sym(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part) {
   hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE, ROT, LAW>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
 }
+using SymBatchedFn = void (*)(dim3, hipStream_t, const float4* jarr, const SymUnit* units, int32_t n_units,
+                              int32_t* counter, float eps2, float* part);
+template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+void launch_sym_batched(dim3 g, hipStream_t st, const float4* jarr, const SymUnit* units, int32_t n_units,
+                        int32_t* counter, float eps2, float* part) {
+  hipLaunchKernelGGL((force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW>), g, dim3(W * 64), 0, st, jarr, units,
+                     n_units, counter, eps2, part);
+}
+template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+const void* sym_batched_ptr() { return (const void*)&force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW>; }
 struct SymVariant {
   int w, i, rot;      // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
   SymFn fn[2][2][3];  // [law][pot][mode]
+  SymBatchedFn bfn[2][2][3];
+  const void* (*bptr[2][2][3])();
 };
-#define SV32_POT(W, I, R, POT, LAW) \
-  { launch_sym<W, I, POT, 0, R, LAW>, launch_sym<W, I, POT, 1, R, LAW>, launch_sym<W, I, POT, 2, R, LAW> }
-#define SV32(W, I, R)                                                                                     \
-  SymVariant {                                                                                            \
-    W, I, R, {{SV32_POT(W, I, R, false, 0), SV32_POT(W, I, R, true, 0)},                                   \
-              {SV32_POT(W, I, R, false, 1), SV32_POT(W, I, R, true, 1)}}                                   \
-  }
+#define SV32_POT(F, W, I, R, POT, LAW) { F<W, I, POT, 0, R, LAW>, F<W, I, POT, 1, R, LAW>, F<W, I, POT, 2, R, LAW> }
+#define SV32_ALL(F, W, I, R)                                                                              \
+  {{SV32_POT(F, W, I, R, false, 0), SV32_POT(F, W, I, R, true, 0)},                                       \
+   {SV32_POT(F, W, I, R, false, 1), SV32_POT(F, W, I, R, true, 1)}}
+#define SV32(W, I, R) \
+  SymVariant { W, I, R, SV32_ALL(launch_sym, W, I, R), SV32_ALL(launch_sym_batched, W, I, R), SV32_ALL(sym_batched_ptr, W, I, R) }
 const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4, 2, 0), SV32(2, 4, 0),
                              SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1), SV32(2, 4, 1),
                              SV32(4, 2, 1), SV32(2, 2, 1)};
@@ -200,7 +211,7 @@ constexpr int kNumKernels = 6;
 int num_variants(int kernel, int prec) {
   kernel = base_kernel(kernel);
   bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
-  if (kernel == NBODY_KERNEL_FORCE && !is_fp64(prec)) return kNumForce32 + kNumSym32;
+  if (f && !is_fp64(prec)) return kNumForce32 + kNumSym32;
   if (f) return is_fp64(prec) ? kNumForce64 : kNumForce32;
   return is_fp64(prec) ? kNumAdj64 : kNumAdj32;
 }
@@ -208,7 +219,8 @@ int num_variants(int kernel, int prec) {
 // Symmetric variant index (or -1) of a FORCE tile variant.
 int sym_index(int kernel, int prec, int v) {
   kernel = base_kernel(kernel);
-  if (kernel != NBODY_KERNEL_FORCE || is_fp64(prec) || v < kNumForce32) return -1;
+  if ((kernel != NBODY_KERNEL_FORCE && kernel != NBODY_KERNEL_FORCE_BATCHED) || is_fp64(prec) || v < kNumForce32)
+    return -1;
   return v - kNumForce32;
 }
 
@@ -386,7 +398,7 @@ int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys, bool law_checks 
 struct Plan {
   // batched metadata
   size_t off_meta = 0, sz_meta = 0;
-  size_t off_sysoff = 0, off_nsplit = 0, off_units = 0, off_counter = 0;
+  size_t off_sysoff = 0, off_nsplit = 0, off_partoff = 0, off_units = 0, off_units_adj = 0, off_counter = 0;
   int64_t n_units_force = 0, n_units_adj = 0;
   // buffers
   size_t off_jbuf = 0, sz_jbuf = 0;
@@ -401,8 +413,14 @@ struct Plan {
 };
 
 struct UnitSet {
-  std::vector<WorkUnit> units;
-  std::vector<int32_t> nsplit;
+  std::vector<WorkUnit> units;     // one-sided units (i-tile x j-chunk)
+  std::vector<int32_t> nsplit;     // per system: j-chunks (one-sided) or blocks nb (symmetric)
+  std::vector<SymUnit> sym_units;  // symmetric units (tile (A, B) of one system)
+  std::vector<int64_t> part_off;   // symmetric: float offset of each system's partial planes
+  int64_t part_floats = 0;         // symmetric: floats of all systems' partial planes
+  bool sym = false;
+  int64_t count() const { return sym ? (int64_t)sym_units.size() : (int64_t)units.size(); }
+  size_t unit_bytes() const { return sym ? sym_units.size() * sizeof(SymUnit) : units.size() * sizeof(WorkUnit); }
 };
 
 // Work units of a batched pass: i-tiles of bs*i particles x j-chunks of jc particles
@@ -429,6 +447,42 @@ void build_units(const Systems& sys, const Tile& t, UnitSet& us) {
   }
   std::stable_sort(us.units.begin(), us.units.end(), [](const WorkUnit& a, const WorkUnit& b) {
     return (a.ie - a.ib) * (a.je - a.jb) > (b.ie - b.ib) * (b.je - b.jb);
+  });
+}
+
+// Symmetric units of a batched pass: every upper-triangle tile (A, B) of blocks of
+// t.tj particles inside each system, sorted by decreasing pair count.
+void build_sym_units(const Systems& sys, const Tile& t, UnitSet& us) {
+  us = UnitSet{};
+  us.sym = true;
+  us.nsplit.assign(sys.S, 0);
+  us.part_off.assign(sys.S + 1, 0);
+  const int64_t bi = t.tj;
+  int64_t off = 0;
+  for (int64_t s = 0; s < sys.S; ++s) {
+    const int64_t b = sys.off[s], ns = sys.off[s + 1] - b;
+    us.part_off[s] = off;
+    if (ns == 0) continue;
+    const int64_t nb = cdiv(ns, bi);
+    us.nsplit[s] = (int32_t)nb;
+    for (int64_t A = 0; A < nb; ++A)
+      for (int64_t B = A; B < nb; ++B) {
+        SymUnit u{};
+        u.base = b;
+        u.part_off = off;
+        u.n = (int32_t)ns;
+        u.nb = (int32_t)nb;
+        u.A = (int32_t)A;
+        u.B = (int32_t)B;
+        us.sym_units.push_back(u);
+      }
+    off += nb * 4 * ns;
+  }
+  us.part_off[sys.S] = off;
+  us.part_floats = off;
+  auto rows = [bi](const SymUnit& u, int32_t X) { return std::min<int64_t>(bi, (int64_t)u.n - (int64_t)X * bi); };
+  std::stable_sort(us.sym_units.begin(), us.sym_units.end(), [&](const SymUnit& a, const SymUnit& b) {
+    return rows(a, a.A) * rows(a, a.B) > rows(b, b.A) * rows(b, b.B);
   });
 }
 
@@ -476,17 +530,24 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     split_geometry(t, ns, S, jc);
     return S > 1 ? (size_t)S * 8 * nd : 0;
   };
-  int64_t units_cap = 0;  // work-unit slots reserved for the force pass (either law)
+  size_t units_bytes = 0;  // force work-unit bytes reserved (either law, either unit kind)
   if (bat && !loop) {
     for (int lw : {LAW_GRAV, LAW_LJ}) {
       UnitSet tmp;
-      build_units(sys, lookup_tile(force_kernel_id(lw, true), prec, sys.max_n), tmp);
-      force_S = std::max(force_S, max_nsplit(tmp));
-      units_cap = std::max<int64_t>(units_cap, (int64_t)tmp.units.size());
+      const Tile tf = lookup_tile(force_kernel_id(lw, true), prec, sys.max_n);
+      if (tf.sym >= 0) {
+        build_sym_units(sys, tf, tmp);
+        force_part = std::max(force_part, (size_t)tmp.part_floats * sizeof(float));
+      } else {
+        build_units(sys, tf, tmp);
+        force_S = std::max(force_S, max_nsplit(tmp));
+        force_part = std::max(force_part, (size_t)max_nsplit(tmp) * 4 * nd);  // persistent kernels always write partials
+      }
+      units_bytes = std::max(units_bytes, tmp.unit_bytes());
       if (lw == law) ufs = std::move(tmp);
     }
-    force_part = (size_t)force_S * 4 * nd;  // the persistent kernels always write partials
-    p.n_units_force = (int64_t)ufs.units.size();
+    p.n_units_force = ufs.count();
+    if (p.n_units_force > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many batched work units");
     if (need & NEED_BACKWARD) {
       Tile ta = lookup_tile(NBODY_KERNEL_ADJOINT_BATCHED, prec, sys.max_n);
       build_units(sys, ta, uas);
@@ -497,7 +558,9 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     p.off_meta = off;
     p.off_sysoff = take((sys.S + 1) * sizeof(int64_t));
     p.off_nsplit = take(2 * sys.S * sizeof(int32_t));  // force then adjoint split counts
-    p.off_units = take((size_t)(units_cap + p.n_units_adj) * sizeof(WorkUnit));
+    p.off_partoff = take((sys.S + 1) * sizeof(int64_t));
+    p.off_units = take(units_bytes);
+    p.off_units_adj = take((size_t)p.n_units_adj * sizeof(WorkUnit));
     p.off_counter = take(2 * sizeof(int32_t));
     p.sz_meta = off - p.off_meta;
   } else if (loop) {
@@ -634,8 +697,10 @@ int upload_meta(Ctx& c) {
   const int64_t S = c.sys.S;
   const size_t b_off = (S + 1) * sizeof(int64_t);
   const size_t b_ns = 2 * S * sizeof(int32_t);
-  const size_t b_units = (c.uf.units.size() + c.ua.units.size()) * sizeof(WorkUnit);
-  const size_t total = align_up(b_off) + align_up(b_ns) + align_up(b_units);
+  const size_t b_poff = c.uf.sym ? (S + 1) * sizeof(int64_t) : 0;
+  const size_t b_units = c.uf.unit_bytes();
+  const size_t b_uadj = c.ua.units.size() * sizeof(WorkUnit);
+  const size_t total = align_up(b_off) + align_up(b_ns) + align_up(b_poff) + align_up(b_units) + align_up(b_uadj);
   std::lock_guard<std::mutex> lk(g_stage_mu);
   if (g_stage_done) HIP_TRY(hipEventSynchronize(g_stage_done));  // previous upload has read the staging
   if (total > g_stage_bytes) {
@@ -649,18 +714,23 @@ int upload_meta(Ctx& c) {
   char* h = (char*)g_stage;
   int64_t* h_off = (int64_t*)h;
   int32_t* h_ns = (int32_t*)(h + align_up(b_off));
-  WorkUnit* h_units = (WorkUnit*)(h + align_up(b_off) + align_up(b_ns));
+  int64_t* h_poff = (int64_t*)(h + align_up(b_off) + align_up(b_ns));
+  char* h_units = h + align_up(b_off) + align_up(b_ns) + align_up(b_poff);
+  char* h_uadj = h_units + align_up(b_units);
   std::memcpy(h_off, c.sys.off, b_off);
   for (int64_t s = 0; s < S; ++s) {
     h_ns[s] = c.uf.nsplit.empty() ? 0 : c.uf.nsplit[s];
     h_ns[S + s] = c.ua.nsplit.empty() ? 0 : c.ua.nsplit[s];
   }
-  if (!c.uf.units.empty()) std::memcpy(h_units, c.uf.units.data(), c.uf.units.size() * sizeof(WorkUnit));
-  if (!c.ua.units.empty())
-    std::memcpy(h_units + c.uf.units.size(), c.ua.units.data(), c.ua.units.size() * sizeof(WorkUnit));
+  if (b_poff) std::memcpy(h_poff, c.uf.part_off.data(), b_poff);
+  if (b_units) std::memcpy(h_units, c.uf.sym ? (const void*)c.uf.sym_units.data() : (const void*)c.uf.units.data(),
+                           b_units);
+  if (b_uadj) std::memcpy(h_uadj, c.ua.units.data(), b_uadj);
   HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_sysoff, h_off, b_off, hipMemcpyHostToDevice, c.st));
   HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_nsplit, h_ns, b_ns, hipMemcpyHostToDevice, c.st));
+  if (b_poff) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_partoff, h_poff, b_poff, hipMemcpyHostToDevice, c.st));
   if (b_units) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_units, h_units, b_units, hipMemcpyHostToDevice, c.st));
+  if (b_uadj) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_units_adj, h_uadj, b_uadj, hipMemcpyHostToDevice, c.st));
   HIP_TRY(hipEventRecord(g_stage_done, c.st));
   return NBODY_OK;
 }
@@ -784,9 +854,29 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
   }
   // batched persistent launch
   Tile t = lookup_tile(force_kernel_id(law, true), prec, c.sys.max_n);
+  int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter);
+  if (t.sym >= 0) {
+    // symmetric tiles of every system; the unit list was built from the same tile
+    if (!c.uf.sym) return fail(NBODY_ERR_DEVICE, "internal: symmetric batched tile without symmetric units");
+    TRY(check_part(c, (size_t)c.uf.part_floats * sizeof(float), "force_sym_batched_kernel"));
+    const SymVariant& sv = kSym32[t.sym];
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)2, 0);
+    LAUNCH_CHECK("fill_i32");
+    unsigned grid;
+    persistent_grid(sv.bptr[law][pot_on][mode](), sv.w * 64, c.plan.n_units_force, grid);
+    float* pf = (float*)(c.ws + c.plan.off_part);
+    sv.bfn[law][pot_on][mode](dim3(grid), c.st, (const float4*)jarr, (const SymUnit*)(c.ws + c.plan.off_units),
+                              (int32_t)c.plan.n_units_force, counter, (float)eps2, pf);
+    LAUNCH_CHECK("force_sym_batched_kernel");
+    hipLaunchKernelGGL(reduce_sym_batched, grid1d(n), dim3(256), 0, c.st, n, c.sys.S,
+                       (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit),
+                       (const int64_t*)(c.ws + c.plan.off_partoff), (const float*)pf, c.ls, acc, pot, vel, hh);
+    LAUNCH_CHECK("reduce_sym_batched");
+    return NBODY_OK;
+  }
+  if (c.uf.sym) return fail(NBODY_ERR_DEVICE, "internal: one-sided batched tile with symmetric units");
   const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
   TRY(check_part(c, (size_t)max_nsplit(c.uf) * 4 * n * sizeof(double), "force_batched_kernel"));
-  int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter);
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)2, 0);
   LAUNCH_CHECK("fill_i32");
   unsigned grid;
@@ -895,7 +985,7 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
   o.G = c.cfg->G;
   o.n_plane = n;
   o.part = part;
-  av.bfn[comp](dim3(grid), c.st, jadj, (const WorkUnit*)(c.ws + c.plan.off_units) + c.plan.n_units_force,
+  av.bfn[comp](dim3(grid), c.st, jadj, (const WorkUnit*)(c.ws + c.plan.off_units_adj),
                (int32_t)c.plan.n_units_adj, counter, eps2, o);
   LAUNCH_CHECK("adjoint_batched_kernel");
   const int32_t* nsplit_adj = (const int32_t*)(c.ws + c.plan.off_nsplit) + c.sys.S;

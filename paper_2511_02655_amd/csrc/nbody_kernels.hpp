@@ -493,19 +493,20 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 // Output: float partial sums part[(slot*4 + c)*n + p], c = ax, ay, az, phi: the
 // i-side of tile (A, B) goes to slot B, the j-side to slot A, so every particle owns
 // exactly nb slots, summed in double (fixed order) by reduce_sym.
+//
+// One tile (A, B) of a system of n particles (jarr and part point at the system's own
+// j-array and partial planes); red is the workgroup's LDS for the cross-wave j sums.
 template <int W, int I, bool POT, int MODE, int ROT, int LAW>
-__global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restrict__ jarr, int64_t n, int32_t nb,
-                                                           float eps2_arg, float* __restrict__ part) {
+__device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_t n, int32_t A, int32_t B,
+                                         float eps2_arg, float* __restrict__ part,
+                                         float (&red)[2][W][POT ? 4 : 3][64]) {
   constexpr bool COMP = MODE != MODE_PLAIN;
   constexpr bool DS = MODE == MODE_DS;
   constexpr int NV = DS ? 2 : 1;
   constexpr int BI = W * 64 * I;
   constexpr int NC = POT ? 4 : 3;
   constexpr int NSUB = BI / 64;
-  __shared__ float red[2][W][NC][64];
 
-  int32_t A, B;
-  tile_rc(blockIdx.x, nb, A, B);
   const bool diag = (A == B);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rot_src = ((lane - 1) & 63) << 2;  // rotation source lane (byte address) for ROT = 1
@@ -542,9 +543,16 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
     nxt = j < n ? jarr[NV * j] : jpad;
     if constexpr (DS) nxtl = j < n ? jarr[NV * j + 1] : zero;
   }
-  for (int sb = 0; sb < NSUB; ++sb) {
+  // Only the sub-blocks of block B that hold particles are visited (block B is ragged
+  // when it is the system's last). Off-diagonal tiles have A < B, so block A is full and
+  // every wave has real i-particles; on a diagonal tile a wave whose i-particles are all
+  // past the end has nothing to do (that path has no workgroup barrier).
+  const int64_t jrows = n - Bbase;
+  const int nsub_b = jrows >= BI ? NSUB : (int)((jrows + 63) >> 6);
+  const int nsub = (diag && Abase + (int64_t)w * 64 * I >= n) ? 0 : nsub_b;
+  for (int sb = 0; sb < nsub; ++sb) {
     const float4 q = nxt, ql = nxtl;
-    if (sb + 1 < NSUB) {
+    if (sb + 1 < nsub) {
       const int64_t j = Bbase + (int64_t)(sb + 1) * 64 + lane;
       nxt = j < n ? jarr[NV * j] : jpad;
       if constexpr (DS) nxtl = j < n ? jarr[NV * j + 1] : zero;
@@ -697,6 +705,16 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
   }
 }
 
+// Single system: one workgroup per tile t of the nb(nb+1)/2 upper-triangle tiles.
+template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+__global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restrict__ jarr, int64_t n, int32_t nb,
+                                                           float eps2_arg, float* __restrict__ part) {
+  __shared__ float red[2][W][POT ? 4 : 3][64];
+  int32_t A, B;
+  tile_rc(blockIdx.x, nb, A, B);
+  sym_tile<W, I, POT, MODE, ROT, LAW>(jarr, n, A, B, eps2_arg, part, red);
+}
+
 // ----------------------------------------------------------------- symmetric pass: per-particle reduction
 
 // Sum of the nb float slots of every particle in double (fixed order), scaled by the
@@ -716,6 +734,69 @@ __global__ void reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* _
     const double ac = ls.ca * a[c] / md;
     acc[c * stride + i] = ac;
     if (vel) vel[c * stride + i] += hh * ac;
+  }
+  if (pot) pot[i] = ls.cp * a[3] / md;
+}
+
+// ----------------------------------------------------------------- batched symmetric pass
+
+// One symmetric work unit: tile (A, B) of the system whose particles start at global
+// index base; its partial planes ([nb][4][n] floats) start at float offset part_off.
+struct SymUnit {
+  int64_t base;
+  int64_t part_off;
+  int32_t n, nb;
+  int32_t A, B;
+};
+
+// Persistent grid over the symmetric tiles of many systems (units sorted by decreasing
+// cost on the host), pulled from a shared counter that must be 0 at launch. Each tile
+// writes its own partial slots, so the result does not depend on which block ran it.
+template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+__global__ __launch_bounds__(W * 64) void force_sym_batched_kernel(const float4* __restrict__ jarr,
+                                                                   const SymUnit* __restrict__ units,
+                                                                   int32_t n_units, int32_t* __restrict__ counter,
+                                                                   float eps2_arg, float* __restrict__ part) {
+  constexpr int NV = MODE == MODE_DS ? 2 : 1;
+  __shared__ float red[2][W][POT ? 4 : 3][64];
+  __shared__ int32_t next;
+  for (;;) {
+    __syncthreads();  // everyone has finished with the previous unit (and its LDS sums)
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int32_t u = next;
+    if (u >= n_units) break;
+    const SymUnit su = units[u];
+    sym_tile<W, I, POT, MODE, ROT, LAW>(jarr + NV * su.base, su.n, su.A, su.B, eps2_arg, part + su.part_off, red);
+  }
+}
+
+// Per-particle sum of the batched symmetric partials: particle i of system s (found by
+// binary search in sys_off) sums the nb_s float slots of its system's planes in double.
+__global__ void reduce_sym_batched(int64_t n, int64_t n_sys, const int64_t* __restrict__ sys_off,
+                                   const int32_t* __restrict__ sys_nb, const int64_t* __restrict__ sys_part,
+                                   const float* __restrict__ part, LawScale ls, double* __restrict__ acc,
+                                   double* __restrict__ pot, double* __restrict__ vel, double hh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t lo = 0, hi = n_sys;  // s with sys_off[s] <= i < sys_off[s+1]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (sys_off[mid] <= i) lo = mid; else hi = mid;
+  }
+  const int64_t b = sys_off[lo], ns = sys_off[lo + 1] - b, li = i - b;
+  const int32_t nb = sys_nb[lo];
+  const float* ps = part + sys_part[lo];
+  const int nc = pot ? 4 : 3;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t k = 0; k < nb; ++k)
+    for (int c = 0; c < nc; ++c) a[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
+  const double md = law_div(ls, i);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double ac = ls.ca * a[c] / md;
+    acc[c * n + i] = ac;
+    if (vel) vel[c * n + i] += hh * ac;
   }
   if (pot) pot[i] = ls.cp * a[3] / md;
 }

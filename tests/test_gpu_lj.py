@@ -266,6 +266,33 @@ def test_lj_batched_vs_oracle_and_loop(nb, oracle):
             check_lj(accl[:, sl], potl[sl], a_ref, p_ref, pos[:, sl], mass[sl], prec)
 
 
+def test_lj_batched_symmetric(nb, oracle):
+    """Lennard-Jones gases of uneven sizes on the batched symmetric pass (two variants)."""
+    sizes = [1, 300, 0, 1500, 700, 2]
+    parts = [_gas(k, 950 + i) if k else (np.zeros((3, 0)), np.zeros(0), None, None) for i, k in enumerate(sizes)]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    pos = np.concatenate([p[0] for p in parts], axis=1)
+    mass = np.concatenate([p[1] for p in parts])
+    refs = [oracle.lj_forces(pos[:, off[k]:off[k + 1]], mass[off[k]:off[k + 1]]) for k in range(len(sizes))]
+    variants = [k for k, d in enumerate(nb.tile_variants("lj_force_batched", "fp32c")) if "sym=" in d]
+    try:
+        for v in (variants[0], variants[-1]):
+            nb.set_tile_table([dict(kernel="lj_force_batched", precision=p, n_min=0, n_max=1 << 40, variant=v,
+                                    j_split=1) for p in ("fp32c", "fp32ds")])
+            for prec in ("fp32c", "fp32ds"):
+                acc, pot = nb.lj_forces(dev(pos), dev(mass), precision=prec, want_pot=True, offsets=off)
+                acc, pot = host(acc), host(pot)
+                assert np.all(np.isfinite(acc)) and np.all(np.isfinite(pot))
+                for k in range(len(sizes)):
+                    if sizes[k] == 0:
+                        continue
+                    sl = slice(off[k], off[k + 1])
+                    check_lj(acc[:, sl], pot[sl], refs[k][0], refs[k][1], pos[:, sl], mass[sl], prec)
+    finally:
+        nb.set_tile_table([])
+
+
 def test_lj_argument_errors(nb):
     pos, mass = dev(np.zeros((3, 4))), dev(np.ones(4))
     with pytest.raises(nb.NBodyError, match="sigma"):

@@ -333,6 +333,77 @@ def test_batched_rollout_energy(nb, oracle):
         np.testing.assert_allclose(tr[:, s, :2], er[:, :2], rtol=1e-11)
 
 
+def test_batched_symmetric_variants(nb, oracle):
+    """The batched symmetric pass (every upper-triangle tile of every system in one
+    persistent launch, float tile partials per system), every variant forced through the
+    tile table, on systems that are empty, single, smaller than a block and several blocks
+    with a ragged edge; against the oracle per system, with and without the potential."""
+    sizes = [0, 1, 2, 63, 130, 0, 700, 2500, 1]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    g = np.random.Generator(np.random.PCG64(77))
+    n = int(off[-1])
+    pos = g.random((3, n))
+    mass = g.uniform(0.5, 1.5, n) / 500
+    refs = [oracle.forces(pos[:, off[k]:off[k + 1]], mass[off[k]:off[k + 1]], eps=1e-2)
+            if sizes[k] else None for k in range(len(sizes))]
+    variants = [k for k, d in enumerate(nb.tile_variants("force_batched", "fp32c")) if "sym=" in d]
+    assert len(variants) >= 8
+    bounds = {(k, p): fp32_bound(pos[:, off[k]:off[k + 1]], mass[off[k]:off[k + 1]], 1e-2,
+                                 accumulate_plain=(p == "fp32"), exact_coords=(p == "fp32ds"))
+              for k in range(len(sizes)) if sizes[k] > 1 for p in ("fp32c", "fp32", "fp32ds")}
+    try:
+        for v in variants:
+            nb.set_tile_table([dict(kernel="force_batched", precision=p, n_min=0, n_max=1 << 40, variant=v,
+                                    j_split=1) for p in ("fp32", "fp32c", "fp32ds")])
+            for prec in ("fp32c", "fp32", "fp32ds"):
+                for want_pot in (True, False):
+                    acc, pot = nb.forces(dev(pos), dev(mass), eps=1e-2, precision=prec, want_pot=want_pot,
+                                         offsets=off)
+                    acc = host(acc)
+                    for k in range(len(sizes)):
+                        if sizes[k] == 0:
+                            continue
+                        sl = slice(off[k], off[k + 1])
+                        if sizes[k] == 1:
+                            assert np.all(acc[:, sl] == 0)
+                            continue
+                        err = np.sqrt(np.sum((acc[:, sl] - refs[k][0]) ** 2, axis=0))
+                        assert np.max(err / bounds[(k, prec)]) <= 1.0, (v, prec, k)
+                        if want_pot:
+                            p_ = host(pot)[sl]
+                            assert np.max(np.abs(p_ - refs[k][1]) / np.abs(refs[k][1])) <= TOL_P[prec], (v, prec)
+    finally:
+        nb.set_tile_table([])
+
+
+def test_batched_symmetric_rollout_matches_looped(nb, oracle):
+    """A 20-step batched rollout on the symmetric batched pass stays within FP32 rounding of
+    the looped single-system path and of the oracle, and is bitwise deterministic."""
+    b = _batch(12, 8, nmin=64, nmax=3000)
+    off = b.offsets
+    variants = [k for k, d in enumerate(nb.tile_variants("force_batched", "fp32c")) if "sym=" in d]
+    try:
+        nb.set_tile_table([dict(kernel="force_batched", precision="fp32c", n_min=0, n_max=1 << 40,
+                                variant=variants[1], j_split=1)])
+        outs = []
+        for rep in range(2):
+            pos, vel, mass = dev(b.pos), dev(b.vel), dev(b.mass)
+            acc, _ = nb.forces(pos, mass, eps=1e-2, precision="fp32c", offsets=off)
+            _, tr = nb.rollout(pos, vel, mass, acc, 1e-3, 20, energy_trace=True, eps=1e-2, precision="fp32c",
+                               offsets=off)
+            outs.append((host(pos), host(tr)))
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    finally:
+        nb.set_tile_table([])
+    x = outs[0][0]
+    for s in range(len(off) - 1):
+        sl = slice(off[s], off[s + 1])
+        xr, _, _, er = oracle.kdk(b.pos[:, sl], b.vel[:, sl], b.mass[sl], 1e-3, 20, eps=1e-2, want_energy=True)
+        assert np.max(np.abs(x[:, sl] - xr)) <= 1e-6 * max(1.0, np.max(np.abs(xr)))
+        np.testing.assert_allclose(outs[0][1][:, s, 1], er[:, 1], rtol=1e-5)
+
+
 # ------------------------------------------------------------------ adjoint
 
 def _rel_l2(a, b):
