@@ -25,7 +25,7 @@ import numpy as np
 FORCE_BUCKETS = [1024, 4096, 16384, 65536, 262144, 1048576]
 LJ_BUCKETS = [1024, 4096, 10000, 32768, 131072]
 SYM_PART_LIMIT = 16.0 * 2 ** 30  # workspace bytes a symmetric tile may ask for
-ADJ_BUCKETS = [1024, 4096, 16384, 65536]
+ADJ_BUCKETS = [1024, 4096, 16384, 65536, 262144]
 J_SPLITS = [1, 2, 4, 8, 16, 32, 64]
 BATCH_JCHUNK = [512, 1024, 2048, 4096]
 
@@ -133,7 +133,10 @@ def tune_adjoint(nb, torch, precision, buckets, log):
         reps = max(1, _reps_for(n) // 2)
         best = None
         for v in range(len(descs)):
-            for js in J_SPLITS:
+            sym = "sym=" in descs[v]
+            if sym and (n < 2048 or -(-n // _sym_edge(descs[v])) * 16.0 * n > SYM_PART_LIMIT):
+                continue
+            for js in ([1] if sym else J_SPLITS):
                 nb.set_tile_table([dict(kernel="adjoint", precision=precision, n_min=0, n_max=1 << 40, variant=v,
                                         j_split=js)])
                 t = _time(lambda: nb.rollout_backward(mass, ckpt, g, g, 1e-3, 1, 1, precision=precision), reps)

@@ -181,6 +181,35 @@ const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4
                              SV32(4, 2, 1), SV32(2, 2, 1)};
 constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
 
+// Symmetric FP32 adjoint variants, indices kNumAdj32 + k in the ADJOINT tables.
+template <int W, int I, bool COMP, int ROT>
+void launch_adj_sym(dim3 g, hipStream_t st, const float4* jadj, int64_t n, int32_t nb, float eps2, float* part) {
+  hipLaunchKernelGGL((adjoint_sym_kernel<W, I, COMP, ROT>), g, dim3(W * 64), 0, st, jadj, n, nb, eps2, part);
+}
+template <int W, int I, bool COMP, int ROT>
+void launch_adj_sym_batched(dim3 g, hipStream_t st, const float4* jadj, const SymUnit* units, int32_t n_units,
+                            int32_t* counter, float eps2, float* part) {
+  hipLaunchKernelGGL((adjoint_sym_batched_kernel<W, I, COMP, ROT>), g, dim3(W * 64), 0, st, jadj, units, n_units,
+                     counter, eps2, part);
+}
+template <int W, int I, bool COMP, int ROT>
+const void* adj_sym_batched_ptr() { return (const void*)&adjoint_sym_batched_kernel<W, I, COMP, ROT>; }
+struct AdjSymVariant {
+  int w, i, rot;
+  SymFn fn[2];  // [comp]
+  SymBatchedFn bfn[2];
+  const void* (*bptr[2])();
+};
+#define SA32(W, I, R)                                                                                     \
+  AdjSymVariant {                                                                                         \
+    W, I, R, {launch_adj_sym<W, I, false, R>, launch_adj_sym<W, I, true, R>},                            \
+        {launch_adj_sym_batched<W, I, false, R>, launch_adj_sym_batched<W, I, true, R>},                 \
+        {adj_sym_batched_ptr<W, I, false, R>, adj_sym_batched_ptr<W, I, true, R>}                        \
+  }
+const AdjSymVariant kAdjSym32[] = {SA32(4, 2, 1), SA32(2, 2, 1), SA32(4, 4, 1), SA32(2, 4, 1), SA32(8, 2, 1),
+                                   SA32(4, 2, 0), SA32(2, 4, 0)};
+constexpr int kNumAdjSym32 = sizeof(kAdjSym32) / sizeof(kAdjSym32[0]);
+
 constexpr int kNumForce32 = sizeof(kForce32) / sizeof(kForce32[0]);
 constexpr int kNumForce64 = sizeof(kForce64) / sizeof(kForce64[0]);
 constexpr int kNumAdj32 = sizeof(kAdj32) / sizeof(kAdj32[0]);
@@ -208,20 +237,33 @@ int force_kernel_id(int law, bool batched) {
 }
 constexpr int kNumKernels = 6;
 
-int num_variants(int kernel, int prec) {
+bool is_force_kernel(int kernel) {
   kernel = base_kernel(kernel);
-  bool f = kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
-  if (f && !is_fp64(prec)) return kNumForce32 + kNumSym32;
-  if (f) return is_fp64(prec) ? kNumForce64 : kNumForce32;
-  return is_fp64(prec) ? kNumAdj64 : kNumAdj32;
+  return kernel == NBODY_KERNEL_FORCE || kernel == NBODY_KERNEL_FORCE_BATCHED;
 }
 
-// Symmetric variant index (or -1) of a FORCE tile variant.
+int num_variants(int kernel, int prec) {
+  const bool f = is_force_kernel(kernel);
+  if (f && !is_fp64(prec)) return kNumForce32 + kNumSym32;
+  if (f) return kNumForce64;
+  return is_fp64(prec) ? kNumAdj64 : kNumAdj32 + kNumAdjSym32;
+}
+
+// Symmetric variant index (or -1) of a tile variant: into kSym32 for the force kernels,
+// into kAdjSym32 for the adjoint kernels (FP32 modes only).
 int sym_index(int kernel, int prec, int v) {
-  kernel = base_kernel(kernel);
-  if ((kernel != NBODY_KERNEL_FORCE && kernel != NBODY_KERNEL_FORCE_BATCHED) || is_fp64(prec) || v < kNumForce32)
-    return -1;
-  return v - kNumForce32;
+  if (is_fp64(prec)) return -1;
+  const int first = is_force_kernel(kernel) ? kNumForce32 : kNumAdj32;
+  return v < first ? -1 : v - first;
+}
+
+// (waves, i-particles per lane, rotation kind) of symmetric variant sv
+void sym_shape(int kernel, int sv, int& w, int& i, int& rot) {
+  if (is_force_kernel(kernel)) {
+    w = kSym32[sv].w; i = kSym32[sv].i; rot = kSym32[sv].rot;
+  } else {
+    w = kAdjSym32[sv].w; i = kAdjSym32[sv].i; rot = kAdjSym32[sv].rot;
+  }
 }
 
 void variant_shape(int kernel, int prec, int v, int& bs, int& i, int& tj) {
@@ -230,7 +272,10 @@ void variant_shape(int kernel, int prec, int v, int& bs, int& i, int& tj) {
   int sv = sym_index(kernel, prec, v);
   if (sv >= 0) {
     // symmetric: block of bs = W*64 threads, i per lane, tile edge tj = W*64*I
-    bs = kSym32[sv].w * 64; i = kSym32[sv].i; tj = bs * i;  // rotation kind: kSym32[sv].rot
+    int w, rot;
+    sym_shape(kernel, sv, w, i, rot);
+    bs = w * 64;
+    tj = bs * i;
     return;
   }
   if (f) {
@@ -398,7 +443,8 @@ int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys, bool law_checks 
 struct Plan {
   // batched metadata
   size_t off_meta = 0, sz_meta = 0;
-  size_t off_sysoff = 0, off_nsplit = 0, off_partoff = 0, off_units = 0, off_units_adj = 0, off_counter = 0;
+  size_t off_sysoff = 0, off_nsplit = 0, off_partoff = 0, off_partoff_adj = 0, off_units = 0, off_units_adj = 0,
+         off_counter = 0;
   int64_t n_units_force = 0, n_units_adj = 0;
   // buffers
   size_t off_jbuf = 0, sz_jbuf = 0;
@@ -452,7 +498,7 @@ void build_units(const Systems& sys, const Tile& t, UnitSet& us) {
 
 // Symmetric units of a batched pass: every upper-triangle tile (A, B) of blocks of
 // t.tj particles inside each system, sorted by decreasing pair count.
-void build_sym_units(const Systems& sys, const Tile& t, UnitSet& us) {
+void build_sym_units(const Systems& sys, const Tile& t, UnitSet& us, int comps) {
   us = UnitSet{};
   us.sym = true;
   us.nsplit.assign(sys.S, 0);
@@ -476,7 +522,7 @@ void build_sym_units(const Systems& sys, const Tile& t, UnitSet& us) {
         u.B = (int32_t)B;
         us.sym_units.push_back(u);
       }
-    off += nb * 4 * ns;
+    off += nb * comps * ns;
   }
   us.part_off[sys.S] = off;
   us.part_floats = off;
@@ -526,6 +572,10 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     return S > 1 ? (size_t)S * 4 * nd : 0;
   };
   auto single_adj_part = [&](const Tile& t, int64_t ns) -> size_t {
+    if (t.sym >= 0) {
+      const int64_t nb = cdiv(ns, (int64_t)t.tj);
+      return (size_t)nb * 4 * (size_t)ns * sizeof(float);
+    }
     int64_t S, jc;
     split_geometry(t, ns, S, jc);
     return S > 1 ? (size_t)S * 8 * nd : 0;
@@ -536,7 +586,7 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
       UnitSet tmp;
       const Tile tf = lookup_tile(force_kernel_id(lw, true), prec, sys.max_n);
       if (tf.sym >= 0) {
-        build_sym_units(sys, tf, tmp);
+        build_sym_units(sys, tf, tmp, 4);
         force_part = std::max(force_part, (size_t)tmp.part_floats * sizeof(float));
       } else {
         build_units(sys, tf, tmp);
@@ -550,17 +600,24 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     if (p.n_units_force > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many batched work units");
     if (need & NEED_BACKWARD) {
       Tile ta = lookup_tile(NBODY_KERNEL_ADJOINT_BATCHED, prec, sys.max_n);
-      build_units(sys, ta, uas);
-      adj_S = max_nsplit(uas);
-      adj_part = (size_t)adj_S * 8 * nd;
-      p.n_units_adj = (int64_t)uas.units.size();
+      if (ta.sym >= 0) {
+        build_sym_units(sys, ta, uas, 4);
+        adj_part = (size_t)uas.part_floats * sizeof(float);
+      } else {
+        build_units(sys, ta, uas);
+        adj_S = max_nsplit(uas);
+        adj_part = (size_t)adj_S * 8 * nd;
+      }
+      p.n_units_adj = uas.count();
+      if (p.n_units_adj > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many batched work units");
     }
     p.off_meta = off;
     p.off_sysoff = take((sys.S + 1) * sizeof(int64_t));
     p.off_nsplit = take(2 * sys.S * sizeof(int32_t));  // force then adjoint split counts
     p.off_partoff = take((sys.S + 1) * sizeof(int64_t));
+    p.off_partoff_adj = take((sys.S + 1) * sizeof(int64_t));
     p.off_units = take(units_bytes);
-    p.off_units_adj = take((size_t)p.n_units_adj * sizeof(WorkUnit));
+    p.off_units_adj = take(uas.unit_bytes());
     p.off_counter = take(2 * sizeof(int32_t));
     p.sz_meta = off - p.off_meta;
   } else if (loop) {
@@ -699,8 +756,10 @@ int upload_meta(Ctx& c) {
   const size_t b_ns = 2 * S * sizeof(int32_t);
   const size_t b_poff = c.uf.sym ? (S + 1) * sizeof(int64_t) : 0;
   const size_t b_units = c.uf.unit_bytes();
-  const size_t b_uadj = c.ua.units.size() * sizeof(WorkUnit);
-  const size_t total = align_up(b_off) + align_up(b_ns) + align_up(b_poff) + align_up(b_units) + align_up(b_uadj);
+  const size_t b_uadj = c.ua.unit_bytes();
+  const size_t b_poffa = c.ua.sym ? (S + 1) * sizeof(int64_t) : 0;
+  const size_t total = align_up(b_off) + align_up(b_ns) + align_up(b_poff) + align_up(b_units) + align_up(b_uadj) +
+                       align_up(b_poffa);
   std::lock_guard<std::mutex> lk(g_stage_mu);
   if (g_stage_done) HIP_TRY(hipEventSynchronize(g_stage_done));  // previous upload has read the staging
   if (total > g_stage_bytes) {
@@ -717,6 +776,7 @@ int upload_meta(Ctx& c) {
   int64_t* h_poff = (int64_t*)(h + align_up(b_off) + align_up(b_ns));
   char* h_units = h + align_up(b_off) + align_up(b_ns) + align_up(b_poff);
   char* h_uadj = h_units + align_up(b_units);
+  char* h_poffa = h_uadj + align_up(b_uadj);
   std::memcpy(h_off, c.sys.off, b_off);
   for (int64_t s = 0; s < S; ++s) {
     h_ns[s] = c.uf.nsplit.empty() ? 0 : c.uf.nsplit[s];
@@ -725,12 +785,16 @@ int upload_meta(Ctx& c) {
   if (b_poff) std::memcpy(h_poff, c.uf.part_off.data(), b_poff);
   if (b_units) std::memcpy(h_units, c.uf.sym ? (const void*)c.uf.sym_units.data() : (const void*)c.uf.units.data(),
                            b_units);
-  if (b_uadj) std::memcpy(h_uadj, c.ua.units.data(), b_uadj);
+  if (b_uadj) std::memcpy(h_uadj, c.ua.sym ? (const void*)c.ua.sym_units.data() : (const void*)c.ua.units.data(),
+                          b_uadj);
+  if (b_poffa) std::memcpy(h_poffa, c.ua.part_off.data(), b_poffa);
   HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_sysoff, h_off, b_off, hipMemcpyHostToDevice, c.st));
   HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_nsplit, h_ns, b_ns, hipMemcpyHostToDevice, c.st));
   if (b_poff) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_partoff, h_poff, b_poff, hipMemcpyHostToDevice, c.st));
   if (b_units) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_units, h_units, b_units, hipMemcpyHostToDevice, c.st));
   if (b_uadj) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_units_adj, h_uadj, b_uadj, hipMemcpyHostToDevice, c.st));
+  if (b_poffa)
+    HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_partoff_adj, h_poffa, b_poffa, hipMemcpyHostToDevice, c.st));
   HIP_TRY(hipEventRecord(g_stage_done, c.st));
   return NBODY_OK;
 }
@@ -922,7 +986,7 @@ int energy_pass(Ctx& c, const double* vel, const double* mass, const double* pot
 int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, const double* gpos_in,
                  double h_drift, double w, double* gpos, double* gmass) {
   const int prec = c.cfg->precision;
-  const bool comp = prec == NBODY_FP32_COMP;
+  const int comp = adj_comp(prec);  // the double-float mode's adjoint runs compensated
   const double eps2 = c.cfg->eps * c.cfg->eps;
   TRY(check_jbuf(c, jadj_bytes(c.cfg->precision), "adjoint_stage"));
   void* jadj = c.ws + c.plan.off_jbuf;
@@ -940,6 +1004,22 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
     const int64_t ns = e - b;
     if (ns == 0) return NBODY_OK;
     Tile t = lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns);
+    if (t.sym >= 0) {
+      const AdjSymVariant& sv = kAdjSym32[t.sym];
+      const int64_t nb = cdiv(ns, (int64_t)t.tj);
+      const int64_t tiles = nb * (nb + 1) / 2;
+      if (tiles > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many symmetric tiles");
+      TRY(check_part(c, (size_t)nb * 4 * ns * sizeof(float), "adjoint_sym_kernel"));
+      float* pf = (float*)(c.ws + c.plan.off_part);
+      const float4* ja = (const float4*)jadj + 2 * b;
+      sv.fn[comp](dim3((unsigned)tiles), c.st, ja, ns, (int32_t)nb, (float)eps2, pf);
+      LAUNCH_CHECK("adjoint_sym_kernel");
+      hipLaunchKernelGGL(adjoint_reduce_sym, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)nb, (const float*)pf,
+                         c.cfg->G, gpos + b, gmass + b, (int64_t)0, (const int64_t*)nullptr, (const int32_t*)nullptr,
+                         (const int64_t*)nullptr);
+      LAUNCH_CHECK("adjoint_reduce_sym");
+      return NBODY_OK;
+    }
     int64_t S, jc;
     split_geometry(t, ns, S, jc);
     const AdjVariant& av = is_fp64(prec) ? kAdj64[t.variant] : kAdj32[t.variant];
@@ -974,9 +1054,30 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
     return NBODY_OK;
   }
   Tile t = lookup_tile(NBODY_KERNEL_ADJOINT_BATCHED, prec, c.sys.max_n);
+  int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter) + 1;
+  const int32_t* nsplit_adj = (const int32_t*)(c.ws + c.plan.off_nsplit) + c.sys.S;
+  if (t.sym >= 0) {
+    if (!c.ua.sym) return fail(NBODY_ERR_DEVICE, "internal: symmetric batched adjoint tile without symmetric units");
+    TRY(check_part(c, (size_t)c.ua.part_floats * sizeof(float), "adjoint_sym_batched_kernel"));
+    const AdjSymVariant& sv = kAdjSym32[t.sym];
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)1, 0);
+    LAUNCH_CHECK("fill_i32");
+    unsigned grid;
+    persistent_grid(sv.bptr[comp](), sv.w * 64, c.plan.n_units_adj, grid);
+    float* pf = (float*)(c.ws + c.plan.off_part);
+    sv.bfn[comp](dim3(grid), c.st, (const float4*)jadj, (const SymUnit*)(c.ws + c.plan.off_units_adj),
+                 (int32_t)c.plan.n_units_adj, counter, (float)eps2, pf);
+    LAUNCH_CHECK("adjoint_sym_batched_kernel");
+    hipLaunchKernelGGL(adjoint_reduce_sym, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, (const float*)pf,
+                       c.cfg->G, gpos, gmass, c.sys.S,
+                       (const int64_t*)(c.ws + c.plan.off_sysoff), nsplit_adj,
+                       (const int64_t*)(c.ws + c.plan.off_partoff_adj));
+    LAUNCH_CHECK("adjoint_reduce_sym");
+    return NBODY_OK;
+  }
+  if (c.ua.sym) return fail(NBODY_ERR_DEVICE, "internal: one-sided batched adjoint tile with symmetric units");
   const AdjVariant& av = is_fp64(prec) ? kAdj64[t.variant] : kAdj32[t.variant];
   TRY(check_part(c, (size_t)max_nsplit(c.ua) * 8 * n * sizeof(double), "adjoint_batched_kernel"));
-  int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter) + 1;
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)1, 0);
   LAUNCH_CHECK("fill_i32");
   unsigned grid;
@@ -988,7 +1089,6 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
   av.bfn[comp](dim3(grid), c.st, jadj, (const WorkUnit*)(c.ws + c.plan.off_units_adj),
                (int32_t)c.plan.n_units_adj, counter, eps2, o);
   LAUNCH_CHECK("adjoint_batched_kernel");
-  const int32_t* nsplit_adj = (const int32_t*)(c.ws + c.plan.off_nsplit) + c.sys.S;
   if (is_fp64(prec))
     hipLaunchKernelGGL(adjoint_reduce<double>, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, (const D4*)jadj,
                        c.cfg->G, gpos, gmass, c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff), nsplit_adj);
@@ -1260,10 +1360,11 @@ __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, i
       int bs, i, tj;
       variant_shape(kernel, precision, v, bs, i, tj);
       char tmp[64];
-      int len = sym_index(kernel, precision, v) >= 0
-                    ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d%s", bs, i, tj,
-                               kSym32[sym_index(kernel, precision, v)].rot ? ",rot=lds" : "")
-                    : snprintf(tmp, sizeof tmp, "bs=%d,i=%d,tj=%d", bs, i, tj);
+      const int sv = sym_index(kernel, precision, v);
+      int sw = 0, si = 0, srot = 0;
+      if (sv >= 0) sym_shape(kernel, sv, sw, si, srot);
+      int len = sv >= 0 ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d%s", bs, i, tj, srot ? ",rot=lds" : "")
+                        : snprintf(tmp, sizeof tmp, "bs=%d,i=%d,tj=%d", bs, i, tj);
       if (pos + len + 1 > cap) break;
       memcpy(buf + pos, tmp, len + 1);
       pos += len + 1;

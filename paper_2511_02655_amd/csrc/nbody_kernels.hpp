@@ -51,11 +51,9 @@ __device__ __forceinline__ float in_vgpr(float x) {
 }
 
 __device__ __forceinline__ double in_vgpr(double x) {
-  union { double d; struct { float lo, hi; } f; } u;
-  u.d = x;
-  u.f.lo = in_vgpr(u.f.lo);
-  u.f.hi = in_vgpr(u.f.hi);
-  return u.d;
+  double r;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "v"(x));
+  return r;
 }
 
 // Error-free transformation (Knuth's TwoSum): s + e == a + b exactly.
@@ -103,6 +101,15 @@ __device__ __forceinline__ typename Vec4<T>::type pad4() {
   typename Vec4<T>::type v = zero4<T>();
   if constexpr (LAW == LAW_LJ) v.x = v.y = v.z = sizeof(T) == 4 ? T(1e30f) : T(1e150);
   return v;
+}
+
+// v[idx] when ok, else fill: an explicit branch around the load (a select between the
+// element's address and a local's would turn the load into a generic one through
+// private memory).
+template <typename V>
+__device__ __forceinline__ V load_or(const V* __restrict__ v, int64_t idx, bool ok, V fill) {
+  if (ok) fill = v[idx];
+  return fill;
 }
 
 // 1/s in double: hardware estimate refined by two Newton-Raphson steps y <- y + y (1 - s y).
@@ -316,7 +323,7 @@ __device__ __forceinline__ void force_block(const typename Vec4<T>::type* __rest
   for (int k = 0; k < PER; ++k) {
     int64_t j = jb + t + (int64_t)k * BS;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) pre[NV * k + v] = j < je ? jarr[NV * j + v] : (v ? zero4<T>() : pad4<T, LAW>());
+    for (int v = 0; v < NV; ++v) pre[NV * k + v] = load_or(jarr, NV * j + v, j < je, v ? zero4<T>() : pad4<T, LAW>());
   }
 
   for (int64_t j0 = jb; j0 < je; j0 += TJ) {
@@ -331,7 +338,8 @@ __device__ __forceinline__ void force_block(const typename Vec4<T>::type* __rest
       for (int k = 0; k < PER; ++k) {
         int64_t j = j0 + TJ + t + (int64_t)k * BS;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) pre[NV * k + v] = j < je ? jarr[NV * j + v] : (v ? zero4<T>() : pad4<T, LAW>());
+        for (int v = 0; v < NV; ++v)
+          pre[NV * k + v] = load_or(jarr, NV * j + v, j < je, v ? zero4<T>() : pad4<T, LAW>());
       }
     }
     const bool diag = (POT || LAW == LAW_LJ) && (j0 < ie) && (j0 + TJ > ib);
@@ -993,8 +1001,8 @@ __device__ __forceinline__ void adjoint_block(const typename Vec4<T>::type* __re
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     int64_t j = jb + t + (int64_t)k * BS;
-    pre[2 * k] = j < je ? jadj[2 * j] : zero4<T>();
-    pre[2 * k + 1] = j < je ? jadj[2 * j + 1] : zero4<T>();
+    pre[2 * k] = load_or(jadj, 2 * j, j < je, zero4<T>());
+    pre[2 * k + 1] = load_or(jadj, 2 * j + 1, j < je, zero4<T>());
   }
 
   for (int64_t j0 = jb; j0 < je; j0 += TJ) {
@@ -1009,8 +1017,8 @@ __device__ __forceinline__ void adjoint_block(const typename Vec4<T>::type* __re
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         int64_t j = j0 + TJ + t + (int64_t)k * BS;
-        pre[2 * k] = j < je ? jadj[2 * j] : zero4<T>();
-        pre[2 * k + 1] = j < je ? jadj[2 * j + 1] : zero4<T>();
+        pre[2 * k] = load_or(jadj, 2 * j, j < je, zero4<T>());
+        pre[2 * k + 1] = load_or(jadj, 2 * j + 1, j < je, zero4<T>());
       }
     }
     const bool diag = (j0 < ie) && (j0 + TJ > ib);
@@ -1149,6 +1157,245 @@ __global__ void adjoint_reduce(int64_t count, int64_t stride, int32_t S, const d
 #pragma unroll
   for (int c = 0; c < 3; ++c) gpos[c * n + i] += G * (m * r[c] - r[3] * lk[c] - r[4 + c]);
   gmass[i] += -G * r[7];
+}
+
+// ----------------------------------------------------------------- symmetric adjoint pass (FP32)
+
+// Each unordered pair once. With d = x_j - x_k, r3 = s^{-3/2}, 3 r5 = 3 s^{-5/2},
+// w = m_k l_j - m_j l_k and cc = 3 r5 (d.w), the pair's share of the VJP is
+//   v = T(d) w = r3 w - cc d:   gx_k += v,  gx_j -= v,
+// (T(d) is even in d and w changes sign when k and j swap), and for the masses
+//   M_k += r3 (d.l_j),  M_j -= r3 (d.l_k),   gm = -G M.
+// Unlike the one-sided pass (which factors m_k and l_k out of its sums), the sums are
+// taken directly, so every particle carries 4 accumulators instead of 8 - half the
+// registers and lane rotations. Tiles, lane rotation and slots as in sym_tile:
+// part[(slot*4 + c)*n + p], c = gx, gy, gz, M. Diagonal tiles run one-sided with the
+// self pair masked (r3 = 0 removes every term).
+template <int W, int I, bool COMP, int ROT>
+__device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, int64_t n, int32_t A, int32_t B,
+                                             float eps2_arg, float* __restrict__ part,
+                                             float (&red)[2][W][4][64]) {
+  constexpr int BI = W * 64 * I;
+  constexpr int NSUB = BI / 64;
+  const bool diag = (A == B);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rot_src = ((lane - 1) & 63) << 2;
+  const int64_t Abase = (int64_t)A * BI, Bbase = (int64_t)B * BI;
+  const float eps2 = in_vgpr(eps2_arg);
+  const float three = in_vgpr(3.f);
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  float xk[I], yk[I], zk[I], mk[I], lx[I], ly[I], lz[I];
+  float ai[4][I], hi[4][I], lo[4][I];
+#pragma unroll
+  for (int u = 0; u < I; ++u) {
+    const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
+    const int64_t ic = i < n ? i : n - 1;
+    const float4 p = jadj[2 * ic];
+    float4 l = zero;  // (a branch, not a select of addresses: keeps the load global)
+    if (i < n) l = jadj[2 * ic + 1];
+    xk[u] = in_vgpr(p.x);
+    yk[u] = in_vgpr(p.y);
+    zk[u] = in_vgpr(p.z);
+    mk[u] = in_vgpr(i < n ? p.w : 0.f);
+    lx[u] = in_vgpr(l.x);
+    ly[u] = in_vgpr(l.y);
+    lz[u] = in_vgpr(l.z);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { ai[c][u] = 0.f; hi[c][u] = 0.f; lo[c][u] = 0.f; }
+  }
+
+  float4 nq = zero, nl = zero;
+  {
+    const int64_t j = Bbase + lane;
+    if (j < n) {
+      nq = jadj[2 * j];
+      nl = jadj[2 * j + 1];
+    }
+  }
+  const int64_t jrows = n - Bbase;
+  const int nsub_b = jrows >= BI ? NSUB : (int)((jrows + 63) >> 6);
+  const int nsub = (diag && Abase + (int64_t)w * 64 * I >= n) ? 0 : nsub_b;
+  for (int sb = 0; sb < nsub; ++sb) {
+    const float4 q = nq, L = nl;
+    if (sb + 1 < nsub) {
+      const int64_t j = Bbase + (int64_t)(sb + 1) * 64 + lane;
+      nq = zero;
+      nl = zero;
+      if (j < n) {
+        nq = jadj[2 * j];
+        nl = jadj[2 * j + 1];
+      }
+    }
+    float xj = q.x, yj = q.y, zj = q.z, mj = q.w, ljx = L.x, ljy = L.y, ljz = L.z;
+    if (diag) {
+      for (int k = 0; k < 64; ++k) {
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+          const float dx = xj - xk[u], dy = yj - yk[u], dz = zj - zk[u];
+          const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
+          const float ri = __builtin_amdgcn_rsqf(r2);
+          const float ri2 = ri * ri;
+          float r3 = ri * ri2;
+          r3 = (k == 0 && sb == w * I + u) ? 0.f : r3;  // the self pair
+          const float r5x3 = r3 * (ri2 * three);
+          const float pp = __builtin_fmaf(dx, ljx, __builtin_fmaf(dy, ljy, dz * ljz));
+          const float qq = __builtin_fmaf(dx, lx[u], __builtin_fmaf(dy, ly[u], dz * lz[u]));
+          const float cc = r5x3 * __builtin_fmaf(mk[u], pp, -(mj * qq));  // 3 r5 (d.w)
+          const float am = r3 * mk[u], bm = r3 * mj;                       // r3 w = am l_j - bm l_k
+          ai[0][u] += __builtin_fmaf(am, ljx, __builtin_fmaf(-bm, lx[u], -(cc * dx)));
+          ai[1][u] += __builtin_fmaf(am, ljy, __builtin_fmaf(-bm, ly[u], -(cc * dy)));
+          ai[2][u] += __builtin_fmaf(am, ljz, __builtin_fmaf(-bm, lz[u], -(cc * dz)));
+          ai[3][u] = __builtin_fmaf(r3, pp, ai[3][u]);
+        }
+        xj = rotate1<ROT>(xj, rot_src);
+        yj = rotate1<ROT>(yj, rot_src);
+        zj = rotate1<ROT>(zj, rot_src);
+        mj = rotate1<ROT>(mj, rot_src);
+        ljx = rotate1<ROT>(ljx, rot_src);
+        ljy = rotate1<ROT>(ljy, rot_src);
+        ljz = rotate1<ROT>(ljz, rot_src);
+      }
+    } else {
+      float aj[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int k = 0; k < 64; ++k) {
+        float dx[I], dy[I], dz[I], rr[I];
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+          dx[u] = xj - xk[u];
+          dy[u] = yj - yk[u];
+          dz[u] = zj - zk[u];
+          rr[u] = __builtin_fmaf(dx[u], dx[u], __builtin_fmaf(dy[u], dy[u], __builtin_fmaf(dz[u], dz[u], eps2)));
+        }
+#pragma unroll
+        for (int u = 0; u < I; ++u) rr[u] = __builtin_amdgcn_rsqf(rr[u]);
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+          const float ri2 = rr[u] * rr[u];
+          const float r3 = rr[u] * ri2;
+          const float r5x3 = r3 * (ri2 * three);
+          const float pp = __builtin_fmaf(dx[u], ljx, __builtin_fmaf(dy[u], ljy, dz[u] * ljz));
+          const float qq = __builtin_fmaf(dx[u], lx[u], __builtin_fmaf(dy[u], ly[u], dz[u] * lz[u]));
+          const float cc = r5x3 * __builtin_fmaf(mk[u], pp, -(mj * qq));  // 3 r5 (d.w)
+          const float am = r3 * mk[u], bm = r3 * mj;                       // r3 w = am l_j - bm l_k
+          const float vx = __builtin_fmaf(am, ljx, __builtin_fmaf(-bm, lx[u], -(cc * dx[u])));
+          const float vy = __builtin_fmaf(am, ljy, __builtin_fmaf(-bm, ly[u], -(cc * dy[u])));
+          const float vz = __builtin_fmaf(am, ljz, __builtin_fmaf(-bm, lz[u], -(cc * dz[u])));
+          ai[0][u] += vx;
+          ai[1][u] += vy;
+          ai[2][u] += vz;
+          ai[3][u] = __builtin_fmaf(r3, pp, ai[3][u]);
+          aj[0] -= vx;
+          aj[1] -= vy;
+          aj[2] -= vz;
+          aj[3] = __builtin_fmaf(-r3, qq, aj[3]);
+        }
+        xj = rotate1<ROT>(xj, rot_src);
+        yj = rotate1<ROT>(yj, rot_src);
+        zj = rotate1<ROT>(zj, rot_src);
+        mj = rotate1<ROT>(mj, rot_src);
+        ljx = rotate1<ROT>(ljx, rot_src);
+        ljy = rotate1<ROT>(ljy, rot_src);
+        ljz = rotate1<ROT>(ljz, rot_src);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) aj[c] = rotate1<ROT>(aj[c], rot_src);
+      }
+      // j-side of this sub-block: the W waves summed in wave order, written to slot A
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[sb & 1][w][c][lane] = aj[c];
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < 4 * 64; idx += W * 64) {
+        const int c = idx >> 6, l = idx & 63;
+        float sum = 0.f;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) sum += red[sb & 1][ww][c][l];
+        const int64_t j = Bbase + (int64_t)sb * 64 + l;
+        if (j < n) part[((int64_t)A * 4 + c) * n + j] = sum;
+      }
+    }
+    if (COMP) {
+#pragma unroll
+      for (int u = 0; u < I; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          float t, e;
+          two_sum(hi[c][u], ai[c][u], t, e);
+          hi[c][u] = t;
+          lo[c][u] += e;
+          ai[c][u] = 0.f;
+        }
+    }
+  }
+  // i-side of the tile: slot B
+#pragma unroll
+  for (int u = 0; u < I; ++u) {
+    const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
+    if (i < n)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) part[((int64_t)B * 4 + c) * n + i] = COMP ? hi[c][u] + lo[c][u] : ai[c][u];
+  }
+}
+
+template <int W, int I, bool COMP, int ROT>
+__global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(const float4* __restrict__ jadj, int64_t n, int32_t nb,
+                                                             float eps2, float* __restrict__ part) {
+  __shared__ float red[2][W][4][64];
+  int32_t A, B;
+  tile_rc(blockIdx.x, nb, A, B);
+  adj_sym_tile<W, I, COMP, ROT>(jadj, n, A, B, eps2, part, red);
+}
+
+// Persistent grid over the symmetric adjoint tiles of many systems (counter = 0 at launch).
+template <int W, int I, bool COMP, int ROT>
+__global__ __launch_bounds__(W * 64) void adjoint_sym_batched_kernel(const float4* __restrict__ jadj,
+                                                                     const SymUnit* __restrict__ units,
+                                                                     int32_t n_units, int32_t* __restrict__ counter,
+                                                                     float eps2, float* __restrict__ part) {
+  __shared__ float red[2][W][4][64];
+  __shared__ int32_t next;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int32_t u = next;
+    if (u >= n_units) break;
+    const SymUnit su = units[u];
+    adj_sym_tile<W, I, COMP, ROT>(jadj + 2 * su.base, su.n, su.A, su.B, eps2, part + su.part_off, red);
+  }
+}
+
+// Sum of the nb float slots (4 components) of every particle in double:
+// gpos += G gx, gmass += -G M. Single system: n particles (partial plane
+// stride), stride = plane stride of gpos; batched (n_sys > 0): system of particle i found
+// by binary search, its nb and partial offset from sys_nb / sys_part.
+__global__ void adjoint_reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* __restrict__ part,
+                                   double G, double* __restrict__ gpos,
+                                   double* __restrict__ gmass, int64_t n_sys, const int64_t* __restrict__ sys_off,
+                                   const int32_t* __restrict__ sys_nb, const int64_t* __restrict__ sys_part) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t ns = n, li = i;
+  int32_t nbs = nb;
+  const float* ps = part;
+  if (n_sys > 0) {
+    int64_t lo = 0, hi = n_sys;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (sys_off[mid] <= i) lo = mid; else hi = mid;
+    }
+    const int64_t b = sys_off[lo];
+    ns = sys_off[lo + 1] - b;
+    li = i - b;
+    nbs = sys_nb[lo];
+    ps = part + sys_part[lo];
+  }
+  double r[4] = {0, 0, 0, 0};
+  for (int32_t k = 0; k < nbs; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) r[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) gpos[c * stride + i] += G * r[c];
+  gmass[i] += -G * r[3];
 }
 
 }  // namespace nbody

@@ -486,6 +486,78 @@ def test_batched_backward_vs_loop_and_oracle(nb, oracle, prec):
                 assert _rel_l2(a, ref[k]) <= tol
 
 
+def _adj_sym_variants(nb, kernel="adjoint"):
+    return [k for k, d in enumerate(nb.tile_variants(kernel, "fp32c")) if "sym=" in d]
+
+
+@pytest.mark.parametrize("n", [2, 100, 1025, 3000])
+def test_symmetric_adjoint_variants(nb, oracle, n):
+    """The symmetric adjoint pass (each pair once, both ends updated; 8 float partial
+    components per slot), every variant and FP32 mode forced through the tile table, on
+    sizes below, across and several blocks beyond the tile edge: a one-step backward (two
+    adjoint passes) against the oracle, and bitwise determinism."""
+    s = inputs.plummer(n, 600 + n)
+    g = np.random.Generator(np.random.PCG64(601))
+    gxK, gvK = g.normal(size=(3, n)), g.normal(size=(3, n))
+    ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, 1e-3, 1, gxK, gvK, eps=1e-2)
+    tol = {"fp32c": 1e-4, "fp32": 1e-3, "fp32ds": 1e-4}
+    try:
+        for v in _adj_sym_variants(nb):
+            nb.set_tile_table([dict(kernel="adjoint", precision=p, n_min=0, n_max=1 << 40, variant=v, j_split=1)
+                               for p in ("fp32", "fp32c", "fp32ds")])
+            for prec in ("fp32c", "fp32", "fp32ds"):
+                pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+                acc, _ = nb.forces(pos, mass, precision=prec)
+                ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 1, ckpt_every=1, precision=prec)
+                out = [host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 1, 1,
+                                                             precision=prec)]
+                for a, b in zip(out, ref):
+                    assert _rel_l2(a, b) <= tol[prec], (v, prec)
+                out2 = [host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 1, 1,
+                                                              precision=prec)]
+                for a, b in zip(out, out2):
+                    assert np.array_equal(a, b)
+    finally:
+        nb.set_tile_table([])
+
+
+def test_batched_symmetric_adjoint(nb, oracle):
+    """Batched backward on the symmetric batched adjoint pass (empty, single and ragged
+    systems) against the oracle per system and the looped path."""
+    sizes = [0, 1, 130, 2, 700, 0, 1500]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    g = np.random.Generator(np.random.PCG64(611))
+    pos0 = g.random((3, n))
+    vel0 = g.normal(size=(3, n)) * 0.05
+    mass0 = g.uniform(0.5, 1.5, n) / 700
+    gxK, gvK = g.normal(size=(3, n)), g.normal(size=(3, n))
+    variants = _adj_sym_variants(nb, "adjoint_batched")
+    try:
+        for v in (variants[0], variants[2]):
+            nb.set_tile_table([dict(kernel="adjoint_batched", precision="fp32c", n_min=0, n_max=1 << 40,
+                                    variant=v, j_split=1)])
+            pos, vel, mass = dev(pos0), dev(vel0), dev(mass0)
+            acc, _ = nb.forces(pos, mass, precision="fp32c", offsets=off)
+            ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 4, ckpt_every=2, precision="fp32c", offsets=off)
+            out = [host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 4, 2,
+                                                         precision="fp32c", offsets=off)]
+            for k in range(len(sizes)):
+                if sizes[k] == 0:
+                    continue
+                sl = slice(off[k], off[k + 1])
+                ref = oracle.rollout_adjoint(pos0[:, sl], vel0[:, sl], mass0[sl], 1e-3, 4, gxK[:, sl], gvK[:, sl],
+                                             eps=1e-2)
+                for a, b in zip(out, ref):
+                    if sizes[k] == 1:
+                        assert np.allclose(a[..., sl], b, rtol=1e-12, atol=0)
+                    else:
+                        assert _rel_l2(a[..., sl], b) <= 1e-4, (v, k)
+    finally:
+        nb.set_tile_table([])
+
+
 def test_autograd_function(nb, oracle):
     import torch
     s = inputs.two_spheres(64, 30)
