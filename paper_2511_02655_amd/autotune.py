@@ -30,9 +30,13 @@ J_SPLITS = [1, 2, 4, 8, 16, 32, 64]
 BATCH_JCHUNK = [512, 1024, 2048, 4096]
 
 
-def _bounds(buckets, k):
-    lo = 0 if k == 0 else int(math.sqrt(buckets[k - 1] * buckets[k])) + 1
-    hi = (1 << 40) if k == len(buckets) - 1 else int(math.sqrt(buckets[k] * buckets[k + 1]))
+def _bounds(buckets, k, standard=()):
+    """n-range of bucket k: geometric midpoints to its neighbours, taken from the union of
+    the tuned buckets and the standard list, so a partial re-tune keeps the table's ranges."""
+    grid = sorted(set(buckets) | set(standard))
+    j = grid.index(buckets[k])
+    lo = 0 if j == 0 else int(math.sqrt(grid[j - 1] * grid[j])) + 1
+    hi = (1 << 40) if j == len(grid) - 1 else int(math.sqrt(grid[j] * grid[j + 1]))
     return lo, hi
 
 
@@ -109,7 +113,7 @@ def tune_force(nb, torch, precision, buckets, log, law="gravity"):
                                                                                    js, t, rate))
                 cands.append((t, v, js, rate))
         best = _pick(cands, descs)
-        lo, hi = _bounds(buckets, k)
+        lo, hi = _bounds(buckets, k, LJ_BUCKETS if law == "lj" else FORCE_BUCKETS)
         entries.append(dict(kernel=kname, precision=precision, n_min=lo, n_max=hi, variant=best[1],
                             j_split=best[2], tuned_n=n, ms=best[0], interactions_per_s=best[3]))
         nb.set_tile_table([])
@@ -143,7 +147,7 @@ def tune_adjoint(nb, torch, precision, buckets, log):
                 log("adjoint %s n=%d variant %d (%s) j_split %d: %.3f ms" % (precision, n, v, descs[v], js, t))
                 if best is None or t < best[0]:
                     best = (t, v, js)
-        lo, hi = _bounds(buckets, k)
+        lo, hi = _bounds(buckets, k, ADJ_BUCKETS)
         entries.append(dict(kernel="adjoint", precision=precision, n_min=lo, n_max=hi, variant=best[1],
                             j_split=best[2], tuned_n=n, ms=best[0]))
         nb.set_tile_table([])
@@ -194,7 +198,8 @@ def main():
     ap.add_argument("--precisions", default=None, help="comma list (default: all)")
     ap.add_argument("--kernels", default="force,adjoint,batched,lj_force",
                     help="comma list of force, adjoint, batched, lj_force")
-    ap.add_argument("--merge", default=None, help="existing table: keep its entries for everything not re-tuned")
+    ap.add_argument("--merge", default=None,
+                    help="existing table: keep its entries for every (kernel, precision, bucket) not re-tuned")
     ap.add_argument("--force-buckets", default=None, help="comma list of particle counts for the force buckets")
     args = ap.parse_args()
     import torch
@@ -229,8 +234,9 @@ def main():
     if args.merge and os.path.exists(args.merge):
         with open(args.merge) as f:
             old = json.load(f).get("entries", [])
-        tuned = {(e["kernel"], e["precision"]) for e in entries}
-        entries = [e for e in old if (e["kernel"], e["precision"]) not in tuned] + entries
+        tuned = {(e["kernel"], e["precision"], e.get("tuned_n")) for e in entries}
+        entries = [e for e in old if (e["kernel"], e["precision"], e.get("tuned_n")) not in tuned] + entries
+        entries.sort(key=lambda e: (e["kernel"], e["precision"], e["n_min"]))
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     table = {"arch": arch, "tuned_in_s": time.time() - t0, "entries": entries}
     out = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune", arch + ".json")

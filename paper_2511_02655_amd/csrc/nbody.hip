@@ -150,35 +150,41 @@ const AdjVariant kAdj64[] = {AV64(256, 1, 256), AV64(128, 1, 128), AV64(64, 1, 6
 // Symmetric FP32 force variants (each pair once), indices kNumForce32 + k in the
 // FORCE tile table.
 using SymFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part);
-template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 void launch_sym(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part) {
-  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE, ROT, LAW>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2, part);
+  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE, ROT, LAW, PIPE>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2,
+                     part);
 }
 using SymBatchedFn = void (*)(dim3, hipStream_t, const float4* jarr, const SymUnit* units, int32_t n_units,
                               int32_t* counter, float eps2, float* part);
-template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 void launch_sym_batched(dim3 g, hipStream_t st, const float4* jarr, const SymUnit* units, int32_t n_units,
                         int32_t* counter, float eps2, float* part) {
-  hipLaunchKernelGGL((force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW>), g, dim3(W * 64), 0, st, jarr, units,
-                     n_units, counter, eps2, part);
+  hipLaunchKernelGGL((force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW, PIPE>), g, dim3(W * 64), 0, st, jarr,
+                     units, n_units, counter, eps2, part);
 }
-template <int W, int I, bool POT, int MODE, int ROT, int LAW>
-const void* sym_batched_ptr() { return (const void*)&force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW>; }
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
+const void* sym_batched_ptr() { return (const void*)&force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW, PIPE>; }
 struct SymVariant {
   int w, i, rot;      // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
+  int pipe;           // coordinate rotation issued after phase 1 (0) or a step ahead (1)
   SymFn fn[2][2][3];  // [law][pot][mode]
   SymBatchedFn bfn[2][2][3];
   const void* (*bptr[2][2][3])();
 };
-#define SV32_POT(F, W, I, R, POT, LAW) { F<W, I, POT, 0, R, LAW>, F<W, I, POT, 1, R, LAW>, F<W, I, POT, 2, R, LAW> }
-#define SV32_ALL(F, W, I, R)                                                                              \
-  {{SV32_POT(F, W, I, R, false, 0), SV32_POT(F, W, I, R, true, 0)},                                       \
-   {SV32_POT(F, W, I, R, false, 1), SV32_POT(F, W, I, R, true, 1)}}
-#define SV32(W, I, R) \
-  SymVariant { W, I, R, SV32_ALL(launch_sym, W, I, R), SV32_ALL(launch_sym_batched, W, I, R), SV32_ALL(sym_batched_ptr, W, I, R) }
+#define SV32_POT(F, W, I, R, P, POT, LAW) \
+  { F<W, I, POT, 0, R, LAW, P>, F<W, I, POT, 1, R, LAW, P>, F<W, I, POT, 2, R, LAW, P> }
+#define SV32_ALL(F, W, I, R, P)                                                                           \
+  {{SV32_POT(F, W, I, R, P, false, 0), SV32_POT(F, W, I, R, P, true, 0)},                                 \
+   {SV32_POT(F, W, I, R, P, false, 1), SV32_POT(F, W, I, R, P, true, 1)}}
+#define SV32P(W, I, R, P)                                                                                  \
+  SymVariant { W, I, R, P, SV32_ALL(launch_sym, W, I, R, P), SV32_ALL(launch_sym_batched, W, I, R, P),   \
+               SV32_ALL(sym_batched_ptr, W, I, R, P) }
+#define SV32(W, I, R) SV32P(W, I, R, 0)
 const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4, 2, 0), SV32(2, 4, 0),
                              SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1), SV32(2, 4, 1),
-                             SV32(4, 2, 1), SV32(2, 2, 1)};
+                             SV32(4, 2, 1), SV32(2, 2, 1), SV32P(8, 4, 1, 1), SV32P(4, 8, 1, 1),
+                             SV32P(4, 4, 1, 1)};
 constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
 
 // Symmetric FP32 adjoint variants, indices kNumAdj32 + k in the ADJOINT tables.
@@ -1363,7 +1369,9 @@ __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, i
       const int sv = sym_index(kernel, precision, v);
       int sw = 0, si = 0, srot = 0;
       if (sv >= 0) sym_shape(kernel, sv, sw, si, srot);
-      int len = sv >= 0 ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d%s", bs, i, tj, srot ? ",rot=lds" : "")
+      const bool pipe = sv >= 0 && is_force_kernel(kernel) && kSym32[sv].pipe;
+      int len = sv >= 0 ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d%s%s", bs, i, tj, srot ? ",rot=lds" : "",
+                                   pipe ? ",pipe" : "")
                         : snprintf(tmp, sizeof tmp, "bs=%d,i=%d,tj=%d", bs, i, tj);
       if (pos + len + 1 > cap) break;
       memcpy(buf + pos, tmp, len + 1);

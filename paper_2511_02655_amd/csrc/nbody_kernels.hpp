@@ -504,7 +504,10 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 //
 // One tile (A, B) of a system of n particles (jarr and part point at the system's own
 // j-array and partial planes); red is the workgroup's LDS for the cross-wave j sums.
-template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+// PIPE chooses when a step's j coordinates are rotated: 0 right after they are consumed
+// (phase 1), 1 at the top of the step, a whole step ahead of their use. Both compute the
+// same values; which schedules better depends on the variant (measured by the tuner).
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE = 0>
 __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_t n, int32_t A, int32_t B,
                                          float eps2_arg, float* __restrict__ part,
                                          float (&red)[2][W][POT ? 4 : 3][64]) {
@@ -548,8 +551,8 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
   float4 nxt, nxtl = zero;
   {
     const int64_t j = Bbase + lane;
-    nxt = j < n ? jarr[NV * j] : jpad;
-    if constexpr (DS) nxtl = j < n ? jarr[NV * j + 1] : zero;
+    nxt = load_or(jarr, NV * j, j < n, jpad);
+    if constexpr (DS) nxtl = load_or(jarr, NV * j + 1, j < n, zero);
   }
   // Only the sub-blocks of block B that hold particles are visited (block B is ragged
   // when it is the system's last). Off-diagonal tiles have A < B, so block A is full and
@@ -562,8 +565,8 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
     const float4 q = nxt, ql = nxtl;
     if (sb + 1 < nsub) {
       const int64_t j = Bbase + (int64_t)(sb + 1) * 64 + lane;
-      nxt = j < n ? jarr[NV * j] : jpad;
-      if constexpr (DS) nxtl = j < n ? jarr[NV * j + 1] : zero;
+      nxt = load_or(jarr, NV * j, j < n, jpad);
+      if constexpr (DS) nxtl = load_or(jarr, NV * j + 1, j < n, zero);
     }
     float xj = q.x, yj = q.y, zj = q.z, mj = q.w, xjl = ql.x, yjl = ql.y, zjl = ql.z;
     if (diag) {
@@ -613,6 +616,17 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
 #pragma unroll
       for (int c = 0; c < NC; ++c) aj[c] = 0.f;
       for (int k = 0; k < 64; ++k) {
+        float xn = xj, yn = yj, zn = zj, xnl = xjl, ynl = yjl, znl = zjl;
+        if constexpr (PIPE == 1) {  // the next step's coordinates, requested a step ahead
+          xn = rotate1<ROT>(xj, rot_src);
+          yn = rotate1<ROT>(yj, rot_src);
+          zn = rotate1<ROT>(zj, rot_src);
+          if constexpr (DS) {
+            xnl = rotate1<ROT>(xjl, rot_src);
+            ynl = rotate1<ROT>(yjl, rot_src);
+            znl = rotate1<ROT>(zjl, rot_src);
+          }
+        }
         // phase 1: separations and r^2 of the I pairs; phase 2: their square roots;
         // phase 3: scale factors and accumulation - independent work behind every rsq
         float dx[I], dy[I], dz[I], ri[I];
@@ -627,6 +641,16 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
             dz[u] += zjl - zl[u];
           }
           ri[u] = __builtin_fmaf(dx[u], dx[u], __builtin_fmaf(dy[u], dy[u], __builtin_fmaf(dz[u], dz[u], eps2)));
+        }
+        if constexpr (PIPE == 0) {  // consumed: pass them on while phases 2 and 3 run
+          xn = rotate1<ROT>(xj, rot_src);
+          yn = rotate1<ROT>(yj, rot_src);
+          zn = rotate1<ROT>(zj, rot_src);
+          if constexpr (DS) {
+            xnl = rotate1<ROT>(xjl, rot_src);
+            ynl = rotate1<ROT>(yjl, rot_src);
+            znl = rotate1<ROT>(zjl, rot_src);
+          }
         }
 #pragma unroll
         for (int u = 0; u < I; ++u) ri[u] = LAW == LAW_LJ ? __builtin_amdgcn_rcpf(ri[u]) : __builtin_amdgcn_rsqf(ri[u]);
@@ -665,15 +689,15 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
           aj[1] = __builtin_fmaf(-sj, dy[u], aj[1]);
           aj[2] = __builtin_fmaf(-sj, dz[u], aj[2]);
         }
-        xj = rotate1<ROT>(xj, rot_src);
-        yj = rotate1<ROT>(yj, rot_src);
-        zj = rotate1<ROT>(zj, rot_src);
-        mj = rotate1<ROT>(mj, rot_src);
+        xj = xn;
+        yj = yn;
+        zj = zn;
         if constexpr (DS) {
-          xjl = rotate1<ROT>(xjl, rot_src);
-          yjl = rotate1<ROT>(yjl, rot_src);
-          zjl = rotate1<ROT>(zjl, rot_src);
+          xjl = xnl;
+          yjl = ynl;
+          zjl = znl;
         }
+        mj = rotate1<ROT>(mj, rot_src);
 #pragma unroll
         for (int c = 0; c < NC; ++c) aj[c] = rotate1<ROT>(aj[c], rot_src);
       }
@@ -714,13 +738,13 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
 }
 
 // Single system: one workgroup per tile t of the nb(nb+1)/2 upper-triangle tiles.
-template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restrict__ jarr, int64_t n, int32_t nb,
                                                            float eps2_arg, float* __restrict__ part) {
   __shared__ float red[2][W][POT ? 4 : 3][64];
   int32_t A, B;
   tile_rc(blockIdx.x, nb, A, B);
-  sym_tile<W, I, POT, MODE, ROT, LAW>(jarr, n, A, B, eps2_arg, part, red);
+  sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr, n, A, B, eps2_arg, part, red);
 }
 
 // ----------------------------------------------------------------- symmetric pass: per-particle reduction
@@ -760,7 +784,7 @@ struct SymUnit {
 // Persistent grid over the symmetric tiles of many systems (units sorted by decreasing
 // cost on the host), pulled from a shared counter that must be 0 at launch. Each tile
 // writes its own partial slots, so the result does not depend on which block ran it.
-template <int W, int I, bool POT, int MODE, int ROT, int LAW>
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 __global__ __launch_bounds__(W * 64) void force_sym_batched_kernel(const float4* __restrict__ jarr,
                                                                    const SymUnit* __restrict__ units,
                                                                    int32_t n_units, int32_t* __restrict__ counter,
@@ -775,7 +799,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_batched_kernel(const float4*
     const int32_t u = next;
     if (u >= n_units) break;
     const SymUnit su = units[u];
-    sym_tile<W, I, POT, MODE, ROT, LAW>(jarr + NV * su.base, su.n, su.A, su.B, eps2_arg, part + su.part_off, red);
+    sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr + NV * su.base, su.n, su.A, su.B, eps2_arg, part + su.part_off, red);
   }
 }
 
@@ -1259,6 +1283,8 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
     } else {
       float aj[4] = {0.f, 0.f, 0.f, 0.f};
       for (int k = 0; k < 64; ++k) {
+        // the next step's coordinates are requested first, a whole step ahead of use
+        const float xn = rotate1<ROT>(xj, rot_src), yn = rotate1<ROT>(yj, rot_src), zn = rotate1<ROT>(zj, rot_src);
         float dx[I], dy[I], dz[I], rr[I];
 #pragma unroll
         for (int u = 0; u < I; ++u) {
@@ -1290,9 +1316,9 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
           aj[2] -= vz;
           aj[3] = __builtin_fmaf(-r3, qq, aj[3]);
         }
-        xj = rotate1<ROT>(xj, rot_src);
-        yj = rotate1<ROT>(yj, rot_src);
-        zj = rotate1<ROT>(zj, rot_src);
+        xj = xn;
+        yj = yn;
+        zj = zn;
         mj = rotate1<ROT>(mj, rot_src);
         ljx = rotate1<ROT>(ljx, rot_src);
         ljy = rotate1<ROT>(ljy, rot_src);
