@@ -385,6 +385,23 @@ def adjoint_leg(nb, torch, np, inputs, dev):
                               eps=W["eps"], precision="fp64")
     rel = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(g32, g64)]
 
+    # checkpoint-free backward: the trajectory rebuilt by stepping back from the final state
+    pos.copy_(x0)
+    vel.copy_(v0)
+    nb.forces(pos, m, eps=W["eps"], precision=prec, out_acc=acc)
+    nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], eps=W["eps"], precision=prec)
+    nb.rollout_backward_reversible(m, pos, vel, gxK, gvK, W["dt"], W["steps"], eps=W["eps"], precision=prec)
+    torch.cuda.synchronize()
+    e3, e4 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e3.record()
+    for _ in range(reps):
+        grev = nb.rollout_backward_reversible(m, pos, vel, gxK, gvK, W["dt"], W["steps"], eps=W["eps"],
+                                              precision=prec)
+    e4.record()
+    torch.cuda.synchronize()
+    rev_ms = e3.elapsed_time(e4) / reps
+    rel_rev = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(grev, g32)]
+
     # FP64 finite differences of the loss along random directions (central, h relative to the group scale)
     def loss64(xa, va, ma):
         p, v = xa.clone(), va.clone()
@@ -416,6 +433,9 @@ def adjoint_leg(nb, torch, np, inputs, dev):
         "adjoint_interactions_per_s_incl_recompute": adj_passes * n2 / (bwd_ms * 1e-3),
         "forward_interactions_per_s": (W["steps"] + 1) * n2 / (fwd_ms * 1e-3),
         "grad_rel_l2_vs_fp64_gpu": {"x0": rel[0], "v0": rel[1], "m": rel[2]},
+        "reversible_backward_ms": rev_ms,
+        "reversible_grad_rel_l2_vs_checkpointed": {"x0": rel_rev[0], "v0": rel_rev[1], "m": rel_rev[2]},
+        "checkpoint_bytes": int(ckpt.numel() * 8),
         "directional_vs_fp64_finite_differences": fd,
     }
 

@@ -162,6 +162,18 @@ int nbody_rollout_backward(const nbody_config *cfg, int64_t n, double dt, int64_
                            const double *gpos_final, const double *gvel_final, double *gpos0,
                            double *gvel0, double *gmass);
 
+/* The same gradient without checkpoints: the positions x_{steps-1} .. x_0 are rebuilt
+ * by integrating backwards from the final state (the kick-drift-kick map is time
+ * reversible: a step of -dt undoes a step of dt up to rounding), so only O(n) memory
+ * is held. Costs the same as nbody_rollout_backward (one force pass and one adjoint pass
+ * per step). The rebuilt positions differ from the forward ones by rounding that
+ * chaotic dynamics amplify over many steps, so the gradient is exact only to that level.
+ *   pos_final, vel_final [3][n]: the state after the rollout (x_steps, v_steps). */
+int nbody_rollout_backward_reversible(const nbody_config *cfg, int64_t n, double dt, int64_t steps,
+                                      const double *mass, const double *pos_final, const double *vel_final,
+                                      const double *gpos_final, const double *gvel_final, double *gpos0,
+                                      double *gvel0, double *gmass);
+
 /* ---- the paper's pair law: Lennard-Jones gas (Eq. (1)) ----
  *
  *   V(r) = 4 epsilon [(sigma/r)^12 - (sigma/r)^6],

@@ -31,7 +31,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPAC
 
 EXPORTED = ("nbody_abi_version", "nbody_last_error", "nbody_workspace_size", "nbody_forces", "nbody_step",
             "nbody_rollout", "nbody_energy_momentum", "nbody_rollout_backward", "nbody_set_tile_table",
-            "nbody_tile_variants", "nbody_tile_lookup", "nbody_lj_forces", "nbody_lj_rollout")
+            "nbody_tile_variants", "nbody_tile_lookup", "nbody_lj_forces", "nbody_lj_rollout",
+            "nbody_rollout_backward_reversible")
 
 
 class NBodyError(RuntimeError):
@@ -103,6 +104,7 @@ def lib():
         "nbody_rollout": ([C, I64, D, I64, I64, P, P, P, P, P, P], ctypes.c_int),
         "nbody_energy_momentum": ([C, I64, P, P, P, P, P], ctypes.c_int),
         "nbody_rollout_backward": ([C, I64, D, I64, I64, P, P, P, P, P, P, P], ctypes.c_int),
+        "nbody_rollout_backward_reversible": ([C, I64, D, I64, P, P, P, P, P, P, P, P], ctypes.c_int),
         "nbody_set_tile_table": ([ctypes.POINTER(TileEntry), I64], ctypes.c_int),
         "nbody_tile_variants": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
         "nbody_tile_lookup": ([ctypes.c_int32, ctypes.c_int32, I64, ctypes.POINTER(ctypes.c_int32),
@@ -384,6 +386,26 @@ def lj_rollout(pos, vel, mass, acc, dt, steps, *, sigma=1.0, epsilon=1.0, soft=0
                                   _dptr(pos, "pos", (3, n)), _dptr(vel, "vel", (3, n)), _dptr(mass, "mass"),
                                   _dptr(acc, "acc", (3, n)), _dptr(trace, "energy_trace")))
     return trace
+
+
+def rollout_backward_reversible(mass, pos_final, vel_final, gpos_final, gvel_final, dt, steps, *, G=1.0, eps=1e-2,
+                                precision="fp32c", offsets=None, flags=0, stream=None):
+    """Discrete-adjoint gradients without checkpoints: the trajectory is rebuilt by
+    integrating backwards from (pos_final, vel_final). Returns (gpos0, gvel0, gmass)."""
+    torch = _torch()
+    n = _n_of(mass)
+    c = _Cfg(precision, G, eps, offsets, flags, stream)
+    c.workspace(n, steps, 1, device=mass.device)
+    gx = torch.empty((3, n), dtype=torch.float64, device=mass.device)
+    gv = torch.empty((3, n), dtype=torch.float64, device=mass.device)
+    gm = torch.empty(n, dtype=torch.float64, device=mass.device)
+    _check(lib().nbody_rollout_backward_reversible(ctypes.byref(c.cfg), n, float(dt), int(steps), _dptr(mass, "mass"),
+                                                   _dptr(pos_final, "pos_final", (3, n)),
+                                                   _dptr(vel_final, "vel_final", (3, n)),
+                                                   _dptr(gpos_final, "gpos_final", (3, n)),
+                                                   _dptr(gvel_final, "gvel_final", (3, n)), _dptr(gx, "gpos0"),
+                                                   _dptr(gv, "gvel0"), _dptr(gm, "gmass")))
+    return gx, gv, gm
 
 
 from .autograd import NBodyRollout, rollout_fn  # noqa: E402,F401

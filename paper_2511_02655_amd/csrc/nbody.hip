@@ -1336,6 +1336,43 @@ __attribute__((visibility("default"))) int nbody_rollout_backward(const nbody_co
   return NBODY_OK;
 }
 
+__attribute__((visibility("default"))) int nbody_rollout_backward_reversible(
+    const nbody_config* cfg, int64_t n, double dt, int64_t steps, const double* mass, const double* pos_final,
+    const double* vel_final, const double* gpos_final, const double* gvel_final, double* gpos0, double* gvel0,
+    double* gmass) {
+  g_err.clear();
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_FORCE | NEED_BACKWARD));
+  if (!std::isfinite(dt)) return fail(NBODY_ERR_INVALID_ARG, "dt must be finite");
+  if (steps < 0) return fail(NBODY_ERR_INVALID_ARG, "steps must be >= 0");
+  if (n == 0) return NBODY_OK;
+  if (!mass || !pos_final || !vel_final || !gpos_final || !gvel_final || !gpos0 || !gvel0 || !gmass)
+    return fail(NBODY_ERR_INVALID_ARG, "mass, final state, gradients and outputs must be non-NULL");
+  TRY(upload_meta(c));
+  const size_t plane3 = (size_t)3 * n * sizeof(double);
+  const double h = dt;
+  double* xw = (double*)(c.ws + c.plan.off_xw);
+  double* vw = (double*)(c.ws + c.plan.off_vw);
+  double* aw = (double*)(c.ws + c.plan.off_aw);
+  TRY(copy_d2d(c, gpos0, gpos_final, plane3));
+  TRY(copy_d2d(c, gvel0, gvel_final, plane3));
+  TRY(zero_f64(c, gmass, n));
+  if (steps == 0) return NBODY_OK;
+  TRY(copy_d2d(c, xw, pos_final, plane3));
+  TRY(copy_d2d(c, vw, vel_final, plane3));
+  TRY(stage(c, xw, mass));
+  TRY(force_pass(c, aw, nullptr, nullptr, 0.0));  // a(x_K)
+  TRY(adjoint_pass(c, xw, mass, gvel0, gpos0, 0.0, 0.5 * h, gpos0, gmass));
+  for (int64_t t = steps - 1; t >= 0; --t) {
+    // one kick-drift-kick step of -h takes (x_{t+1}, v_{t+1}, a_{t+1}) back to (x_t, v_t, a_t)
+    TRY(kick_drift(c, -h, xw, vw, aw, mass));
+    TRY(force_pass(c, aw, nullptr, vw, -0.5 * h));
+    const double w = t > 0 ? h : 0.5 * h;
+    TRY(adjoint_pass(c, xw, mass, gvel0, gpos0, h, w, gpos0, gmass));
+  }
+  return NBODY_OK;
+}
+
 __attribute__((visibility("default"))) int nbody_set_tile_table(const nbody_tile_entry* entries, int64_t count) {
   g_err.clear();
   if (count < 0 || (count > 0 && !entries)) return fail(NBODY_ERR_INVALID_ARG, "bad tile table");

@@ -139,6 +139,12 @@ def test_other_entry_point_errors(nb):
     assert L.nbody_rollout(ctypes.byref(c), 10, 1e-3, 5, 0, FAKE, FAKE, FAKE, FAKE, FAKE, None) == 1
     assert L.nbody_rollout_backward(ctypes.byref(c), 10, 1e-3, 5, 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE) == 1
     assert L.nbody_rollout_backward(ctypes.byref(c), 10, 1e-3, 5, 2, None, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE) == 1
+    assert L.nbody_rollout_backward_reversible(ctypes.byref(c), 10, float("inf"), 5, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                               FAKE, FAKE, FAKE) == 1
+    assert L.nbody_rollout_backward_reversible(ctypes.byref(c), 10, 1e-3, -1, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                               FAKE, FAKE, FAKE) == 1
+    assert L.nbody_rollout_backward_reversible(ctypes.byref(c), 10, 1e-3, 5, FAKE, None, FAKE, FAKE, FAKE,
+                                               FAKE, FAKE, FAKE) == 1
     assert L.nbody_energy_momentum(ctypes.byref(c), 10, FAKE, FAKE, FAKE, None, None) == 1
     assert "out" in L.nbody_last_error().decode()
     # n == 0 is a valid no-op that touches nothing
