@@ -79,6 +79,8 @@ def _load():
     lib.oracle_lj_energy.restype = None
     lib.oracle_lj_kdk.argtypes = [I64, D, D, D, D, I64, P, P, P, P, P, P]
     lib.oracle_lj_kdk.restype = None
+    lib.oracle_diagnostics.argtypes = [I64, P, P, P, P, P, P]
+    lib.oracle_diagnostics.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -243,3 +245,14 @@ def lj_kdk(pos, vel, mass, dt, steps, sigma=1.0, epsilon=1.0, soft=0.0, box=None
     _load().oracle_lj_kdk(n, sigma, epsilon, soft, dt, steps, _p(pos), _p(vel), _p(mass), _p(lo), _p(hi),
                           _p(energy))
     return pos, vel, energy
+
+
+def diagnostics(pos, vel, mass, pot, acc):
+    """(KE, PE, Px, Py, Pz, Lx, Ly, Lz, W, M) of one system from its state, the potential
+    per unit mass and the acceleration (L = sum m x cross v, W = sum m x . a)."""
+    mass = _f64(mass)
+    n = mass.shape[0]
+    out = np.empty(10)
+    _load().oracle_diagnostics(n, _p(_f64(pos, (3, n))), _p(_f64(vel, (3, n))), _p(mass), _p(_f64(pot, (n,))),
+                               _p(_f64(acc, (3, n))), _p(out))
+    return out

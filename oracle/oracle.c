@@ -365,3 +365,33 @@ EXPORT void oracle_lj_kdk(int64_t n, double sigma, double epsilon, double soft, 
     }
     free(acc);
 }
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics of one system from its state and a force evaluation (any pair law):
+ *   out = {KE, PE, Px, Py, Pz, Lx, Ly, Lz, W, M}
+ *   KE = 1/2 sum m |v|^2, PE = 1/2 sum m pot, P = sum m v, L = sum m x cross v,
+ *   W = sum m x . a (the virial of the pair forces), M = sum m.
+ * pot is the per-particle potential per unit mass and acc the acceleration, as the
+ * force routines return them.
+ * --------------------------------------------------------------------------- */
+EXPORT void oracle_diagnostics(int64_t n, const double *pos, const double *vel, const double *mass,
+                               const double *pot, const double *acc, double *out)
+{
+    for (int k = 0; k < 10; ++k) out[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double m = mass[i];
+        const double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+        const double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+        const double ax = acc[i], ay = acc[n + i], az = acc[2 * n + i];
+        out[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+        out[1] += 0.5 * m * pot[i];
+        out[2] += m * vx;
+        out[3] += m * vy;
+        out[4] += m * vz;
+        out[5] += m * (y * vz - z * vy);
+        out[6] += m * (z * vx - x * vz);
+        out[7] += m * (x * vy - y * vx);
+        out[8] += m * (x * ax + y * ay + z * az);
+        out[9] += m;
+    }
+}
