@@ -146,6 +146,16 @@ int nbody_rollout(const nbody_config *cfg, int64_t n, double dt, int64_t steps, 
 int nbody_energy_momentum(const nbody_config *cfg, int64_t n, const double *pos, const double *vel,
                           const double *mass, const double *pot, double *out);
 
+/* Diagnostics of every system from its state and a force evaluation of any pair law
+ * (the pot and acc written by nbody_forces or nbody_lj_forces for these positions):
+ *   out [n_systems][10] double: KE, PE, Px, Py, Pz, Lx, Ly, Lz, W, M with
+ *   L = sum m x cross v (angular momentum about the origin), W = sum m x . a (the virial
+ *   of the pair forces; for a gas in a box it gives the pressure), M = sum m.
+ * Reduced in FP64 by the same deterministic two-pass tree as the energy. G and eps
+ * are not used. */
+int nbody_diagnostics(const nbody_config *cfg, int64_t n, const double *pos, const double *vel,
+                      const double *mass, const double *pot, const double *acc, double *out);
+
 /* Reverse-mode gradient of a function of the final state of a rollout made by
  * nbody_rollout(cfg, n, dt, steps, ckpt_every, ...) with the same cfg:
  * the exact adjoint of the discrete KDK map (discretise, then differentiate).

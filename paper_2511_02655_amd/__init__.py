@@ -32,7 +32,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPAC
 EXPORTED = ("nbody_abi_version", "nbody_last_error", "nbody_workspace_size", "nbody_forces", "nbody_step",
             "nbody_rollout", "nbody_energy_momentum", "nbody_rollout_backward", "nbody_set_tile_table",
             "nbody_tile_variants", "nbody_tile_lookup", "nbody_lj_forces", "nbody_lj_rollout",
-            "nbody_rollout_backward_reversible")
+            "nbody_rollout_backward_reversible", "nbody_diagnostics")
 
 
 class NBodyError(RuntimeError):
@@ -103,6 +103,7 @@ def lib():
         "nbody_step": ([C, I64, D, P, P, P, P, P], ctypes.c_int),
         "nbody_rollout": ([C, I64, D, I64, I64, P, P, P, P, P, P], ctypes.c_int),
         "nbody_energy_momentum": ([C, I64, P, P, P, P, P], ctypes.c_int),
+        "nbody_diagnostics": ([C, I64, P, P, P, P, P, P], ctypes.c_int),
         "nbody_rollout_backward": ([C, I64, D, I64, I64, P, P, P, P, P, P, P], ctypes.c_int),
         "nbody_rollout_backward_reversible": ([C, I64, D, I64, P, P, P, P, P, P, P, P], ctypes.c_int),
         "nbody_set_tile_table": ([ctypes.POINTER(TileEntry), I64], ctypes.c_int),
@@ -386,6 +387,23 @@ def lj_rollout(pos, vel, mass, acc, dt, steps, *, sigma=1.0, epsilon=1.0, soft=0
                                   _dptr(pos, "pos", (3, n)), _dptr(vel, "vel", (3, n)), _dptr(mass, "mass"),
                                   _dptr(acc, "acc", (3, n)), _dptr(trace, "energy_trace")))
     return trace
+
+
+DIAGNOSTICS = ("KE", "PE", "Px", "Py", "Pz", "Lx", "Ly", "Lz", "W", "M")
+
+
+def diagnostics(pos, vel, mass, pot, acc, *, precision="fp32c", offsets=None, flags=0, stream=None):
+    """(S, 10) per system: KE, PE, Px, Py, Pz, Lx, Ly, Lz, W = sum m x.a, M (see DIAGNOSTICS),
+    from the state and the pot / acc of a force call (either pair law)."""
+    torch = _torch()
+    n = _n_of(mass)
+    c = _Cfg(precision, 1.0, 1.0, offsets, flags, stream)
+    c.workspace(n, device=mass.device)
+    out = torch.empty((c.cfg.n_systems, 10), dtype=torch.float64, device=mass.device)
+    _check(lib().nbody_diagnostics(ctypes.byref(c.cfg), n, _dptr(pos, "pos", (3, n)), _dptr(vel, "vel", (3, n)),
+                                   _dptr(mass, "mass"), _dptr(pot, "pot", (n,)), _dptr(acc, "acc", (3, n)),
+                                   _dptr(out, "out")))
+    return out
 
 
 def rollout_backward_reversible(mass, pos_final, vel_final, gpos_final, gvel_final, dt, steps, *, G=1.0, eps=1e-2,

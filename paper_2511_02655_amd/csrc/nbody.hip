@@ -648,7 +648,7 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
   int64_t chunks = std::min<int64_t>(std::max<int64_t>(1, cdiv(sys.max_n, 256 * 4)), bat ? 16 : 1024);
   p.e_chunks = (int32_t)chunks;
   if (need & (NEED_ENERGY | NEED_ROLLOUT)) {
-    p.sz_epart = (size_t)sys.S * chunks * 5 * dsz;
+    p.sz_epart = (size_t)sys.S * chunks * kDiag * dsz;  // energy (5) or diagnostics (10) partials
     p.off_epart = take(p.sz_epart);
     p.sz_pot = (size_t)n * dsz;
     p.off_pot = take(p.sz_pot);
@@ -708,9 +708,11 @@ struct Ctx {
   }
 };
 
+// lj: the Lennard-Jones law (nullptr: gravity); law_free: a call that uses no pair law
+// (its G and eps are not checked).
 int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsigned need,
-            const nbody_lj_params* lj = nullptr) {
-  TRY(check_cfg(cfg, n, c.sys, lj == nullptr));
+            const nbody_lj_params* lj = nullptr, bool law_free = false) {
+  TRY(check_cfg(cfg, n, c.sys, lj == nullptr && !law_free));
   if (lj) {
     TRY(check_lj(cfg, lj));
     c.law = LAW_LJ;
@@ -984,6 +986,28 @@ int energy_pass(Ctx& c, const double* vel, const double* mass, const double* pot
   }
   hipLaunchKernelGGL(energy_final<256>, dim3((unsigned)c.sys.S), dim3(256), 0, c.st, chunks, ep, out);
   LAUNCH_CHECK("energy_final");
+  return NBODY_OK;
+}
+
+int diag_pass(Ctx& c, const double* pos, const double* vel, const double* mass, const double* pot,
+              const double* acc, double* out) {
+  const int32_t chunks = c.plan.e_chunks;
+  double* ep = (double*)(c.ws + c.plan.off_epart);
+  const int64_t* dev_off = c.bat ? (const int64_t*)(c.ws + c.plan.off_sysoff) : nullptr;
+  if (c.bat && c.loop) {
+    for (int64_t s = 0; s < c.sys.S; ++s) {
+      const int64_t b = c.sys.off[s], ns = c.sys.off[s + 1] - b;
+      hipLaunchKernelGGL(diag_partial<256>, dim3(chunks, 1), dim3(256), 0, c.st, c.n, pos + b, vel + b, mass + b,
+                         pot + b, acc + b, (const int64_t*)nullptr, ns, chunks, ep + s * chunks * kDiag);
+      LAUNCH_CHECK("diag_partial");
+    }
+  } else {
+    hipLaunchKernelGGL(diag_partial<256>, dim3(chunks, (unsigned)c.sys.S), dim3(256), 0, c.st, c.n, pos, vel, mass, pot,
+                       acc, dev_off, c.n, chunks, ep);
+    LAUNCH_CHECK("diag_partial");
+  }
+  hipLaunchKernelGGL(diag_final<256>, dim3((unsigned)c.sys.S), dim3(256), 0, c.st, chunks, ep, out);
+  LAUNCH_CHECK("diag_final");
   return NBODY_OK;
 }
 
@@ -1272,6 +1296,25 @@ __attribute__((visibility("default"))) int nbody_energy_momentum(const nbody_con
     p = pw;
   }
   return energy_pass(c, vel, mass, p, out);
+}
+
+__attribute__((visibility("default"))) int nbody_diagnostics(const nbody_config* cfg, int64_t n, const double* pos,
+                                                             const double* vel, const double* mass, const double* pot,
+                                                             const double* acc, double* out) {
+  g_err.clear();
+  Ctx c;
+  // law-free: pot and acc come from the caller's force pass, G and eps are not used
+  TRY(prepare(c, cfg, n, 1, NEED_ENERGY, nullptr, true));
+  if (!out) return fail(NBODY_ERR_INVALID_ARG, "out must be non-NULL");
+  if (n == 0) {
+    hipLaunchKernelGGL(fill_f64, grid1d(c.sys.S * kDiag), dim3(256), 0, c.st, out, c.sys.S * kDiag, 0.0);
+    LAUNCH_CHECK("fill_f64");
+    return NBODY_OK;
+  }
+  if (!pos || !vel || !mass || !pot || !acc)
+    return fail(NBODY_ERR_INVALID_ARG, "pos, vel, mass, pot and acc must be non-NULL");
+  TRY(upload_meta(c));
+  return diag_pass(c, pos, vel, mass, pot, acc, out);
 }
 
 __attribute__((visibility("default"))) int nbody_rollout_backward(const nbody_config* cfg, int64_t n, double dt,

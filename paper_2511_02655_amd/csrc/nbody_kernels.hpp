@@ -881,10 +881,10 @@ __global__ void fill_f64(double* p, int64_t count, double v) {
 // Deterministic two-pass reduction per system. Pass 1: block (bx, s) sums chunk bx
 // of system s (grid-stride over the system, fixed order), wave64 shuffle tree then
 // LDS tree; writes part[s][bx][5]. Pass 2: one block per system sums its chunks.
-template <int BS>
-__device__ __forceinline__ void block_sum5(double v[5], double* sh /* [5][BS/64] */) {
+template <int BS, int K>
+__device__ __forceinline__ void block_sum(double v[K], double* sh /* [K][BS/64] */) {
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < K; ++c) {
     double x = v[c];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -893,16 +893,21 @@ __device__ __forceinline__ void block_sum5(double v[5], double* sh /* [5][BS/64]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
-    for (int c = 0; c < 5; ++c) sh[c * (BS / 64) + wave] = v[c];
+    for (int c = 0; c < K; ++c) sh[c * (BS / 64) + wave] = v[c];
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < K; ++c) {
       double x = 0.0;
       for (int w = 0; w < BS / 64; ++w) x += sh[c * (BS / 64) + w];
       v[c] = x;
     }
   }
+}
+
+template <int BS>
+__device__ __forceinline__ void block_sum5(double v[5], double* sh /* [5][BS/64] */) {
+  block_sum<BS, 5>(v, sh);
 }
 
 template <int BS>
@@ -943,6 +948,61 @@ __global__ __launch_bounds__(BS) void energy_final(int32_t chunks, const double*
   if (threadIdx.x == 0)
 #pragma unroll
     for (int c = 0; c < 5; ++c) out[s * 5 + c] = v[c];
+}
+
+// Diagnostics, the same two-pass scheme with K = 10 components per system:
+// KE, PE, Px, Py, Pz, Lx, Ly, Lz (L = sum m x cross v), W (= sum m x . a), M.
+constexpr int kDiag = 10;
+
+template <int BS>
+__global__ __launch_bounds__(BS) void diag_partial(int64_t n, const double* __restrict__ pos,
+                                                   const double* __restrict__ vel, const double* __restrict__ mass,
+                                                   const double* __restrict__ pot, const double* __restrict__ acc,
+                                                   const int64_t* __restrict__ sys_off, int64_t single_n,
+                                                   int32_t chunks, double* __restrict__ part) {
+  __shared__ double sh[kDiag * (BS / 64)];
+  const int64_t s = blockIdx.y;
+  const int64_t b = sys_off ? sys_off[s] : 0;
+  const int64_t e = sys_off ? sys_off[s + 1] : single_n;
+  double v[kDiag];
+#pragma unroll
+  for (int c = 0; c < kDiag; ++c) v[c] = 0.0;
+  for (int64_t i = b + (int64_t)blockIdx.x * BS + threadIdx.x; i < e; i += (int64_t)chunks * BS) {
+    const double m = mass[i];
+    const double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+    const double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+    v[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+    v[1] += 0.5 * m * pot[i];
+    v[2] += m * vx;
+    v[3] += m * vy;
+    v[4] += m * vz;
+    v[5] += m * (y * vz - z * vy);
+    v[6] += m * (z * vx - x * vz);
+    v[7] += m * (x * vy - y * vx);
+    v[8] += m * (x * acc[i] + y * acc[n + i] + z * acc[2 * n + i]);
+    v[9] += m;
+  }
+  block_sum<BS, kDiag>(v, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < kDiag; ++c) part[(s * chunks + blockIdx.x) * kDiag + c] = v[c];
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void diag_final(int32_t chunks, const double* __restrict__ part,
+                                                 double* __restrict__ out) {
+  __shared__ double sh[kDiag * (BS / 64)];
+  const int64_t s = blockIdx.x;
+  double v[kDiag];
+#pragma unroll
+  for (int c = 0; c < kDiag; ++c) v[c] = 0.0;
+  for (int k = threadIdx.x; k < chunks; k += BS)
+#pragma unroll
+    for (int c = 0; c < kDiag; ++c) v[c] += part[(s * chunks + k) * kDiag + c];
+  block_sum<BS, kDiag>(v, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < kDiag; ++c) out[s * kDiag + c] = v[c];
 }
 
 // ----------------------------------------------------------------- adjoint pair pass

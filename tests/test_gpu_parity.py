@@ -404,6 +404,62 @@ def test_batched_symmetric_rollout_matches_looped(nb, oracle):
         np.testing.assert_allclose(outs[0][1][:, s, 1], er[:, 1], rtol=1e-5)
 
 
+# ------------------------------------------------------------------ diagnostics (angular momentum, virial)
+
+def test_diagnostics_vs_oracle(nb, oracle):
+    """KE, PE, P, L, W, M per system (empty and single systems included) against the oracle,
+    both from each side's own force evaluation and as a pure reduction of the GPU's."""
+    sizes = [0, 1, 300, 1200]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    g = np.random.Generator(np.random.PCG64(51))
+    pos, vel, mass = g.normal(size=(3, n)), g.normal(size=(3, n)), g.uniform(0.5, 1.5, n) / n
+    for flags in (0, nb.FLAG_LOOP_SYSTEMS):
+        acc, pot = nb.forces(dev(pos), dev(mass), precision="fp64", want_pot=True, offsets=off, flags=flags)
+        d = host(nb.diagnostics(dev(pos), dev(vel), dev(mass), pot, acc, offsets=off, flags=flags))
+        assert d.shape == (len(sizes), 10)
+        a_h, p_h = host(acc), host(pot)
+        for k in range(len(sizes)):
+            sl = slice(off[k], off[k + 1])
+            if sizes[k] == 0:
+                assert np.all(d[k] == 0)
+                continue
+            same = oracle.diagnostics(pos[:, sl], vel[:, sl], mass[sl], p_h[sl], a_h[:, sl])
+            a_r, p_r = oracle.forces(pos[:, sl], mass[sl])
+            ref = oracle.diagnostics(pos[:, sl], vel[:, sl], mass[sl], p_r, a_r)
+            scale = np.array([abs(ref[0]), abs(ref[1]) + 1e-300] + [np.abs(ref[2:5]).max() + ref[0] ** 0.5] * 3
+                             + [np.abs(ref[5:8]).max() + 1e-300] * 3 + [abs(ref[1]) + 1e-300, ref[9]])
+            assert np.max(np.abs(d[k] - same) / scale) <= 1e-13
+            assert np.max(np.abs(d[k] - ref) / scale) <= 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-6)])
+def test_angular_momentum_conserved_on_gpu(nb, prec, tol):
+    """Central pair forces and the KDK map conserve L: over 100 steps of a Plummer sphere it
+    stays constant to rounding (FP32 pair math breaks exact centrality at float rounding)."""
+    s = inputs.plummer(3000, 52)
+    pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+    acc, pot = nb.forces(pos, mass, precision=prec, want_pot=True)
+    L0 = host(nb.diagnostics(pos, vel, mass, pot, acc))[0, 5:8]
+    nb.rollout(pos, vel, mass, acc, 1e-3, 100, precision=prec)
+    acc, pot = nb.forces(pos, mass, precision=prec, want_pot=True)
+    L1 = host(nb.diagnostics(pos, vel, mass, pot, acc))[0, 5:8]
+    scale = float(np.sum(s.mass * np.linalg.norm(s.pos, axis=0) * np.linalg.norm(s.vel, axis=0)))
+    assert np.max(np.abs(L1 - L0)) <= tol * scale
+
+
+def test_lj_virial_on_gpu(nb, oracle):
+    """The Lennard-Jones gas's virial from the GPU's LJ forces, against the oracle."""
+    s, box = inputs.lj_gas(2000, 53, spacing=1.2)
+    acc, pot = nb.lj_forces(dev(s.pos), dev(s.mass), precision="fp64", want_pot=True)
+    d = host(nb.diagnostics(dev(s.pos), dev(s.vel), dev(s.mass), pot, acc))[0]
+    a_r, p_r = oracle.lj_forces(s.pos, s.mass)
+    ref = oracle.diagnostics(s.pos, s.vel, s.mass, p_r, a_r)
+    assert d[8] == pytest.approx(ref[8], rel=1e-10)
+    assert d[1] == pytest.approx(ref[1], rel=1e-10)
+
+
 # ------------------------------------------------------------------ adjoint
 
 def _rel_l2(a, b):
