@@ -864,8 +864,42 @@ int persistent_grid(const void* kfn, int bs, int64_t units, unsigned& grid) {
   return NBODY_OK;
 }
 
+// The first half of the next KDK step (dt), to be fused into this force pass's reduction.
+NextStep next_step(const Ctx& c, double dt, double* pos, const double* mass) {
+  NextStep nx{};
+  const int prec = c.cfg->precision;
+  nx.kind = is_fp64(prec) ? 2 : is_ds(prec) ? 3 : 1;
+  nx.pos = pos;
+  nx.mass = mass;
+  nx.hh = 0.5 * dt;
+  nx.h = dt;
+  nx.xs = c.xs;
+  nx.wl = c.wl;
+  nx.jarr = c.ws + c.plan.off_jbuf;
+  return nx;
+}
+
+// The same, for the particles of a system starting at global index b (offset pointers).
+NextStep next_step_at(const Ctx& c, const NextStep* nx, int64_t b) {
+  NextStep r{};
+  if (!nx) return r;  // kind 0: nothing fused
+  r = *nx;
+  r.pos += b;
+  r.mass += b;
+  r.jarr = (char*)r.jarr + (size_t)b * jvec_bytes(c.cfg->precision);
+  return r;
+}
+
 // Force pass on the staged j-array: acc = a, pot (nullable), vel += hh*acc when vel != NULL.
-int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
+// nx (nullable): also perform the next step's kick, drift, walls and staging inside the
+// pass's per-particle reduction; *fused tells whether that happened (it cannot when the
+// pass has no separate reduction, or for the per-system loop), in which case the caller
+// runs kick_drift itself.
+int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, const NextStep* nx = nullptr,
+               bool* fused = nullptr) {
+  if (fused) *fused = false;
+  if (c.loop || !vel) nx = nullptr;  // all systems or none (the loop may mix reduced and direct
+                                     // passes); the fused kick needs the velocities
   const int prec = c.cfg->precision;
   const int mode = force_mode(prec);
   const int pot_on = pot != nullptr;
@@ -890,8 +924,9 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
                                (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("force_sym_kernel");
       hipLaunchKernelGGL(reduce_sym, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)nb, (const float*)pf, c.ls_at(b),
-                         acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh);
+                         acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, next_step_at(c, nx, b));
       LAUNCH_CHECK("reduce_sym");
+      if (nx && fused) *fused = true;
       return NBODY_OK;
     }
     int64_t S, jc;
@@ -913,8 +948,9 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
       // reduce only this system's particle range: offset pointers into the planes
       hipLaunchKernelGGL(reduce_splits, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)S, part + b, c.ls_at(b),
                          acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, (int64_t)0,
-                         (const int64_t*)nullptr, (const int32_t*)nullptr);
+                         (const int64_t*)nullptr, (const int32_t*)nullptr, next_step_at(c, nx, b));
       LAUNCH_CHECK("reduce_splits");
+      if (nx && fused) *fused = true;
     }
     return NBODY_OK;
   };
@@ -942,8 +978,10 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
     LAUNCH_CHECK("force_sym_batched_kernel");
     hipLaunchKernelGGL(reduce_sym_batched, grid1d(n), dim3(256), 0, c.st, n, c.sys.S,
                        (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit),
-                       (const int64_t*)(c.ws + c.plan.off_partoff), (const float*)pf, c.ls, acc, pot, vel, hh);
+                       (const int64_t*)(c.ws + c.plan.off_partoff), (const float*)pf, c.ls, acc, pot, vel, hh,
+                       next_step_at(c, nx, 0));
     LAUNCH_CHECK("reduce_sym_batched");
+    if (nx && fused) *fused = true;
     return NBODY_OK;
   }
   if (c.uf.sym) return fail(NBODY_ERR_DEVICE, "internal: one-sided batched tile with symmetric units");
@@ -961,8 +999,10 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh) {
                             (int32_t)c.plan.n_units_force, counter, eps2, o);
   LAUNCH_CHECK("force_batched_kernel");
   hipLaunchKernelGGL(reduce_splits, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, c.ls, acc, pot, vel, hh,
-                     c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit));
+                     c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit),
+                     next_step_at(c, nx, 0));
   LAUNCH_CHECK("reduce_splits");
+  if (nx && fused) *fused = true;
   return NBODY_OK;
 }
 
@@ -1220,9 +1260,15 @@ int rollout_impl(Ctx& c, int64_t n, double dt, int64_t steps, int64_t ckpt_every
     TRY(force_pass(c, (double*)(c.ws + c.plan.off_accs), pot, nullptr, 0.0));
     TRY(energy_pass(c, vel, mass, pot, energy_trace));
   }
+  const NextStep nx = next_step(c, dt, pos, mass);
+  bool staged = false;  // the previous pass already ran this step's kick, drift and staging
   for (int64_t s = 0; s < steps; ++s) {
-    TRY(kick_drift(c, dt, pos, vel, acc, mass));
-    TRY(force_pass(c, acc, pot, vel, 0.5 * dt));
+    if (!staged) TRY(kick_drift(c, dt, pos, vel, acc, mass));
+    // the next step's first half can ride on this pass unless the state at s + 1 is read
+    // in between (energy trace, checkpoint) or there is no next step
+    const bool read_state = energy_trace || (ckpt && (s + 1) % ckpt_every == 0);
+    const bool fuse = s + 1 < steps && !read_state;
+    TRY(force_pass(c, acc, pot, vel, 0.5 * dt, fuse ? &nx : nullptr, &staged));
     if (energy_trace) TRY(energy_pass(c, vel, mass, pot, energy_trace + (s + 1) * S * 5));
     if (ckpt && (s + 1) % ckpt_every == 0) {
       double* slot = ckpt + (size_t)((s + 1) / ckpt_every) * 6 * n;

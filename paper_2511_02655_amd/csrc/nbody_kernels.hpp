@@ -223,6 +223,48 @@ struct LawScale {
 
 __device__ __forceinline__ double law_div(const LawScale& ls, int64_t i) { return ls.mdiv ? ls.mdiv[i] : 1.0; }
 
+// The next kick-drift-kick step's first half, fused into the kernel that finishes the
+// current step (the per-particle reduction of the force pass): after the closing kick
+// v += hh a of step n, the opening kick v += hh a of step n+1, the drift x += h v, the
+// walls and the staging of x into the j-array - the same operations in the same order
+// as kick_drift_stage, so trajectories are bitwise those of the unfused loop.
+// kind: 0 none, 1 float j-array, 2 double, 3 double-float (two float4 per particle).
+struct NextStep {
+  int32_t kind;
+  int32_t pad;
+  double* pos;
+  const double* mass;
+  double hh, h, xs;
+  Walls wl;
+  void* jarr;
+};
+
+// vel planes already hold v after the closing kick of particle i; a = its acceleration.
+__device__ __forceinline__ void next_step_tail(const NextStep& ns, int64_t i, int64_t n, const double a[3],
+                                               double* __restrict__ vel) {
+  double x[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double v = vel[c * n + i] + ns.hh * a[c];
+    double xc = ns.pos[c * n + i] + ns.h * v;
+    if (ns.wl.on) {
+      if (xc < ns.wl.lo[c]) {
+        xc = 2.0 * ns.wl.lo[c] - xc;
+        v = -v;
+      } else if (xc > ns.wl.hi[c]) {
+        xc = 2.0 * ns.wl.hi[c] - xc;
+        v = -v;
+      }
+    }
+    vel[c * n + i] = v;
+    ns.pos[c * n + i] = xc;
+    x[c] = xc;
+  }
+  if (ns.kind == 1) put_j<float, false>((float4*)ns.jarr, i, x, ns.mass[i], ns.xs);
+  else if (ns.kind == 2) put_j<double, false>((D4*)ns.jarr, i, x, ns.mass[i], ns.xs);
+  else put_j<float, true>((float4*)ns.jarr, i, x, ns.mass[i], ns.xs);
+}
+
 // Sum of j-split partials (fixed order p = 0..S-1), scaled by the law's constants;
 // optional potential and optional closing half-kick v += hh a.
 //   part [S][4][n]: planes ax, ay, az, phi of every split.
@@ -232,7 +274,8 @@ __device__ __forceinline__ double law_div(const LawScale& ls, int64_t i) { retur
 __global__ void reduce_splits(int64_t count, int64_t stride, int32_t S, const double* __restrict__ part, LawScale ls,
                               double* __restrict__ acc, double* __restrict__ pot,
                               double* __restrict__ vel, double hh, int64_t n_sys,
-                              const int64_t* __restrict__ sys_off, const int32_t* __restrict__ nsplit) {
+                              const int64_t* __restrict__ sys_off, const int32_t* __restrict__ nsplit,
+                              NextStep nx) {
   const int64_t n = stride;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -250,13 +293,15 @@ __global__ void reduce_splits(int64_t count, int64_t stride, int32_t S, const do
 #pragma unroll
     for (int c = 0; c < 4; ++c) a[c] += part[((int64_t)p * 4 + c) * n + i];
   const double md = law_div(ls, i);
+  double ac[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double ac = ls.ca * a[c] / md;
-    acc[c * n + i] = ac;
-    if (vel) vel[c * n + i] += hh * ac;
+    ac[c] = ls.ca * a[c] / md;
+    acc[c * n + i] = ac[c];
+    if (vel) vel[c * n + i] += hh * ac[c];
   }
   if (pot) pot[i] = ls.cp * a[3] / md;
+  if (nx.kind) next_step_tail(nx, i, n, ac, vel);
 }
 
 // ----------------------------------------------------------------- force pair pass
@@ -753,7 +798,8 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 // law's constants; optional potential and closing half-kick.
 // n: particles of the system (partial plane stride); stride: plane stride of acc/vel.
 __global__ void reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* __restrict__ part, LawScale ls,
-                           double* __restrict__ acc, double* __restrict__ pot, double* __restrict__ vel, double hh) {
+                           double* __restrict__ acc, double* __restrict__ pot, double* __restrict__ vel, double hh,
+                           NextStep nx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int nc = pot ? 4 : 3;
@@ -761,13 +807,15 @@ __global__ void reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* _
   for (int32_t s = 0; s < nb; ++s)
     for (int c = 0; c < nc; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
   const double md = law_div(ls, i);
+  double ac[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double ac = ls.ca * a[c] / md;
-    acc[c * stride + i] = ac;
-    if (vel) vel[c * stride + i] += hh * ac;
+    ac[c] = ls.ca * a[c] / md;
+    acc[c * stride + i] = ac[c];
+    if (vel) vel[c * stride + i] += hh * ac[c];
   }
   if (pot) pot[i] = ls.cp * a[3] / md;
+  if (nx.kind) next_step_tail(nx, i, stride, ac, vel);
 }
 
 // ----------------------------------------------------------------- batched symmetric pass
@@ -808,7 +856,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_batched_kernel(const float4*
 __global__ void reduce_sym_batched(int64_t n, int64_t n_sys, const int64_t* __restrict__ sys_off,
                                    const int32_t* __restrict__ sys_nb, const int64_t* __restrict__ sys_part,
                                    const float* __restrict__ part, LawScale ls, double* __restrict__ acc,
-                                   double* __restrict__ pot, double* __restrict__ vel, double hh) {
+                                   double* __restrict__ pot, double* __restrict__ vel, double hh, NextStep nx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int64_t lo = 0, hi = n_sys;  // s with sys_off[s] <= i < sys_off[s+1]
@@ -824,13 +872,15 @@ __global__ void reduce_sym_batched(int64_t n, int64_t n_sys, const int64_t* __re
   for (int32_t k = 0; k < nb; ++k)
     for (int c = 0; c < nc; ++c) a[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
   const double md = law_div(ls, i);
+  double ac[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double ac = ls.ca * a[c] / md;
-    acc[c * n + i] = ac;
-    if (vel) vel[c * n + i] += hh * ac;
+    ac[c] = ls.ca * a[c] / md;
+    acc[c * n + i] = ac[c];
+    if (vel) vel[c * n + i] += hh * ac[c];
   }
   if (pot) pot[i] = ls.cp * a[3] / md;
+  if (nx.kind) next_step_tail(nx, i, n, ac, vel);
 }
 
 // ----------------------------------------------------------------- batched persistent force pass
