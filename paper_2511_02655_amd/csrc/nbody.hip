@@ -644,8 +644,11 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
   p.off_jbuf = take(p.sz_jbuf);
   p.sz_part = std::max(force_part, adj_part);
   p.off_part = take(p.sz_part);
-  // energy partials: chunks per system
-  int64_t chunks = std::min<int64_t>(std::max<int64_t>(1, cdiv(sys.max_n, 256 * 4)), bat ? 16 : 1024);
+  // energy partials: chunks of 256 threads per system, about one particle per thread (the
+  // energy can ride on a per-particle reduction, which needs that parallelism), with at most
+  // max(16 S, 32768) chunks in all
+  const int64_t chunk_cap = std::max<int64_t>(16, 32768 / std::max<int64_t>(1, sys.S));
+  int64_t chunks = std::min<int64_t>(std::max<int64_t>(1, cdiv(sys.max_n, 256)), chunk_cap);
   p.e_chunks = (int32_t)chunks;
   if (need & (NEED_ENERGY | NEED_ROLLOUT)) {
     p.sz_epart = (size_t)sys.S * chunks * kDiag * dsz;  // energy (5) or diagnostics (10) partials
@@ -890,16 +893,47 @@ NextStep next_step_at(const Ctx& c, const NextStep* nx, int64_t b) {
   return r;
 }
 
+// Optional work fused into a force pass's per-particle reduction.
+struct Fuse {
+  const NextStep* nx = nullptr;  // the next step's kick, drift, walls and staging
+  double* eout = nullptr;        // energy and momentum of the new state, [S][5] (needs pot and vel)
+  const double* mass = nullptr;  // masses, with eout
+  bool done = false;             // set by force_pass: the pass had such a reduction and did all of it
+};
+
 // Force pass on the staged j-array: acc = a, pot (nullable), vel += hh*acc when vel != NULL.
-// nx (nullable): also perform the next step's kick, drift, walls and staging inside the
-// pass's per-particle reduction; *fused tells whether that happened (it cannot when the
-// pass has no separate reduction, or for the per-system loop), in which case the caller
-// runs kick_drift itself.
-int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, const NextStep* nx = nullptr,
-               bool* fused = nullptr) {
-  if (fused) *fused = false;
-  if (c.loop || !vel) nx = nullptr;  // all systems or none (the loop may mix reduced and direct
-                                     // passes); the fused kick needs the velocities
+// fz (nullable): work to fuse into the pass's per-particle reduction. A pass without one (a
+// one-sided pass that writes accelerations directly) or the per-system loop fuses nothing and
+// leaves fz->done false; the caller then runs energy_pass and kick_drift itself.
+int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* fz = nullptr) {
+  const NextStep* nx = nullptr;
+  EnergyFuse ef{};
+  if (fz) {
+    fz->done = false;
+    if (c.loop || !vel || (fz->eout && (!pot || !fz->mass))) fz = nullptr;  // all systems or none; the
+                                                                          // kick needs the velocities
+  }
+  if (fz) {
+    nx = fz->nx;
+    if (fz->eout) {
+      ef.part = (double*)(c.ws + c.plan.off_epart);
+      ef.mass = fz->mass;
+      ef.chunks = c.plan.e_chunks;
+    }
+  }
+  // the reduction's launch geometry: one thread per particle, or the energy chunk grid
+  auto rgrid = [&](int64_t count) { return ef.part ? dim3((unsigned)ef.chunks, (unsigned)c.sys.S) : grid1d(count); };
+  // after a reduction that carried the fused work, finish the energy sum
+  auto fused_tail = [&]() -> int {
+    if (!fz) return NBODY_OK;
+    if (ef.part) {
+      hipLaunchKernelGGL(energy_final<256>, dim3((unsigned)c.sys.S), dim3(256), 0, c.st, ef.chunks,
+                         (const double*)ef.part, fz->eout);
+      LAUNCH_CHECK("energy_final");
+    }
+    fz->done = true;
+    return NBODY_OK;
+  };
   const int prec = c.cfg->precision;
   const int mode = force_mode(prec);
   const int pot_on = pot != nullptr;
@@ -923,11 +957,11 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, const N
       sv.fn[law][pot_on][mode](dim3((unsigned)tiles), c.st, (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b, ns,
                                (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("force_sym_kernel");
-      hipLaunchKernelGGL(reduce_sym, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)nb, (const float*)pf, c.ls_at(b),
-                         acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, next_step_at(c, nx, b));
+      hipLaunchKernelGGL(reduce_sym, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n, (int32_t)nb, (const float*)pf,
+                         c.ls_at(b), acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh,
+                         next_step_at(c, nx, b), ef);
       LAUNCH_CHECK("reduce_sym");
-      if (nx && fused) *fused = true;
-      return NBODY_OK;
+      return fused_tail();
     }
     int64_t S, jc;
     split_geometry(t, ns, S, jc);
@@ -946,11 +980,11 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, const N
     LAUNCH_CHECK("force_kernel");
     if (S > 1) {
       // reduce only this system's particle range: offset pointers into the planes
-      hipLaunchKernelGGL(reduce_splits, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)S, part + b, c.ls_at(b),
-                         acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, (int64_t)0,
-                         (const int64_t*)nullptr, (const int32_t*)nullptr, next_step_at(c, nx, b));
+      hipLaunchKernelGGL(reduce_splits, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n, (int32_t)S, part + b,
+                         c.ls_at(b), acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, (int64_t)0,
+                         (const int64_t*)nullptr, (const int32_t*)nullptr, next_step_at(c, nx, b), ef);
       LAUNCH_CHECK("reduce_splits");
-      if (nx && fused) *fused = true;
+      return fused_tail();
     }
     return NBODY_OK;
   };
@@ -976,13 +1010,12 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, const N
     sv.bfn[law][pot_on][mode](dim3(grid), c.st, (const float4*)jarr, (const SymUnit*)(c.ws + c.plan.off_units),
                               (int32_t)c.plan.n_units_force, counter, (float)eps2, pf);
     LAUNCH_CHECK("force_sym_batched_kernel");
-    hipLaunchKernelGGL(reduce_sym_batched, grid1d(n), dim3(256), 0, c.st, n, c.sys.S,
+    hipLaunchKernelGGL(reduce_sym_batched, rgrid(n), dim3(kReduceBS), 0, c.st, n, c.sys.S,
                        (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit),
                        (const int64_t*)(c.ws + c.plan.off_partoff), (const float*)pf, c.ls, acc, pot, vel, hh,
-                       next_step_at(c, nx, 0));
+                       next_step_at(c, nx, 0), ef);
     LAUNCH_CHECK("reduce_sym_batched");
-    if (nx && fused) *fused = true;
-    return NBODY_OK;
+    return fused_tail();
   }
   if (c.uf.sym) return fail(NBODY_ERR_DEVICE, "internal: one-sided batched tile with symmetric units");
   const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
@@ -998,12 +1031,11 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, const N
   fv.bfn[law][pot_on][mode](dim3(grid), c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
                             (int32_t)c.plan.n_units_force, counter, eps2, o);
   LAUNCH_CHECK("force_batched_kernel");
-  hipLaunchKernelGGL(reduce_splits, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, c.ls, acc, pot, vel, hh,
-                     c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit),
-                     next_step_at(c, nx, 0));
+  hipLaunchKernelGGL(reduce_splits, rgrid(n), dim3(kReduceBS), 0, c.st, n, n, (int32_t)0, part, c.ls, acc, pot, vel,
+                     hh, c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff),
+                     (const int32_t*)(c.ws + c.plan.off_nsplit), next_step_at(c, nx, 0), ef);
   LAUNCH_CHECK("reduce_splits");
-  if (nx && fused) *fused = true;
-  return NBODY_OK;
+  return fused_tail();
 }
 
 int energy_pass(Ctx& c, const double* vel, const double* mass, const double* pot, double* out) {
@@ -1264,12 +1296,17 @@ int rollout_impl(Ctx& c, int64_t n, double dt, int64_t steps, int64_t ckpt_every
   bool staged = false;  // the previous pass already ran this step's kick, drift and staging
   for (int64_t s = 0; s < steps; ++s) {
     if (!staged) TRY(kick_drift(c, dt, pos, vel, acc, mass));
-    // the next step's first half can ride on this pass unless the state at s + 1 is read
-    // in between (energy trace, checkpoint) or there is no next step
-    const bool read_state = energy_trace || (ckpt && (s + 1) % ckpt_every == 0);
-    const bool fuse = s + 1 < steps && !read_state;
-    TRY(force_pass(c, acc, pot, vel, 0.5 * dt, fuse ? &nx : nullptr, &staged));
-    if (energy_trace) TRY(energy_pass(c, vel, mass, pot, energy_trace + (s + 1) * S * 5));
+    // the next step's first half rides on this pass unless the state at s + 1 is copied out
+    // in between (checkpoint) or there is no next step; the energy of the state at s + 1
+    // is reduced inside the same pass, before that next kick
+    const bool ckpt_due = ckpt && (s + 1) % ckpt_every == 0;
+    Fuse fz;
+    fz.nx = s + 1 < steps && !ckpt_due ? &nx : nullptr;
+    fz.eout = energy_trace ? energy_trace + (s + 1) * S * 5 : nullptr;
+    fz.mass = mass;
+    TRY(force_pass(c, acc, pot, vel, 0.5 * dt, &fz));
+    staged = fz.done && fz.nx;
+    if (energy_trace && !fz.done) TRY(energy_pass(c, vel, mass, pot, fz.eout));
     if (ckpt && (s + 1) % ckpt_every == 0) {
       double* slot = ckpt + (size_t)((s + 1) / ckpt_every) * 6 * n;
       TRY(copy_d2d(c, slot, pos, plane3));

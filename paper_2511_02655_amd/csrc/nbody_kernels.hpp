@@ -265,19 +265,126 @@ __device__ __forceinline__ void next_step_tail(const NextStep& ns, int64_t i, in
   else put_j<float, true>((float4*)ns.jarr, i, x, ns.mass[i], ns.xs);
 }
 
+// Block-wide sum of K doubles per thread in a fixed order (wave64 shuffle tree, then the
+// waves in order); the result is valid in thread 0. sh: [K][BS/64] doubles of LDS.
+template <int BS, int K>
+__device__ __forceinline__ void block_sum(double v[K], double* sh) {
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    v[c] = x;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < K; ++c) sh[c * (BS / 64) + wave] = v[c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      double x = 0.0;
+      for (int w = 0; w < BS / 64; ++w) x += sh[c * (BS / 64) + w];
+      v[c] = x;
+    }
+  }
+}
+
+// One particle's share of the energy and momentum: KE, PE (half its mass times its
+// potential), P.
+__device__ __forceinline__ void energy_terms(double m, double vx, double vy, double vz, double phi, double e[5]) {
+  e[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+  e[1] += 0.5 * m * phi;
+  e[2] += m * vx;
+  e[3] += m * vy;
+  e[4] += m * vz;
+}
+
+// Energy of the state a per-particle reduction has just finished, fused into it: the
+// reduction then runs on the (chunk, system) grid of energy_partial, each thread taking
+// the same particles in the same order, and block (chunk, s) writes part[s][chunk][5]
+// exactly as energy_partial would (energy_final completes the sum). part == nullptr:
+// nothing fused, one thread per particle.
+constexpr int kReduceBS = 256;  // block size of every per-particle reduction
+
+struct EnergyFuse {
+  double* part;
+  const double* mass;
+  int32_t chunks;
+  int32_t pad;
+};
+
+// Thread loop of chunk blockIdx.x over the particles [b, e) of system s, with body(i, en)
+// adding particle i's energy terms to en, then the chunk's block sum.
+template <typename F>
+__device__ __forceinline__ void energy_chunk(int64_t b, int64_t e, int64_t s, const EnergyFuse& ef, F&& body) {
+  __shared__ double sh[5 * (kReduceBS / 64)];
+  double en[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = b + (int64_t)blockIdx.x * kReduceBS + threadIdx.x; i < e; i += (int64_t)ef.chunks * kReduceBS)
+    body(i, en);
+  block_sum<kReduceBS, 5>(en, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) ef.part[(s * ef.chunks + blockIdx.x) * 5 + c] = en[c];
+}
+
+// The common end of the per-particle reductions, given particle i's raw sums a[4]:
+// acceleration, closing half kick v += hh a (vel != nullptr), potential (pot != nullptr),
+// its energy terms (en != nullptr; needs pot, vel and emass) and the next step's first half.
+__device__ __forceinline__ void finish_particle(int64_t i, int64_t stride, const double a[4], const LawScale& ls,
+                                                double* __restrict__ acc, double* __restrict__ pot,
+                                                double* __restrict__ vel, double hh, const NextStep& nx,
+                                                const double* __restrict__ emass, double* en) {
+  const double md = law_div(ls, i);
+  double ac[3], v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ac[c] = ls.ca * a[c] / md;
+    acc[c * stride + i] = ac[c];
+    if (vel) {
+      v[c] = vel[c * stride + i] + hh * ac[c];
+      vel[c * stride + i] = v[c];
+    }
+  }
+  double phi = 0.0;
+  if (pot) {
+    phi = ls.cp * a[3] / md;
+    pot[i] = phi;
+  }
+  if (en) energy_terms(emass[i], v[0], v[1], v[2], phi, en);
+  if (nx.kind) next_step_tail(nx, i, stride, ac, vel);
+}
+
 // Sum of j-split partials (fixed order p = 0..S-1), scaled by the law's constants;
 // optional potential and optional closing half-kick v += hh a.
 //   part [S][4][n]: planes ax, ay, az, phi of every split.
 // Batched form: sys_off (device, n_sys+1) and nsplit (device, n_sys) give the split
 // count of the system that owns particle i; single-system form passes n_sys = 0.
 // count particles starting at the given pointers; stride = plane stride of part/acc/vel.
-__global__ void reduce_splits(int64_t count, int64_t stride, int32_t S, const double* __restrict__ part, LawScale ls,
-                              double* __restrict__ acc, double* __restrict__ pot,
-                              double* __restrict__ vel, double hh, int64_t n_sys,
-                              const int64_t* __restrict__ sys_off, const int32_t* __restrict__ nsplit,
-                              NextStep nx) {
+__global__ __launch_bounds__(kReduceBS) void reduce_splits(int64_t count, int64_t stride, int32_t S,
+                                                          const double* __restrict__ part, LawScale ls,
+                                                          double* __restrict__ acc, double* __restrict__ pot,
+                                                          double* __restrict__ vel, double hh, int64_t n_sys,
+                                                          const int64_t* __restrict__ sys_off,
+                                                          const int32_t* __restrict__ nsplit, NextStep nx,
+                                                          EnergyFuse ef) {
   const int64_t n = stride;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  auto body = [&](int64_t i, int32_t s_cnt, double* en) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t p = 0; p < s_cnt; ++p)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c] += part[((int64_t)p * 4 + c) * n + i];
+    finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
+  };
+  if (ef.part) {  // grid (chunks, systems)
+    const int64_t s = blockIdx.y;
+    const int64_t b = n_sys > 0 ? sys_off[s] : 0, e = n_sys > 0 ? sys_off[s + 1] : count;
+    const int32_t s_cnt = n_sys > 0 ? nsplit[s] : S;
+    energy_chunk(b, e, s, ef, [&](int64_t i, double* en) { body(i, s_cnt, en); });
+    return;
+  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   int32_t s_cnt = S;
   if (n_sys > 0) {
@@ -288,20 +395,7 @@ __global__ void reduce_splits(int64_t count, int64_t stride, int32_t S, const do
     }
     s_cnt = nsplit[lo];
   }
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t p = 0; p < s_cnt; ++p)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] += part[((int64_t)p * 4 + c) * n + i];
-  const double md = law_div(ls, i);
-  double ac[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    ac[c] = ls.ca * a[c] / md;
-    acc[c * n + i] = ac[c];
-    if (vel) vel[c * n + i] += hh * ac[c];
-  }
-  if (pot) pot[i] = ls.cp * a[3] / md;
-  if (nx.kind) next_step_tail(nx, i, n, ac, vel);
+  body(i, s_cnt, nullptr);
 }
 
 // ----------------------------------------------------------------- force pair pass
@@ -797,25 +891,24 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 // Sum of the nb float slots of every particle in double (fixed order), scaled by the
 // law's constants; optional potential and closing half-kick.
 // n: particles of the system (partial plane stride); stride: plane stride of acc/vel.
-__global__ void reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* __restrict__ part, LawScale ls,
-                           double* __restrict__ acc, double* __restrict__ pot, double* __restrict__ vel, double hh,
-                           NextStep nx) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__global__ __launch_bounds__(kReduceBS) void reduce_sym(int64_t n, int64_t stride, int32_t nb,
+                                                       const float* __restrict__ part, LawScale ls,
+                                                       double* __restrict__ acc, double* __restrict__ pot,
+                                                       double* __restrict__ vel, double hh, NextStep nx,
+                                                       EnergyFuse ef) {
   const int nc = pot ? 4 : 3;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t s = 0; s < nb; ++s)
-    for (int c = 0; c < nc; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
-  const double md = law_div(ls, i);
-  double ac[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    ac[c] = ls.ca * a[c] / md;
-    acc[c * stride + i] = ac[c];
-    if (vel) vel[c * stride + i] += hh * ac[c];
+  auto body = [&](int64_t i, double* en) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t s = 0; s < nb; ++s)
+      for (int c = 0; c < nc; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
+    finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
+  };
+  if (ef.part) {  // grid (chunks, 1)
+    energy_chunk(0, n, 0, ef, body);
+    return;
   }
-  if (pot) pot[i] = ls.cp * a[3] / md;
-  if (nx.kind) next_step_tail(nx, i, stride, ac, vel);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) body(i, nullptr);
 }
 
 // ----------------------------------------------------------------- batched symmetric pass
@@ -853,10 +946,29 @@ __global__ __launch_bounds__(W * 64) void force_sym_batched_kernel(const float4*
 
 // Per-particle sum of the batched symmetric partials: particle i of system s (found by
 // binary search in sys_off) sums the nb_s float slots of its system's planes in double.
-__global__ void reduce_sym_batched(int64_t n, int64_t n_sys, const int64_t* __restrict__ sys_off,
-                                   const int32_t* __restrict__ sys_nb, const int64_t* __restrict__ sys_part,
-                                   const float* __restrict__ part, LawScale ls, double* __restrict__ acc,
-                                   double* __restrict__ pot, double* __restrict__ vel, double hh, NextStep nx) {
+__global__ __launch_bounds__(kReduceBS) void reduce_sym_batched(int64_t n, int64_t n_sys,
+                                                               const int64_t* __restrict__ sys_off,
+                                                               const int32_t* __restrict__ sys_nb,
+                                                               const int64_t* __restrict__ sys_part,
+                                                               const float* __restrict__ part, LawScale ls,
+                                                               double* __restrict__ acc, double* __restrict__ pot,
+                                                               double* __restrict__ vel, double hh, NextStep nx,
+                                                               EnergyFuse ef) {
+  const int nc = pot ? 4 : 3;
+  auto body = [&](int64_t i, int64_t s, double* en) {
+    const int64_t b = sys_off[s], ns = sys_off[s + 1] - b, li = i - b;
+    const int32_t nb = sys_nb[s];
+    const float* ps = part + sys_part[s];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t k = 0; k < nb; ++k)
+      for (int c = 0; c < nc; ++c) a[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
+    finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
+  };
+  if (ef.part) {  // grid (chunks, systems)
+    const int64_t s = blockIdx.y;
+    energy_chunk(sys_off[s], sys_off[s + 1], s, ef, [&](int64_t i, double* en) { body(i, s, en); });
+    return;
+  }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int64_t lo = 0, hi = n_sys;  // s with sys_off[s] <= i < sys_off[s+1]
@@ -864,23 +976,7 @@ __global__ void reduce_sym_batched(int64_t n, int64_t n_sys, const int64_t* __re
     const int64_t mid = (lo + hi) >> 1;
     if (sys_off[mid] <= i) lo = mid; else hi = mid;
   }
-  const int64_t b = sys_off[lo], ns = sys_off[lo + 1] - b, li = i - b;
-  const int32_t nb = sys_nb[lo];
-  const float* ps = part + sys_part[lo];
-  const int nc = pot ? 4 : 3;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t k = 0; k < nb; ++k)
-    for (int c = 0; c < nc; ++c) a[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
-  const double md = law_div(ls, i);
-  double ac[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    ac[c] = ls.ca * a[c] / md;
-    acc[c * n + i] = ac[c];
-    if (vel) vel[c * n + i] += hh * ac[c];
-  }
-  if (pot) pot[i] = ls.cp * a[3] / md;
-  if (nx.kind) next_step_tail(nx, i, n, ac, vel);
+  body(i, lo, nullptr);
 }
 
 // ----------------------------------------------------------------- batched persistent force pass
@@ -931,35 +1027,6 @@ __global__ void fill_f64(double* p, int64_t count, double v) {
 // Deterministic two-pass reduction per system. Pass 1: block (bx, s) sums chunk bx
 // of system s (grid-stride over the system, fixed order), wave64 shuffle tree then
 // LDS tree; writes part[s][bx][5]. Pass 2: one block per system sums its chunks.
-template <int BS, int K>
-__device__ __forceinline__ void block_sum(double v[K], double* sh /* [K][BS/64] */) {
-#pragma unroll
-  for (int c = 0; c < K; ++c) {
-    double x = v[c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    v[c] = x;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < K; ++c) sh[c * (BS / 64) + wave] = v[c];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-      double x = 0.0;
-      for (int w = 0; w < BS / 64; ++w) x += sh[c * (BS / 64) + w];
-      v[c] = x;
-    }
-  }
-}
-
-template <int BS>
-__device__ __forceinline__ void block_sum5(double v[5], double* sh /* [5][BS/64] */) {
-  block_sum<BS, 5>(v, sh);
-}
-
 template <int BS>
 __global__ __launch_bounds__(BS) void energy_partial(int64_t n, const double* __restrict__ vel,
                                                      const double* __restrict__ mass, const double* __restrict__ pot,
@@ -970,16 +1037,9 @@ __global__ __launch_bounds__(BS) void energy_partial(int64_t n, const double* __
   const int64_t b = sys_off ? sys_off[s] : 0;
   const int64_t e = sys_off ? sys_off[s + 1] : single_n;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = b + (int64_t)blockIdx.x * BS + threadIdx.x; i < e; i += (int64_t)chunks * BS) {
-    const double m = mass[i];
-    const double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
-    v[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
-    v[1] += 0.5 * m * pot[i];
-    v[2] += m * vx;
-    v[3] += m * vy;
-    v[4] += m * vz;
-  }
-  block_sum5<BS>(v, sh);
+  for (int64_t i = b + (int64_t)blockIdx.x * BS + threadIdx.x; i < e; i += (int64_t)chunks * BS)
+    energy_terms(mass[i], vel[i], vel[n + i], vel[2 * n + i], pot[i], v);
+  block_sum<BS, 5>(v, sh);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int c = 0; c < 5; ++c) part[(s * chunks + blockIdx.x) * 5 + c] = v[c];
@@ -994,7 +1054,7 @@ __global__ __launch_bounds__(BS) void energy_final(int32_t chunks, const double*
   for (int k = threadIdx.x; k < chunks; k += BS)
 #pragma unroll
     for (int c = 0; c < 5; ++c) v[c] += part[(s * chunks + k) * 5 + c];
-  block_sum5<BS>(v, sh);
+  block_sum<BS, 5>(v, sh);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int c = 0; c < 5; ++c) out[s * 5 + c] = v[c];

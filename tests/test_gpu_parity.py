@@ -268,6 +268,81 @@ def test_rollout_energy_trace_does_not_change_state(nb, n):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+def _trace_case(nb, case):
+    """(state, kwargs, tile table) of one force-pass path for the fused energy trace."""
+    fp32_one = [k for k, d in enumerate(nb.tile_variants("force", "fp32c")) if "sym=" not in d]
+    fp64_one = list(range(len(nb.tile_variants("force", "fp64"))))
+    bat = nb.tile_variants("force_batched", "fp32c")
+    if case == "sym":  # default tile at this size: the symmetric pass
+        return inputs.plummer(40000, 14), dict(precision="fp32c"), []
+    if case == "sym_ragged":
+        return inputs.plummer(5000, 15), dict(precision="fp32"), [
+            dict(kernel="force", precision="fp32", n_min=0, n_max=1 << 40, variant=_sym_variants(nb)[0], j_split=1)]
+    if case == "split":
+        return inputs.plummer(1500, 16), dict(precision="fp32ds"), [
+            dict(kernel="force", precision="fp32ds", n_min=0, n_max=1 << 40, variant=fp32_one[0], j_split=4)]
+    if case == "split_fp64":
+        return inputs.plummer(1300, 17), dict(precision="fp64"), [
+            dict(kernel="force", precision="fp64", n_min=0, n_max=1 << 40, variant=fp64_one[-1], j_split=3)]
+    if case == "direct":  # no reduction: the separate energy pass and kick/drift kernels run
+        return inputs.plummer(1200, 18), dict(precision="fp32c"), [
+            dict(kernel="force", precision="fp32c", n_min=0, n_max=1 << 40, variant=fp32_one[0], j_split=1)]
+    b = _batch(9, 19, nmin=1, nmax=2500)
+    sym = case == "batched_sym"
+    v = [k for k, d in enumerate(bat) if ("sym=" in d) == sym][0]
+    return b, dict(precision="fp32c", offsets=b.offsets), [
+        dict(kernel="force_batched", precision="fp32c", n_min=0, n_max=1 << 40, variant=v, j_split=1)]
+
+
+@pytest.mark.parametrize("case", ["sym", "sym_ragged", "split", "split_fp64", "direct", "batched_sym",
+                                  "batched_onesided"])
+def test_fused_energy_trace_equals_separate_passes(nb, case):
+    """With the energy trace on, the rollout reduces each step's energy and momentum inside the
+    force pass's per-particle reduction (and still fuses the next step's first half): every
+    trace row must equal, bitwise, the energy entry applied to the state and potential that
+    single KDK steps produce, and the final state must equal theirs."""
+    import torch
+    s, kw, table = _trace_case(nb, case)
+    steps, dt = 6, 1e-3
+    try:
+        nb.set_tile_table(table)
+        p, v, m = dev(s.pos), dev(s.vel), dev(s.mass)
+        a, _ = nb.forces(p, m, **kw)
+        _, trace = nb.rollout(p, v, m, a, dt, steps, energy_trace=True, **kw)
+        p2, v2 = dev(s.pos), dev(s.vel)
+        rows = [host(nb.energy_momentum(p2, v2, m, **kw))]
+        a2, _ = nb.forces(p2, m, **kw)
+        pot = torch.empty(m.shape[0], dtype=torch.float64, device=m.device)
+        for _ in range(steps):
+            nb.step(p2, v2, m, a2, dt, out_pot=pot, **kw)
+            rows.append(host(nb.energy_momentum(p2, v2, m, pot=pot, **kw)))
+    finally:
+        nb.set_tile_table([])
+    assert np.array_equal(host(p), host(p2)) and np.array_equal(host(v), host(v2))
+    assert np.array_equal(host(trace), np.stack(rows)), np.max(np.abs(host(trace) - np.stack(rows)))
+
+
+def test_fused_energy_trace_lennard_jones(nb):
+    """Lennard-Jones rollout with walls and the energy trace on: its last row equals the energy
+    terms of the diagnostics entry applied to the final state's own force call, and the state
+    equals a rollout without the trace."""
+    g, box = inputs.lj_gas(3000, 21, spacing=1.2, temperature=2.0)
+    kw = dict(sigma=1.0, epsilon=1.0, box=(box.lo, box.hi), precision="fp32c")
+    outs = []
+    for et in (True, False):
+        p, v, m = dev(g.pos), dev(g.vel), dev(g.mass)
+        a, _ = nb.lj_forces(p, m, sigma=1.0, epsilon=1.0, precision="fp32c")
+        tr = nb.lj_rollout(p, v, m, a, 2e-3, 7, energy_trace=et, **kw)
+        outs.append((host(p), host(v), tr))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    p, v, m = dev(outs[0][0]), dev(outs[0][1]), dev(g.mass)
+    a, pot = nb.lj_forces(p, m, sigma=1.0, epsilon=1.0, precision="fp32c", want_pot=True)
+    d = host(nb.diagnostics(p, v, m, pot, a, precision="fp32c"))[0]
+    last = host(outs[0][2])[-1, 0]
+    np.testing.assert_allclose(last[:2], d[:2], rtol=1e-14)
+    np.testing.assert_allclose(last[2:5], d[2:5], rtol=0, atol=1e-14 * float(np.sum(g.mass)) * float(np.abs(g.vel).max()))
+
+
 # ------------------------------------------------------------------ batched
 
 def _batch(S, seed, nmin=64, nmax=1500):
