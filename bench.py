@@ -34,6 +34,11 @@ sys.path.insert(0, ROOT)
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector, FLOP/s
 FLOP_PER_INTERACTION = 20.0   # forward pair-interaction convention
 LJ_FLOP_PER_INTERACTION = 22.0  # Lennard-Jones pair: 3 sub, 3 FMA (r^2), rcp, 2 mul (u^3), FMA, 2 mul, 3 FMA
+# adjoint interaction (one ordered pair's share of the force VJP): 3 sub, 3 FMA (r^2), rsq
+# (2, as in the forward convention), 2 mul (r^-2, r^-3), 2 mul (3 r^-5), two dot products
+# d.l_j and d.l_k (5 each), 4 FMA (r^-3 l_j, m_j r^-3), w = m_k (d.l_j) - m_j (d.l_k) (3), mul,
+# 4 FMA (C, M)
+ADJ_FLOP_PER_INTERACTION = 45.0
 METRIC = "pair interactions/s (fwd & adjoint), % FP32 vector peak, at stated error"
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_02655_amd", "csrc", "nbody_kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_fp32c_plummer1m_traffic.json")
@@ -210,11 +215,45 @@ def main():
         out["cube1k"] = cube1k_leg(nb, torch, np, inputs, dev)
         out["plummer64k"] = plummer64k_leg(nb, torch, np, inputs, dev)
         out["adjoint"] = adjoint_leg(nb, torch, np, inputs, dev)
+        out["adjoint_1m"] = adjoint_1m_leg(nb, torch, np, pos0, mass, s, eps, prec)
         out["batched"] = batched_leg(nb, torch, np, inputs, dev)
         out["lj10k"] = lj_leg(nb, torch, np, inputs, dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(np, s, eps)
     print(json.dumps(out), flush=True)
+
+
+def adjoint_1m_leg(nb, torch, np, pos0, mass, s, eps, prec):
+    """The adjoint pair pass at the headline size: a one-step backward (two adjoint passes
+    and one recomputed force pass, with their staging and reductions) timed with HIP events,
+    less one force pass timed the same way, halved."""
+    log("adjoint 1M leg")
+    dt = 5e-4
+    pos, vel = pos0.clone(), torch.from_numpy(s.vel).to(pos0.device)
+    acc, _ = nb.forces(pos, mass, eps=eps, precision=prec)
+    ckpt, _ = nb.rollout(pos, vel, mass, acc, dt, 1, ckpt_every=1, eps=eps, precision=prec)
+    gx = torch.ones_like(pos)
+    gv = torch.zeros_like(pos)
+    nb.rollout_backward(mass, ckpt, gx, gv, dt, 1, 1, eps=eps, precision=prec)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    nb.forces(pos0, mass, eps=eps, precision=prec, out_acc=acc)
+    ev[1].record()
+    nb.rollout_backward(mass, ckpt, gx, gv, dt, 1, 1, eps=eps, precision=prec)
+    ev[2].record()
+    torch.cuda.synchronize()
+    f_ms, b_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    adj_ms = 0.5 * (b_ms - f_ms)
+    n2 = float(s.n) ** 2
+    vid, _ = nb.tile_lookup("adjoint", prec, s.n)
+    return {"workload": "plummer1m state, one-step backward (dt=%g) with a unit position cotangent, %s" % (dt, prec),
+            "kernel": nb.tile_variants("adjoint", prec)[vid],
+            "backward_1step_ms": b_ms, "force_pass_ms": f_ms, "adjoint_pass_ms": adj_ms,
+            "adjoint_interactions_per_s": n2 / (adj_ms * 1e-3),
+            "flop_per_adjoint_interaction": ADJ_FLOP_PER_INTERACTION,
+            "pct_fp32_peak": 100.0 * ADJ_FLOP_PER_INTERACTION * n2 / (adj_ms * 1e-3) / PEAK_FP32,
+            "adjoint_over_forward_time": adj_ms / f_ms}
 
 
 def force_errors(nb, torch, np, pos0, mass, s, eps, prec):
