@@ -210,6 +210,7 @@ def main():
                    "P_end": [float(x) for x in em1[2:]]},
     }
 
+    out["force_pass_reps"] = force_pass_reps(nb, torch, np, pos0, mass, eps, prec, n)
     if not args.no_extras:
         out["error"] = force_errors(nb, torch, np, pos0, mass, s, eps, prec)
         out["cube1k"] = cube1k_leg(nb, torch, np, inputs, dev)
@@ -221,6 +222,57 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(np, s, eps)
     print(json.dumps(out), flush=True)
+
+
+def sample_sclk():
+    """Current GPU engine clock in MHz from rocm-smi (None when it cannot be read)."""
+    import re
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "-g", "--json"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                           text=True, timeout=20)
+        cards = json.loads(r.stdout)
+    except Exception:
+        return None
+    for card in cards.values():
+        if not isinstance(card, dict):
+            continue
+        for key, val in card.items():
+            m = re.search(r"\((\d+(?:\.\d+)?)\s*mhz\)", str(val), re.I)
+            if "sclk" in key.lower() and m:
+                return float(m.group(1))
+    return None
+
+
+def force_pass_reps(nb, torch, np, pos0, mass, eps, prec, n, warm=2, reps=10):
+    """The headline force pass alone (staging, pair pass and per-particle reduction, no
+    potential): `warm` untimed launches, then `reps` launches timed one by one with HIP
+    events; median, min and max. The engine clock is sampled with rocm-smi while they run."""
+    log("force pass: %d warm-up + %d timed launches" % (warm, reps))
+    acc = torch.empty((3, n), dtype=torch.float64, device=pos0.device)
+    for _ in range(warm):
+        nb.forces(pos0, mass, eps=eps, precision=prec, out_acc=acc)
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nb.forces(pos0, mass, eps=eps, precision=prec, out_acc=acc)
+        e1.record()
+        evs.append((e0, e1))
+    sclk = [c for c in (sample_sclk() for _ in range(3)) if c]  # the launches are still running
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in evs])
+    med = float(np.median(ms))
+    flops = FLOP_PER_INTERACTION * float(n) * float(n) / (med * 1e-3)
+    out = {"median_ms": med, "min_ms": float(ms.min()), "max_ms": float(ms.max()), "reps": reps, "warmup": warm,
+           "interactions_per_s": float(n) * float(n) / (med * 1e-3), "pct_fp32_peak": 100.0 * flops / PEAK_FP32,
+           "sclk_mhz_samples": sclk}
+    if sclk:
+        # peak at the sampled clock: 256 CUs x 128 FMA lanes x 2 flop per clock
+        peak_at_clk = 256 * 256 * float(np.median(sclk)) * 1e6
+        out["pct_fp32_peak_at_sampled_sclk"] = 100.0 * flops / peak_at_clk
+    return out
 
 
 def adjoint_1m_leg(nb, torch, np, pos0, mass, s, eps, prec):
