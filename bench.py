@@ -677,9 +677,26 @@ def cpu_baseline(np, s, eps, target_s=12.0):
     t0 = time.perf_counter()
     oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
     t2 = time.perf_counter() - t0
+    # the same oracle on one thread, on a smaller sample (about target_s / 4 seconds)
+    oracle.set_threads(1)
+    k1 = int(min(s.n, max(8, k2 * (target_s / 4.0) / max(t2 * threads, 1e-3))))
+    idx1 = np.sort(g.choice(s.n, k1, replace=False))
+    t0 = time.perf_counter()
+    oracle.forces_sample(s.pos, s.mass, idx1, eps=eps)
+    t3 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": k2 * float(s.n) / t2, "unit": "pair interactions/s", "cores": threads, "kind": "oracle",
             "sample": "%d random particles of the Plummer N=%d system against all N (one FP64 force evaluation "
-                      "restricted to the sample), %.1f s" % (k2, s.n, t2)}
+                      "restricted to the sample), %.1f s" % (k2, s.n, t2),
+            "value_1_thread": k1 * float(s.n) / t3, "sample_1_thread": "%d particles, %.1f s" % (k1, t3),
+            "host_cpus_visible": os.cpu_count(), "cpu_model": model,
+            "build": "gcc -O2 -fopenmp (oracle/__init__.py), OpenMP over target particles"}
 
 
 if __name__ == "__main__":

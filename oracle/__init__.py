@@ -81,6 +81,8 @@ def _load():
     lib.oracle_lj_kdk.restype = None
     lib.oracle_diagnostics.argtypes = [I64, P, P, P, P, P, P]
     lib.oracle_diagnostics.restype = None
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -188,6 +190,11 @@ def loss_msd(pos, target):
 def num_threads() -> int:
     """OpenMP threads the oracle runs with."""
     return int(_load().oracle_num_threads())
+
+
+def set_threads(t: int) -> None:
+    """Run later oracle calls on t OpenMP threads (results do not depend on it)."""
+    _load().oracle_set_threads(int(t))
 
 
 # ---- batched systems: each system is an independent call (no cross-system pairs) ----

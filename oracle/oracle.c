@@ -256,6 +256,16 @@ EXPORT double oracle_loss_msd(int64_t n, const double *pos, const double *target
     return n > 0 ? acc / (double)n : 0.0;
 }
 
+/* Thread count of later parallel regions (t >= 1); the results do not depend on it. */
+EXPORT void oracle_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t >= 1) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 EXPORT int oracle_num_threads(void)
 {
     int t = 1;
