@@ -19,6 +19,7 @@ without the per-step energy reduction, in FP64 and FP32 (the "lj10k" leg).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
        python bench.py --lj-only     (only the Lennard-Jones leg, printed as one JSON line)
+       python bench.py --adjoint-1m-only  (only the adjoint pass at the headline size)
 """
 import argparse
 import hashlib
@@ -84,6 +85,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--lj-only", action="store_true")
+    ap.add_argument("--adjoint-1m-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole system on a single MI355X "
@@ -114,6 +116,9 @@ def main():
     pos0 = torch.from_numpy(s.pos).to(dev)
     vel0 = torch.from_numpy(s.vel).to(dev)
     mass = torch.from_numpy(s.mass).to(dev)
+    if args.adjoint_1m_only:
+        print(json.dumps({"adjoint_1m": adjoint_1m_leg(nb, torch, np, pos0, mass, s, eps, prec)}), flush=True)
+        return
     pos, vel = pos0.clone(), vel0.clone()
     acc = torch.empty((3, n), dtype=torch.float64, device=dev)
     pot = torch.empty(n, dtype=torch.float64, device=dev)
