@@ -584,6 +584,30 @@ def batched_leg(nb, torch, np, inputs, dev):
     res["max_abs_pos_diff_persistent_vs_looped"] = d
     res["speedup_forward"] = res["looped"]["forward_ms"] / res["persistent"]["forward_ms"]
     res["speedup_backward"] = res["looped"]["backward_ms"] / res["persistent"]["backward_ms"]
+    # forward without checkpoints: one persistent launch per pass against every step in one launch
+    wr = {}
+    for name, flags in (("per_pass", 0), ("whole_rollout", nb.FLAG_WHOLE_ROLLOUT)):
+        pos, vel = x0.clone(), v0.clone()
+        acc, _ = nb.forces(pos, m, eps=W["eps"], precision="fp32c", offsets=off)
+        nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], eps=W["eps"], precision="fp32c", offsets=off, flags=flags)
+        ts = []
+        for _ in range(3):
+            pos.copy_(x0)
+            vel.copy_(v0)
+            nb.forces(pos, m, eps=W["eps"], precision="fp32c", offsets=off, out_acc=acc)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], eps=W["eps"], precision="fp32c", offsets=off,
+                       flags=flags)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        wr[name] = {"ms": ms, "interactions_per_s": W["steps"] * sum_n2 / (ms * 1e-3), "final_pos": pos.clone()}
+    wr["bitwise_equal"] = bool(torch.equal(wr["per_pass"].pop("final_pos"), wr["whole_rollout"].pop("final_pos")))
+    wr["speedup"] = wr["per_pass"]["ms"] / wr["whole_rollout"]["ms"]
+    res["rollout_no_checkpoints"] = wr
     return res
 
 

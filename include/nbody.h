@@ -79,6 +79,14 @@ typedef enum { NBODY_FP64 = 0, NBODY_FP32 = 1, NBODY_FP32_COMP = 2, NBODY_FP32_D
 /* config.flags */
 #define NBODY_FLAG_LOOP_SYSTEMS 1u /* batched calls: one plain launch per system
                                       instead of one persistent launch (baseline) */
+#define NBODY_FLAG_WHOLE_ROLLOUT 2u /* nbody_rollout / nbody_lj_rollout of a batch on
+                                      symmetric tiles without an energy trace or
+                                      checkpoints: every step in one launch, systems
+                                      advancing independently (per-system waits on
+                                      device counters); the trajectory is bitwise that
+                                      of the per-step path. Such a call waits for the
+                                      launch to finish (it reads back a device error
+                                      word). Ignored where it does not apply. */
 
 typedef struct {
   int32_t abi_version;     /* must equal NBODY_ABI_VERSION */

@@ -165,21 +165,42 @@ void launch_sym_batched(dim3 g, hipStream_t st, const float4* jarr, const SymUni
 }
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 const void* sym_batched_ptr() { return (const void*)&force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW, PIPE>; }
+using RolloutFn = void (*)(dim3, hipStream_t, const float4* jarr, const SymUnit* units, int32_t n_solo,
+                           int32_t n_units, const int32_t* rtasks, int32_t n_rtasks, int64_t n, const int64_t* sys_off,
+                           const int32_t* sys_nb, const int64_t* sys_part, float eps2, float* part, LawScale ls,
+                           double* acc, double* vel, double hh, NextStep nx, int32_t steps, RolloutSync sy);
+template <int W, int I, int MODE, int ROT, int LAW, int PIPE>
+void launch_rollout(dim3 g, hipStream_t st, const float4* jarr, const SymUnit* units, int32_t n_solo, int32_t n_units,
+                    const int32_t* rtasks, int32_t n_rtasks, int64_t n, const int64_t* sys_off, const int32_t* sys_nb,
+                    const int64_t* sys_part, float eps2, float* part, LawScale ls, double* acc, double* vel, double hh,
+                    NextStep nx, int32_t steps, RolloutSync sy) {
+  hipLaunchKernelGGL((rollout_sym_batched_kernel<W, I, MODE, ROT, LAW, PIPE>), g, dim3(W * 64), 0, st, jarr, units,
+                     n_solo, n_units, rtasks, n_rtasks, n, sys_off, sys_nb, sys_part, eps2, part, ls, acc, vel, hh, nx, steps,
+                     sy);
+}
+template <int W, int I, int MODE, int ROT, int LAW, int PIPE>
+const void* rollout_ptr() { return (const void*)&rollout_sym_batched_kernel<W, I, MODE, ROT, LAW, PIPE>; }
 struct SymVariant {
   int w, i, rot;      // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
   int pipe;           // coordinate rotation issued after phase 1 (0) or a step ahead (1)
   SymFn fn[2][2][3];  // [law][pot][mode]
   SymBatchedFn bfn[2][2][3];
   const void* (*bptr[2][2][3])();
+  RolloutFn rfn[2][3];  // whole batched rollout [law][mode] (no potential)
+  const void* (*rptr[2][3])();
 };
 #define SV32_POT(F, W, I, R, P, POT, LAW) \
   { F<W, I, POT, 0, R, LAW, P>, F<W, I, POT, 1, R, LAW, P>, F<W, I, POT, 2, R, LAW, P> }
 #define SV32_ALL(F, W, I, R, P)                                                                           \
   {{SV32_POT(F, W, I, R, P, false, 0), SV32_POT(F, W, I, R, P, true, 0)},                                 \
    {SV32_POT(F, W, I, R, P, false, 1), SV32_POT(F, W, I, R, P, true, 1)}}
+#define SV32_RO(F, W, I, R, P, LAW) \
+  { F<W, I, 0, R, LAW, P>, F<W, I, 1, R, LAW, P>, F<W, I, 2, R, LAW, P> }
 #define SV32P(W, I, R, P)                                                                                  \
   SymVariant { W, I, R, P, SV32_ALL(launch_sym, W, I, R, P), SV32_ALL(launch_sym_batched, W, I, R, P),   \
-               SV32_ALL(sym_batched_ptr, W, I, R, P) }
+               SV32_ALL(sym_batched_ptr, W, I, R, P),                                                      \
+               {SV32_RO(launch_rollout, W, I, R, P, 0), SV32_RO(launch_rollout, W, I, R, P, 1)},          \
+               {SV32_RO(rollout_ptr, W, I, R, P, 0), SV32_RO(rollout_ptr, W, I, R, P, 1)} }
 #define SV32(W, I, R) SV32P(W, I, R, 0)
 const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4, 2, 0), SV32(2, 4, 0),
                              SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1), SV32(2, 4, 1),
@@ -418,7 +439,8 @@ int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys, bool law_checks 
       return fail(NBODY_ERR_INVALID_ARG, "eps must be >= 1e-10 for the FP32 modes (got %g)", cfg->eps);
   }
   if (cfg->reserved != 0) return fail(NBODY_ERR_INVALID_ARG, "reserved must be 0");
-  if (cfg->flags & ~NBODY_FLAG_LOOP_SYSTEMS) return fail(NBODY_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
+  if (cfg->flags & ~(NBODY_FLAG_LOOP_SYSTEMS | NBODY_FLAG_WHOLE_ROLLOUT))
+    return fail(NBODY_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
   if (n < 0) return fail(NBODY_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)n);
   if (n > ((int64_t)1 << 31)) return fail(NBODY_ERR_UNSUPPORTED, "n = %lld exceeds 2^31", (long long)n);
   if (cfg->n_systems < 1) return fail(NBODY_ERR_INVALID_ARG, "n_systems must be >= 1");
@@ -450,7 +472,7 @@ struct Plan {
   // batched metadata
   size_t off_meta = 0, sz_meta = 0;
   size_t off_sysoff = 0, off_nsplit = 0, off_partoff = 0, off_partoff_adj = 0, off_units = 0, off_units_adj = 0,
-         off_counter = 0;
+         off_counter = 0, off_sync = 0, off_rtasks = 0, off_units_ro = 0;
   int64_t n_units_force = 0, n_units_adj = 0;
   // buffers
   size_t off_jbuf = 0, sz_jbuf = 0;
@@ -469,6 +491,9 @@ struct UnitSet {
   std::vector<int32_t> nsplit;     // per system: j-chunks (one-sided) or blocks nb (symmetric)
   std::vector<SymUnit> sym_units;  // symmetric units (tile (A, B) of one system)
   std::vector<int64_t> part_off;   // symmetric: float offset of each system's partial planes
+  std::vector<SymUnit> ro_units;   // symmetric, whole rollout: one-tile systems, then the other units
+  int64_t n_solo = 0;              //   (the first n_solo of ro_units run all their steps in one task)
+  std::vector<int32_t> rtasks;     //   reduction tasks of the systems of several tiles: (system, chunk)
   int64_t part_floats = 0;         // symmetric: floats of all systems' partial planes
   bool sym = false;
   int64_t count() const { return sym ? (int64_t)sym_units.size() : (int64_t)units.size(); }
@@ -526,8 +551,13 @@ void build_sym_units(const Systems& sys, const Tile& t, UnitSet& us, int comps) 
         u.nb = (int32_t)nb;
         u.A = (int32_t)A;
         u.B = (int32_t)B;
+        u.sys = (int32_t)s;
         us.sym_units.push_back(u);
       }
+    for (int64_t ch = 0; nb > 1 && ch * kRolloutChunk < ns; ++ch) {
+      us.rtasks.push_back((int32_t)s);
+      us.rtasks.push_back((int32_t)ch);
+    }
     off += nb * comps * ns;
   }
   us.part_off[sys.S] = off;
@@ -536,6 +566,13 @@ void build_sym_units(const Systems& sys, const Tile& t, UnitSet& us, int comps) 
   std::stable_sort(us.sym_units.begin(), us.sym_units.end(), [&](const SymUnit& a, const SymUnit& b) {
     return rows(a, a.A) * rows(a, a.B) > rows(b, b.A) * rows(b, b.B);
   });
+  // whole-rollout order: the one-tile systems (largest first), then the other units as above
+  us.ro_units.clear();
+  for (const SymUnit& u : us.sym_units)
+    if (u.nb == 1) us.ro_units.push_back(u);
+  us.n_solo = (int64_t)us.ro_units.size();
+  for (const SymUnit& u : us.sym_units)
+    if (u.nb > 1) us.ro_units.push_back(u);
 }
 
 int64_t max_nsplit(const UnitSet& us) {
@@ -625,6 +662,11 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     p.off_units = take(units_bytes);
     p.off_units_adj = take(uas.unit_bytes());
     p.off_counter = take(2 * sizeof(int32_t));
+    p.off_sync = take(16 + 2 * sys.S * sizeof(int32_t));  // whole-rollout queue, error word, per-system counts
+    int64_t rchunks = 0;  // whole-rollout reduction tasks (the same for either law and tile)
+    for (int64_t s = 0; s < sys.S; ++s) rchunks += cdiv(sys.off[s + 1] - sys.off[s], kRolloutChunk);
+    p.off_rtasks = take(2 * rchunks * sizeof(int32_t));
+    p.off_units_ro = take(units_bytes);  // the force units again, in whole-rollout order
     p.sz_meta = off - p.off_meta;
   } else if (loop) {
     for (int64_t s = 0; s < sys.S; ++s) {
@@ -769,8 +811,10 @@ int upload_meta(Ctx& c) {
   const size_t b_units = c.uf.unit_bytes();
   const size_t b_uadj = c.ua.unit_bytes();
   const size_t b_poffa = c.ua.sym ? (S + 1) * sizeof(int64_t) : 0;
+  const size_t b_rt = c.uf.sym ? c.uf.rtasks.size() * sizeof(int32_t) : 0;
+  const size_t b_ro = c.uf.sym ? c.uf.ro_units.size() * sizeof(SymUnit) : 0;
   const size_t total = align_up(b_off) + align_up(b_ns) + align_up(b_poff) + align_up(b_units) + align_up(b_uadj) +
-                       align_up(b_poffa);
+                       align_up(b_poffa) + align_up(b_rt) + align_up(b_ro);
   std::lock_guard<std::mutex> lk(g_stage_mu);
   if (g_stage_done) HIP_TRY(hipEventSynchronize(g_stage_done));  // previous upload has read the staging
   if (total > g_stage_bytes) {
@@ -788,6 +832,8 @@ int upload_meta(Ctx& c) {
   char* h_units = h + align_up(b_off) + align_up(b_ns) + align_up(b_poff);
   char* h_uadj = h_units + align_up(b_units);
   char* h_poffa = h_uadj + align_up(b_uadj);
+  char* h_rt = h_poffa + align_up(b_poffa);
+  char* h_ro = h_rt + align_up(b_rt);
   std::memcpy(h_off, c.sys.off, b_off);
   for (int64_t s = 0; s < S; ++s) {
     h_ns[s] = c.uf.nsplit.empty() ? 0 : c.uf.nsplit[s];
@@ -799,6 +845,8 @@ int upload_meta(Ctx& c) {
   if (b_uadj) std::memcpy(h_uadj, c.ua.sym ? (const void*)c.ua.sym_units.data() : (const void*)c.ua.units.data(),
                           b_uadj);
   if (b_poffa) std::memcpy(h_poffa, c.ua.part_off.data(), b_poffa);
+  if (b_rt) std::memcpy(h_rt, c.uf.rtasks.data(), b_rt);
+  if (b_ro) std::memcpy(h_ro, c.uf.ro_units.data(), b_ro);
   HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_sysoff, h_off, b_off, hipMemcpyHostToDevice, c.st));
   HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_nsplit, h_ns, b_ns, hipMemcpyHostToDevice, c.st));
   if (b_poff) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_partoff, h_poff, b_poff, hipMemcpyHostToDevice, c.st));
@@ -806,6 +854,8 @@ int upload_meta(Ctx& c) {
   if (b_uadj) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_units_adj, h_uadj, b_uadj, hipMemcpyHostToDevice, c.st));
   if (b_poffa)
     HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_partoff_adj, h_poffa, b_poffa, hipMemcpyHostToDevice, c.st));
+  if (b_rt) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_rtasks, h_rt, b_rt, hipMemcpyHostToDevice, c.st));
+  if (b_ro) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_units_ro, h_ro, b_ro, hipMemcpyHostToDevice, c.st));
   HIP_TRY(hipEventRecord(g_stage_done, c.st));
   return NBODY_OK;
 }
@@ -1270,6 +1320,45 @@ __attribute__((visibility("default"))) int nbody_step(const nbody_config* cfg, i
 
 namespace {
 
+// Every step of a batched rollout on symmetric tiles in one launch (see
+// rollout_sym_batched_kernel): the first half of step 0 here, then the kernel, then a
+// read-back of its error word.
+int whole_rollout(Ctx& c, double dt, int64_t steps, double* pos, double* vel, const double* mass, double* acc,
+                  const NextStep& nx) {
+  if (steps > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many steps for one launch");
+  Tile t = lookup_tile(force_kernel_id(c.law, true), c.cfg->precision, c.sys.max_n);
+  if (t.sym < 0 || !c.uf.sym) return fail(NBODY_ERR_DEVICE, "internal: whole rollout without symmetric units");
+  TRY(check_part(c, (size_t)c.uf.part_floats * sizeof(float), "rollout_sym_batched_kernel"));
+  const SymVariant& sv = kSym32[t.sym];
+  const int law = c.law, mode = force_mode(c.cfg->precision);
+  TRY(kick_drift(c, dt, pos, vel, acc, mass));
+  int32_t* words = (int32_t*)(c.ws + c.plan.off_sync);
+  const int64_t nwords = 4 + 2 * c.sys.S;
+  hipLaunchKernelGGL(fill_i32, grid1d(nwords), dim3(256), 0, c.st, words, nwords, 0);
+  LAUNCH_CHECK("fill_i32");
+  RolloutSync sy;
+  sy.queue = (unsigned long long*)words;
+  sy.err = words + 2;
+  sy.tiles_done = words + 4;
+  sy.red_done = words + 4 + c.sys.S;
+  unsigned grid;
+  const int64_t n_rtasks = (int64_t)c.uf.rtasks.size() / 2;
+  const int64_t n_solo = c.uf.n_solo, n_multi = (int64_t)c.uf.ro_units.size() - n_solo;
+  TRY(persistent_grid(sv.rptr[law][mode](), sv.w * 64, n_solo + (n_multi + n_rtasks) * steps, grid));
+  sv.rfn[law][mode](dim3(grid), c.st, (const float4*)(c.ws + c.plan.off_jbuf),
+                    (const SymUnit*)(c.ws + c.plan.off_units_ro), (int32_t)n_solo, (int32_t)n_multi,
+                    (const int32_t*)(c.ws + c.plan.off_rtasks), (int32_t)n_rtasks, c.n,
+                    (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit),
+                    (const int64_t*)(c.ws + c.plan.off_partoff), (float)c.eps2, (float*)(c.ws + c.plan.off_part), c.ls,
+                    acc, vel, 0.5 * dt, nx, (int32_t)steps, sy);
+  LAUNCH_CHECK("rollout_sym_batched_kernel");
+  int32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, sy.err, sizeof err, hipMemcpyDeviceToHost, c.st));
+  HIP_TRY(hipStreamSynchronize(c.st));
+  if (err) return fail(NBODY_ERR_DEVICE, "whole rollout: a per-system wait gave up (device error word set)");
+  return NBODY_OK;
+}
+
 // The KDK loop shared by both pair laws (c prepared with NEED_FORCE | NEED_ROLLOUT).
 int rollout_impl(Ctx& c, int64_t n, double dt, int64_t steps, int64_t ckpt_every, double* pos, double* vel,
                  const double* mass, double* acc, double* ckpt, double* energy_trace) {
@@ -1293,6 +1382,8 @@ int rollout_impl(Ctx& c, int64_t n, double dt, int64_t steps, int64_t ckpt_every
     TRY(energy_pass(c, vel, mass, pot, energy_trace));
   }
   const NextStep nx = next_step(c, dt, pos, mass);
+  if ((c.cfg->flags & NBODY_FLAG_WHOLE_ROLLOUT) && !energy_trace && !ckpt && steps > 0)
+    if (c.bat && !c.loop && c.uf.sym) return whole_rollout(c, dt, steps, pos, vel, mass, acc, nx);
   bool staged = false;  // the previous pass already ran this step's kick, drift and staging
   for (int64_t s = 0; s < steps; ++s) {
     if (!staged) TRY(kick_drift(c, dt, pos, vel, acc, mass));

@@ -920,6 +920,8 @@ struct SymUnit {
   int64_t part_off;
   int32_t n, nb;
   int32_t A, B;
+  int32_t sys;  // index of the system
+  int32_t pad;
 };
 
 // Persistent grid over the symmetric tiles of many systems (units sorted by decreasing
@@ -933,6 +935,14 @@ __global__ __launch_bounds__(W * 64) void force_sym_batched_kernel(const float4*
   constexpr int NV = MODE == MODE_DS ? 2 : 1;
   __shared__ float red[2][W][POT ? 4 : 3][64];
   __shared__ int32_t next;
+  if (!counter) {  // one unit per workgroup, taken in launch order
+    if ((int32_t)blockIdx.x < n_units) {
+      const SymUnit su = units[blockIdx.x];
+      sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr + NV * su.base, su.n, su.A, su.B, eps2_arg, part + su.part_off,
+                                                red);
+    }
+    return;
+  }
   for (;;) {
     __syncthreads();  // everyone has finished with the previous unit (and its LDS sums)
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -977,6 +987,136 @@ __global__ __launch_bounds__(kReduceBS) void reduce_sym_batched(int64_t n, int64
     if (sys_off[mid] <= i) lo = mid; else hi = mid;
   }
   body(i, lo, nullptr);
+}
+
+// ----------------------------------------------------------------- whole batched rollout in one launch
+
+// Synchronisation words of the whole-rollout kernel (device memory, zero at launch).
+//   queue: next task; err: set when a wait gives up; tiles_done[s]: tiles of system s
+//   finished over all steps so far; red_done[s]: per-particle reductions of system s
+//   finished (the steps whose end state is written and, but for the last, staged).
+struct RolloutSync {
+  unsigned long long* queue;
+  int32_t* err;
+  int32_t* tiles_done;
+  int32_t* red_done;
+};
+
+// Bounded wait of one thread for *p >= v: agent-scope loads, each followed by a short sleep;
+// gives up (and sets err) after kSpinLimit probes, or when another workgroup has given up.
+constexpr int64_t kSpinLimit = 1ll << 24;
+__device__ __forceinline__ bool wait_at_least(const int32_t* p, int32_t v, int32_t* err) {
+  for (int64_t k = 0; k < kSpinLimit; ++k) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return false;
+}
+
+constexpr int32_t kRolloutChunk = 8192;  // particles of one reduction task
+
+// End of a task: every thread fences its own writes (device scope), the workgroup meets,
+// and one thread counts the task done. (Weaker forms, one fence per workgroup or
+// release/acquire-only fences, gave wrong results across the XCDs.)
+__device__ __forceinline__ void release_to(int32_t* counter) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(counter, 1);
+}
+
+// Every step of a batched symmetric rollout in one launch (no potential). The task queue
+// holds first the n_solo systems of one tile (units[0, n_solo)), each run for all its steps
+// by the workgroup that takes it: tile, per-particle reduction and staging, separated by
+// workgroup barriers only. Then, step by step, the tiles of the systems of several tiles
+// (units[n_solo, n_solo + n_units), the host's order) and their per-particle reductions in
+// chunks of kRolloutChunk particles (rtasks: pairs of system and chunk index). A tile of
+// such a system s at step t > 0 first waits for every reduction chunk (s, t - 1), which
+// staged its positions; a reduction chunk (s, t) waits for all tiles (s, t). Each wait is
+// for a task earlier in the queue, already taken by a running workgroup, so every wait
+// ends; each is bounded besides. A reduction does for its particles what
+// reduce_sym_batched does (slots summed in the same order, acceleration, closing kick, and
+// for t + 1 < steps the next step's kick, drift, walls and staging), so the trajectory is
+// bitwise that of one launch per pass.
+template <int W, int I, int MODE, int ROT, int LAW, int PIPE>
+__global__ __launch_bounds__(W * 64) void rollout_sym_batched_kernel(
+    const float4* __restrict__ jarr, const SymUnit* __restrict__ units, int32_t n_solo, int32_t n_units,
+    const int32_t* __restrict__ rtasks, int32_t n_rtasks, int64_t n, const int64_t* __restrict__ sys_off,
+    const int32_t* __restrict__ sys_nb, const int64_t* __restrict__ sys_part, float eps2_arg,
+    float* __restrict__ part, LawScale ls, double* __restrict__ acc, double* __restrict__ vel, double hh, NextStep nx,
+    int32_t steps, RolloutSync sy) {
+  constexpr int NV = MODE == MODE_DS ? 2 : 1;
+  __shared__ float red[2][W][3][64];
+  __shared__ int64_t task_sh;
+  __shared__ int32_t ok_sh;
+  const int64_t per_step = (int64_t)n_units + n_rtasks;
+  const int64_t total = n_solo + per_step * steps;
+  for (;;) {
+    __syncthreads();  // everyone has read the previous task (and finished with the LDS sums)
+    if (threadIdx.x == 0) {
+      const int64_t q = (int64_t)atomicAdd(sy.queue, 1ull);
+      const bool stop = q >= total || __hip_atomic_load(sy.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      task_sh = stop ? -1 : q;
+    }
+    __syncthreads();
+    const int64_t q0 = task_sh;
+    if (q0 < 0) break;
+    if (q0 < n_solo) {  // a system of one tile, all its steps
+      const SymUnit su = units[q0];
+      const float4* js = jarr + NV * su.base;
+      float* ps = part + su.part_off;
+      for (int32_t t = 0; t < steps; ++t) {
+        sym_tile<W, I, false, MODE, ROT, LAW, PIPE>(js, su.n, 0, 0, eps2_arg, ps, red);
+        __syncthreads();  // the tile's partial sums, from every wave
+        NextStep nxt = nx;
+        if (t + 1 >= steps) nxt.kind = 0;  // the last step stages nothing
+        for (int64_t li = threadIdx.x; li < su.n; li += W * 64) {
+          double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a[c] += (double)ps[(int64_t)c * su.n + li];
+          finish_particle(su.base + li, n, a, ls, acc, nullptr, vel, hh, nxt, nullptr, nullptr);
+        }
+        __syncthreads();  // positions staged for the next step's tile
+      }
+      continue;
+    }
+    const int64_t q = q0 - n_solo;
+    const int32_t t = (int32_t)(q / per_step);
+    const int64_t r = q - (int64_t)t * per_step;
+    if (r < n_units) {
+      const SymUnit su = units[n_solo + r];
+      const int32_t chunks = (su.n + kRolloutChunk - 1) / kRolloutChunk;  // reduction tasks of the system
+      if (threadIdx.x == 0) ok_sh = t == 0 || wait_at_least(sy.red_done + su.sys, t * chunks, sy.err);
+      __syncthreads();
+      if (!ok_sh) break;
+      __threadfence();  // every thread: ordered after the positions staged by (s, t - 1)
+      sym_tile<W, I, false, MODE, ROT, LAW, PIPE>(jarr + NV * su.base, su.n, su.A, su.B, eps2_arg,
+                                                 part + su.part_off, red);
+      release_to(sy.tiles_done + su.sys);
+    } else {
+      const int64_t s = rtasks[2 * (r - n_units)];
+      const int64_t l0 = (int64_t)rtasks[2 * (r - n_units) + 1] * kRolloutChunk;
+      const int64_t b = sys_off[s], ns = sys_off[s + 1] - b;
+      const int64_t l1 = l0 + kRolloutChunk < ns ? l0 + kRolloutChunk : ns;
+      const int32_t nb = sys_nb[s];
+      if (threadIdx.x == 0) ok_sh = wait_at_least(sy.tiles_done + s, (t + 1) * (nb * (nb + 1) / 2), sy.err);
+      __syncthreads();
+      if (!ok_sh) break;
+      __threadfence();  // every thread: ordered after the tiles' partial sums
+      const float* ps = part + sys_part[s];
+      NextStep nxt = nx;
+      if (t + 1 >= steps) nxt.kind = 0;  // the last step stages nothing
+      for (int64_t li = l0 + threadIdx.x; li < l1; li += W * 64) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int32_t k = 0; k < nb; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
+        finish_particle(b + li, n, a, ls, acc, nullptr, vel, hh, nxt, nullptr, nullptr);
+      }
+      release_to(sy.red_done + s);
+    }
+  }
 }
 
 // ----------------------------------------------------------------- batched persistent force pass
@@ -1549,6 +1689,13 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_batched_kernel(const float
                                                                      float eps2, float* __restrict__ part) {
   __shared__ float red[2][W][4][64];
   __shared__ int32_t next;
+  if (!counter) {  // one unit per workgroup, taken in launch order
+    if ((int32_t)blockIdx.x < n_units) {
+      const SymUnit su = units[blockIdx.x];
+      adj_sym_tile<W, I, COMP, ROT>(jadj + 2 * su.base, su.n, su.A, su.B, eps2, part + su.part_off, red);
+    }
+    return;
+  }
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);

@@ -116,6 +116,8 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails val
     (dict(offsets=[1, 5, 10]), 1, "offsets[0]"),
     (dict(offsets=[0, 5, 9]), 1, "must equal n"),
     (dict(flags=8), 1, "flags"),
+    (dict(flags=4), 1, "flags"),
+    (dict(flags=3 | 16), 1, "flags"),
     (dict(reserved=1), 1, "reserved"),
     (dict(), 4, "workspace is NULL"),
     (dict(ws=0x1000, ws_bytes=10), 4, "too small"),
@@ -210,3 +212,28 @@ def test_lj_ignores_gravity_constants(nb):
     assert rc == 0 and b > 0
     rc, b2 = _ws_size(nb, _cfg(nb), 1000)
     assert b == b2
+
+
+def test_known_flags_accepted(nb):
+    """The per-system loop and the whole-rollout flags pass validation (the call then stops
+    at the missing workspace, the first check after the configuration)."""
+    for flags in (nb.FLAG_LOOP_SYSTEMS, nb.FLAG_WHOLE_ROLLOUT, nb.FLAG_LOOP_SYSTEMS | nb.FLAG_WHOLE_ROLLOUT):
+        c = _cfg(nb, flags=flags)
+        assert nb.lib().nbody_forces(ctypes.byref(c), 10, FAKE, FAKE, FAKE, None) == 4
+        assert "workspace is NULL" in nb.lib().nbody_last_error().decode()
+
+
+def test_workspace_size_covers_whole_rollout_tables(nb):
+    """A batch's workspace, which holds the whole-rollout tables (unit copy, reduction tasks,
+    per-system counters), does not depend on the flags."""
+    import numpy as np
+    sizes = [0, 1, 300, 5000, 9000, 64]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    b = []
+    for flags in (0, nb.FLAG_WHOLE_ROLLOUT):
+        c = _cfg(nb, n_systems=len(sizes), offsets=list(off), flags=flags)
+        out = ctypes.c_size_t()
+        assert nb.lib().nbody_workspace_size(ctypes.byref(c), int(off[-1]), 10, 0, ctypes.byref(out)) == 0
+        b.append(out.value)
+    assert b[0] == b[1] and b[0] > 0
