@@ -584,7 +584,24 @@ def batched_leg(nb, torch, np, inputs, dev):
     res["max_abs_pos_diff_persistent_vs_looped"] = d
     res["speedup_forward"] = res["looped"]["forward_ms"] / res["persistent"]["forward_ms"]
     res["speedup_backward"] = res["looped"]["backward_ms"] / res["persistent"]["backward_ms"]
-    # forward without checkpoints: one persistent launch per pass against every step in one launch
+    # forward without checkpoints: one persistent launch per pass against every step in one launch,
+    # on this mix and on a mix of tiny systems (4096 systems of 16-256 particles)
+    res["rollout_no_checkpoints"] = whole_rollout_compare(nb, torch, np, b, W, sum_n2)
+    tiny = inputs.batched_mix(4096, 7, nmin=16, nmax=256)
+    tiny_n2 = float(np.sum(np.diff(tiny.offsets).astype(np.float64) ** 2))
+    res["rollout_no_checkpoints_tiny"] = whole_rollout_compare(nb, torch, np, tiny, W, tiny_n2)
+    res["rollout_no_checkpoints_tiny"]["workload"] = ("4096 systems, N_s log-uniform [16, 256] (sum N^2 = %.3e), "
+                                                      "50 KDK steps, FP32 compensated" % tiny_n2)
+    return res
+
+
+def whole_rollout_compare(nb, torch, np, b, W, sum_n2):
+    """50-step forward of batch b without checkpoints: one launch per pass against every step
+    in one launch (NBODY_FLAG_WHOLE_ROLLOUT); median of 3, and the final states compared."""
+    off = b.offsets
+    x0 = torch.from_numpy(b.pos).cuda()
+    v0 = torch.from_numpy(b.vel).cuda()
+    m = torch.from_numpy(b.mass).cuda()
     wr = {}
     for name, flags in (("per_pass", 0), ("whole_rollout", nb.FLAG_WHOLE_ROLLOUT)):
         pos, vel = x0.clone(), v0.clone()
@@ -607,8 +624,7 @@ def batched_leg(nb, torch, np, inputs, dev):
         wr[name] = {"ms": ms, "interactions_per_s": W["steps"] * sum_n2 / (ms * 1e-3), "final_pos": pos.clone()}
     wr["bitwise_equal"] = bool(torch.equal(wr["per_pass"].pop("final_pos"), wr["whole_rollout"].pop("final_pos")))
     wr["speedup"] = wr["per_pass"]["ms"] / wr["whole_rollout"]["ms"]
-    res["rollout_no_checkpoints"] = wr
-    return res
+    return wr
 
 
 def lj_leg(nb, torch, np, inputs, dev):

@@ -60,11 +60,11 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 using ForceFn = void (*)(dim3, hipStream_t, const void* jarr, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
                          int64_t jchunk, double eps2, const ForceOut&);
 using ForceBatchedFn = void (*)(dim3, hipStream_t, const void* jarr, const WorkUnit* units, int32_t n_units,
-                                int32_t* counter, double eps2, const ForceOut&);
+                                double eps2, const ForceOut&);
 using AdjFn = void (*)(dim3, hipStream_t, const void* jadj, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
                        int64_t jchunk, double eps2, const AdjOut&);
 using AdjBatchedFn = void (*)(dim3, hipStream_t, const void* jadj, const WorkUnit* units, int32_t n_units,
-                              int32_t* counter, double eps2, const AdjOut&);
+                              double eps2, const AdjOut&);
 
 template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
 void launch_force(dim3 g, hipStream_t st, const void* jarr, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
@@ -74,9 +74,9 @@ void launch_force(dim3 g, hipStream_t st, const void* jarr, int64_t i0, int64_t 
 }
 template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
 void launch_force_batched(dim3 g, hipStream_t st, const void* jarr, const WorkUnit* units, int32_t n_units,
-                          int32_t* counter, double eps2, const ForceOut& o) {
+                          double eps2, const ForceOut& o) {
   hipLaunchKernelGGL((force_batched_kernel<T, BS, I, TJ, POT, MODE, LAW>), g, dim3(BS), 0, st,
-                     (const typename Vec4<T>::type*)jarr, units, n_units, counter, (T)eps2, o);
+                     (const typename Vec4<T>::type*)jarr, units, n_units, (T)eps2, o);
 }
 template <typename T, int BS, int I, int TJ, bool COMP>
 void launch_adj(dim3 g, hipStream_t st, const void* jadj, int64_t i0, int64_t i1, int64_t j0, int64_t j1,
@@ -86,28 +86,20 @@ void launch_adj(dim3 g, hipStream_t st, const void* jadj, int64_t i0, int64_t i1
 }
 template <typename T, int BS, int I, int TJ, bool COMP>
 void launch_adj_batched(dim3 g, hipStream_t st, const void* jadj, const WorkUnit* units, int32_t n_units,
-                        int32_t* counter, double eps2, const AdjOut& o) {
+                        double eps2, const AdjOut& o) {
   hipLaunchKernelGGL((adjoint_batched_kernel<T, BS, I, TJ, COMP>), g, dim3(BS), 0, st,
-                     (const typename Vec4<T>::type*)jadj, units, n_units, counter, (T)eps2, o);
+                     (const typename Vec4<T>::type*)jadj, units, n_units, (T)eps2, o);
 }
-
-// Kernel pointers for occupancy queries of the persistent kernels.
-template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
-const void* force_batched_ptr() { return (const void*)&force_batched_kernel<T, BS, I, TJ, POT, MODE, LAW>; }
-template <typename T, int BS, int I, int TJ, bool COMP>
-const void* adj_batched_ptr() { return (const void*)&adjoint_batched_kernel<T, BS, I, TJ, COMP>; }
 
 struct ForceVariant {
   int bs, i, tj;
   ForceFn fn[2][2][3];            // [law][pot][mode]: plain, compensated, double-float separations
   ForceBatchedFn bfn[2][2][3];
-  const void* (*bptr[2][2][3])();
 };
 struct AdjVariant {
   int bs, i, tj;
   AdjFn fn[2];                    // [comp]
   AdjBatchedFn bfn[2];
-  const void* (*bptr[2])();
 };
 
 #define FV32_MODES(F, BS, I, TJ, POT, LAW) \
@@ -117,28 +109,24 @@ struct AdjVariant {
 #define FV32(BS, I, TJ)                                                                                    \
   ForceVariant {                                                                                           \
     BS, I, TJ, {FV32_LAW(launch_force, BS, I, TJ, 0), FV32_LAW(launch_force, BS, I, TJ, 1)},              \
-        {FV32_LAW(launch_force_batched, BS, I, TJ, 0), FV32_LAW(launch_force_batched, BS, I, TJ, 1)},     \
-        {FV32_LAW(force_batched_ptr, BS, I, TJ, 0), FV32_LAW(force_batched_ptr, BS, I, TJ, 1)}            \
+        {FV32_LAW(launch_force_batched, BS, I, TJ, 0), FV32_LAW(launch_force_batched, BS, I, TJ, 1)}      \
   }
 #define FV64_LAW(F, BS, I, TJ, LAW) \
   { {F<double, BS, I, TJ, false, 0, LAW>, nullptr, nullptr}, {F<double, BS, I, TJ, true, 0, LAW>, nullptr, nullptr} }
 #define FV64(BS, I, TJ)                                                                                    \
   ForceVariant {                                                                                           \
     BS, I, TJ, {FV64_LAW(launch_force, BS, I, TJ, 0), FV64_LAW(launch_force, BS, I, TJ, 1)},              \
-        {FV64_LAW(launch_force_batched, BS, I, TJ, 0), FV64_LAW(launch_force_batched, BS, I, TJ, 1)},     \
-        {FV64_LAW(force_batched_ptr, BS, I, TJ, 0), FV64_LAW(force_batched_ptr, BS, I, TJ, 1)}            \
+        {FV64_LAW(launch_force_batched, BS, I, TJ, 0), FV64_LAW(launch_force_batched, BS, I, TJ, 1)}      \
   }
 #define AV32(BS, I, TJ)                                                                                    \
   AdjVariant {                                                                                             \
     BS, I, TJ, {launch_adj<float, BS, I, TJ, false>, launch_adj<float, BS, I, TJ, true>},                 \
-        {launch_adj_batched<float, BS, I, TJ, false>, launch_adj_batched<float, BS, I, TJ, true>},       \
-        {adj_batched_ptr<float, BS, I, TJ, false>, adj_batched_ptr<float, BS, I, TJ, true>}              \
+        {launch_adj_batched<float, BS, I, TJ, false>, launch_adj_batched<float, BS, I, TJ, true>}        \
   }
 #define AV64(BS, I, TJ)                                                                                    \
   AdjVariant {                                                                                             \
     BS, I, TJ, {launch_adj<double, BS, I, TJ, false>, nullptr},                                            \
-        {launch_adj_batched<double, BS, I, TJ, false>, nullptr},                                           \
-        {adj_batched_ptr<double, BS, I, TJ, false>, nullptr}                                               \
+        {launch_adj_batched<double, BS, I, TJ, false>, nullptr}                                            \
   }
 
 const ForceVariant kForce32[] = {FV32(256, 1, 256), FV32(512, 1, 512), FV32(256, 2, 256), FV32(128, 1, 256),
@@ -156,15 +144,13 @@ void launch_sym(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t n
                      part);
 }
 using SymBatchedFn = void (*)(dim3, hipStream_t, const float4* jarr, const SymUnit* units, int32_t n_units,
-                              int32_t* counter, float eps2, float* part);
+                              float eps2, float* part);
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
-void launch_sym_batched(dim3 g, hipStream_t st, const float4* jarr, const SymUnit* units, int32_t n_units,
-                        int32_t* counter, float eps2, float* part) {
+void launch_sym_batched(dim3 g, hipStream_t st, const float4* jarr, const SymUnit* units, int32_t n_units, float eps2,
+                        float* part) {
   hipLaunchKernelGGL((force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW, PIPE>), g, dim3(W * 64), 0, st, jarr,
-                     units, n_units, counter, eps2, part);
+                     units, n_units, eps2, part);
 }
-template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
-const void* sym_batched_ptr() { return (const void*)&force_sym_batched_kernel<W, I, POT, MODE, ROT, LAW, PIPE>; }
 using RolloutFn = void (*)(dim3, hipStream_t, const float4* jarr, const SymUnit* units, int32_t n_solo,
                            int32_t n_units, const int32_t* rtasks, int32_t n_rtasks, int64_t n, const int64_t* sys_off,
                            const int32_t* sys_nb, const int64_t* sys_part, float eps2, float* part, LawScale ls,
@@ -185,7 +171,6 @@ struct SymVariant {
   int pipe;           // coordinate rotation issued after phase 1 (0) or a step ahead (1)
   SymFn fn[2][2][3];  // [law][pot][mode]
   SymBatchedFn bfn[2][2][3];
-  const void* (*bptr[2][2][3])();
   RolloutFn rfn[2][3];  // whole batched rollout [law][mode] (no potential)
   const void* (*rptr[2][3])();
 };
@@ -198,14 +183,13 @@ struct SymVariant {
   { F<W, I, 0, R, LAW, P>, F<W, I, 1, R, LAW, P>, F<W, I, 2, R, LAW, P> }
 #define SV32P(W, I, R, P)                                                                                  \
   SymVariant { W, I, R, P, SV32_ALL(launch_sym, W, I, R, P), SV32_ALL(launch_sym_batched, W, I, R, P),   \
-               SV32_ALL(sym_batched_ptr, W, I, R, P),                                                      \
                {SV32_RO(launch_rollout, W, I, R, P, 0), SV32_RO(launch_rollout, W, I, R, P, 1)},          \
                {SV32_RO(rollout_ptr, W, I, R, P, 0), SV32_RO(rollout_ptr, W, I, R, P, 1)} }
 #define SV32(W, I, R) SV32P(W, I, R, 0)
 const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4, 2, 0), SV32(2, 4, 0),
                              SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1), SV32(2, 4, 1),
                              SV32(4, 2, 1), SV32(2, 2, 1), SV32P(8, 4, 1, 1), SV32P(4, 8, 1, 1),
-                             SV32P(4, 4, 1, 1)};
+                             SV32P(4, 4, 1, 1), SV32(1, 4, 1)};
 constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
 
 // Symmetric FP32 adjoint variants, indices kNumAdj32 + k in the ADJOINT tables.
@@ -215,26 +199,22 @@ void launch_adj_sym(dim3 g, hipStream_t st, const float4* jadj, int64_t n, int32
 }
 template <int W, int I, bool COMP, int ROT>
 void launch_adj_sym_batched(dim3 g, hipStream_t st, const float4* jadj, const SymUnit* units, int32_t n_units,
-                            int32_t* counter, float eps2, float* part) {
+                            float eps2, float* part) {
   hipLaunchKernelGGL((adjoint_sym_batched_kernel<W, I, COMP, ROT>), g, dim3(W * 64), 0, st, jadj, units, n_units,
-                     counter, eps2, part);
+                     eps2, part);
 }
-template <int W, int I, bool COMP, int ROT>
-const void* adj_sym_batched_ptr() { return (const void*)&adjoint_sym_batched_kernel<W, I, COMP, ROT>; }
 struct AdjSymVariant {
   int w, i, rot;
   SymFn fn[2];  // [comp]
   SymBatchedFn bfn[2];
-  const void* (*bptr[2])();
 };
 #define SA32(W, I, R)                                                                                     \
   AdjSymVariant {                                                                                         \
     W, I, R, {launch_adj_sym<W, I, false, R>, launch_adj_sym<W, I, true, R>},                            \
-        {launch_adj_sym_batched<W, I, false, R>, launch_adj_sym_batched<W, I, true, R>},                 \
-        {adj_sym_batched_ptr<W, I, false, R>, adj_sym_batched_ptr<W, I, true, R>}                        \
+        {launch_adj_sym_batched<W, I, false, R>, launch_adj_sym_batched<W, I, true, R>}                  \
   }
 const AdjSymVariant kAdjSym32[] = {SA32(4, 2, 1), SA32(2, 2, 1), SA32(4, 4, 1), SA32(2, 4, 1), SA32(8, 2, 1),
-                                   SA32(4, 2, 0), SA32(2, 4, 0)};
+                                   SA32(4, 2, 0), SA32(2, 4, 0), SA32(1, 4, 1)};
 constexpr int kNumAdjSym32 = sizeof(kAdjSym32) / sizeof(kAdjSym32[0]);
 
 constexpr int kNumForce32 = sizeof(kForce32) / sizeof(kForce32[0]);
@@ -472,7 +452,7 @@ struct Plan {
   // batched metadata
   size_t off_meta = 0, sz_meta = 0;
   size_t off_sysoff = 0, off_nsplit = 0, off_partoff = 0, off_partoff_adj = 0, off_units = 0, off_units_adj = 0,
-         off_counter = 0, off_sync = 0, off_rtasks = 0, off_units_ro = 0;
+         off_sync = 0, off_rtasks = 0, off_units_ro = 0;
   int64_t n_units_force = 0, n_units_adj = 0;
   // buffers
   size_t off_jbuf = 0, sz_jbuf = 0;
@@ -661,7 +641,6 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     p.off_partoff_adj = take((sys.S + 1) * sizeof(int64_t));
     p.off_units = take(units_bytes);
     p.off_units_adj = take(uas.unit_bytes());
-    p.off_counter = take(2 * sizeof(int32_t));
     p.off_sync = take(16 + 2 * sys.S * sizeof(int32_t));  // whole-rollout queue, error word, per-system counts
     int64_t rchunks = 0;  // whole-rollout reduction tasks (the same for either law and tile)
     for (int64_t s = 0; s < sys.S; ++s) rchunks += cdiv(sys.off[s + 1] - sys.off[s], kRolloutChunk);
@@ -1044,21 +1023,17 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
     for (int64_t s = 0; s < c.sys.S; ++s) TRY(single(c.sys.off[s], c.sys.off[s + 1]));
     return NBODY_OK;
   }
-  // batched persistent launch
+  // batched: one launch, one workgroup per work unit (units sorted by decreasing cost)
   Tile t = lookup_tile(force_kernel_id(law, true), prec, c.sys.max_n);
-  int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter);
+  const dim3 ugrid((unsigned)std::max<int64_t>(1, c.plan.n_units_force));
   if (t.sym >= 0) {
     // symmetric tiles of every system; the unit list was built from the same tile
     if (!c.uf.sym) return fail(NBODY_ERR_DEVICE, "internal: symmetric batched tile without symmetric units");
     TRY(check_part(c, (size_t)c.uf.part_floats * sizeof(float), "force_sym_batched_kernel"));
     const SymVariant& sv = kSym32[t.sym];
-    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)2, 0);
-    LAUNCH_CHECK("fill_i32");
-    unsigned grid;
-    persistent_grid(sv.bptr[law][pot_on][mode](), sv.w * 64, c.plan.n_units_force, grid);
     float* pf = (float*)(c.ws + c.plan.off_part);
-    sv.bfn[law][pot_on][mode](dim3(grid), c.st, (const float4*)jarr, (const SymUnit*)(c.ws + c.plan.off_units),
-                              (int32_t)c.plan.n_units_force, counter, (float)eps2, pf);
+    sv.bfn[law][pot_on][mode](ugrid, c.st, (const float4*)jarr, (const SymUnit*)(c.ws + c.plan.off_units),
+                              (int32_t)c.plan.n_units_force, (float)eps2, pf);
     LAUNCH_CHECK("force_sym_batched_kernel");
     hipLaunchKernelGGL(reduce_sym_batched, rgrid(n), dim3(kReduceBS), 0, c.st, n, c.sys.S,
                        (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit),
@@ -1070,16 +1045,12 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
   if (c.uf.sym) return fail(NBODY_ERR_DEVICE, "internal: one-sided batched tile with symmetric units");
   const ForceVariant& fv = is_fp64(prec) ? kForce64[t.variant] : kForce32[t.variant];
   TRY(check_part(c, (size_t)max_nsplit(c.uf) * 4 * n * sizeof(double), "force_batched_kernel"));
-  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)2, 0);
-  LAUNCH_CHECK("fill_i32");
-  unsigned grid;
-  persistent_grid(fv.bptr[law][pot_on][mode](), t.bs, c.plan.n_units_force, grid);
   ForceOut o{};
   o.ls = c.ls;
   o.n_plane = n;
   o.part = part;
-  fv.bfn[law][pot_on][mode](dim3(grid), c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
-                            (int32_t)c.plan.n_units_force, counter, eps2, o);
+  fv.bfn[law][pot_on][mode](ugrid, c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
+                            (int32_t)c.plan.n_units_force, eps2, o);
   LAUNCH_CHECK("force_batched_kernel");
   hipLaunchKernelGGL(reduce_splits, rgrid(n), dim3(kReduceBS), 0, c.st, n, n, (int32_t)0, part, c.ls, acc, pot, vel,
                      hh, c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff),
@@ -1206,19 +1177,15 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
     return NBODY_OK;
   }
   Tile t = lookup_tile(NBODY_KERNEL_ADJOINT_BATCHED, prec, c.sys.max_n);
-  int32_t* counter = (int32_t*)(c.ws + c.plan.off_counter) + 1;
+  const dim3 ugrid((unsigned)std::max<int64_t>(1, c.plan.n_units_adj));  // one workgroup per work unit
   const int32_t* nsplit_adj = (const int32_t*)(c.ws + c.plan.off_nsplit) + c.sys.S;
   if (t.sym >= 0) {
     if (!c.ua.sym) return fail(NBODY_ERR_DEVICE, "internal: symmetric batched adjoint tile without symmetric units");
     TRY(check_part(c, (size_t)c.ua.part_floats * sizeof(float), "adjoint_sym_batched_kernel"));
     const AdjSymVariant& sv = kAdjSym32[t.sym];
-    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)1, 0);
-    LAUNCH_CHECK("fill_i32");
-    unsigned grid;
-    persistent_grid(sv.bptr[comp](), sv.w * 64, c.plan.n_units_adj, grid);
     float* pf = (float*)(c.ws + c.plan.off_part);
-    sv.bfn[comp](dim3(grid), c.st, (const float4*)jadj, (const SymUnit*)(c.ws + c.plan.off_units_adj),
-                 (int32_t)c.plan.n_units_adj, counter, (float)eps2, pf);
+    sv.bfn[comp](ugrid, c.st, (const float4*)jadj, (const SymUnit*)(c.ws + c.plan.off_units_adj),
+                 (int32_t)c.plan.n_units_adj, (float)eps2, pf);
     LAUNCH_CHECK("adjoint_sym_batched_kernel");
     hipLaunchKernelGGL(adjoint_reduce_sym, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, (const float*)pf,
                        c.cfg->G, gpos, gmass, c.sys.S,
@@ -1230,16 +1197,12 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
   if (c.ua.sym) return fail(NBODY_ERR_DEVICE, "internal: one-sided batched adjoint tile with symmetric units");
   const AdjVariant& av = is_fp64(prec) ? kAdj64[t.variant] : kAdj32[t.variant];
   TRY(check_part(c, (size_t)max_nsplit(c.ua) * 8 * n * sizeof(double), "adjoint_batched_kernel"));
-  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, c.st, counter, (int64_t)1, 0);
-  LAUNCH_CHECK("fill_i32");
-  unsigned grid;
-  persistent_grid(av.bptr[comp](), t.bs, c.plan.n_units_adj, grid);
   AdjOut o{};
   o.G = c.cfg->G;
   o.n_plane = n;
   o.part = part;
-  av.bfn[comp](dim3(grid), c.st, jadj, (const WorkUnit*)(c.ws + c.plan.off_units_adj),
-               (int32_t)c.plan.n_units_adj, counter, eps2, o);
+  av.bfn[comp](ugrid, c.st, jadj, (const WorkUnit*)(c.ws + c.plan.off_units_adj), (int32_t)c.plan.n_units_adj, eps2,
+               o);
   LAUNCH_CHECK("adjoint_batched_kernel");
   if (is_fp64(prec))
     hipLaunchKernelGGL(adjoint_reduce<double>, grid1d(n), dim3(256), 0, c.st, n, n, (int32_t)0, part, (const D4*)jadj,

@@ -924,34 +924,19 @@ struct SymUnit {
   int32_t pad;
 };
 
-// Persistent grid over the symmetric tiles of many systems (units sorted by decreasing
-// cost on the host), pulled from a shared counter that must be 0 at launch. Each tile
-// writes its own partial slots, so the result does not depend on which block ran it.
+// One workgroup per symmetric tile of many systems (units sorted by decreasing cost on the
+// host, started in index order, as force_batched_kernel). Each tile writes its own partial
+// slots, so the result does not depend on the order in which they ran.
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 __global__ __launch_bounds__(W * 64) void force_sym_batched_kernel(const float4* __restrict__ jarr,
                                                                    const SymUnit* __restrict__ units,
-                                                                   int32_t n_units, int32_t* __restrict__ counter,
-                                                                   float eps2_arg, float* __restrict__ part) {
+                                                                   int32_t n_units, float eps2_arg,
+                                                                   float* __restrict__ part) {
   constexpr int NV = MODE == MODE_DS ? 2 : 1;
   __shared__ float red[2][W][POT ? 4 : 3][64];
-  __shared__ int32_t next;
-  if (!counter) {  // one unit per workgroup, taken in launch order
-    if ((int32_t)blockIdx.x < n_units) {
-      const SymUnit su = units[blockIdx.x];
-      sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr + NV * su.base, su.n, su.A, su.B, eps2_arg, part + su.part_off,
-                                                red);
-    }
-    return;
-  }
-  for (;;) {
-    __syncthreads();  // everyone has finished with the previous unit (and its LDS sums)
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int32_t u = next;
-    if (u >= n_units) break;
-    const SymUnit su = units[u];
-    sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr + NV * su.base, su.n, su.A, su.B, eps2_arg, part + su.part_off, red);
-  }
+  if ((int32_t)blockIdx.x >= n_units) return;
+  const SymUnit su = units[blockIdx.x];
+  sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr + NV * su.base, su.n, su.A, su.B, eps2_arg, part + su.part_off, red);
 }
 
 // Per-particle sum of the batched symmetric partials: particle i of system s (found by
@@ -1129,27 +1114,20 @@ struct WorkUnit {
   int32_t pad;
 };
 
-// Persistent grid: every block pulls units from a shared counter until the list
-// is exhausted (units are sorted by decreasing cost on the host). Each unit writes
-// its own partial slot, so the result does not depend on which block ran it.
-// counter must be 0 at launch.
+// One workgroup per work unit. The units are sorted by decreasing cost on the host and the
+// hardware starts workgroups in index order, so the largest start first with no queue in
+// memory. Each unit writes its own partial slot, so the result does not depend on the order
+// in which they ran.
 template <typename T, int BS, int I, int TJ, bool POT, int MODE, int LAW>
 __global__ __launch_bounds__(BS) void force_batched_kernel(const typename Vec4<T>::type* __restrict__ jarr,
                                                            const WorkUnit* __restrict__ units, int32_t n_units,
-                                                           int32_t* __restrict__ counter, T eps2, ForceOut o) {
+                                                           T eps2, ForceOut o) {
   __shared__ typename Vec4<T>::type tile[TJ * (MODE == MODE_DS ? 2 : 1)];
-  __shared__ int32_t next;
-  for (;;) {
-    __syncthreads();  // everyone has finished with the previous `next`
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int32_t u = next;
-    if (u >= n_units) break;
-    const WorkUnit w = units[u];
-    double res[4][I];
-    force_block<T, BS, I, TJ, POT, MODE, LAW>(jarr, w.ib, w.ie, w.jb, w.je, eps2, tile, res);
-    force_store<I>(o, w.ib, w.ie, w.slot, res, POT, BS);
-  }
+  if ((int32_t)blockIdx.x >= n_units) return;
+  const WorkUnit w = units[blockIdx.x];
+  double res[4][I];
+  force_block<T, BS, I, TJ, POT, MODE, LAW>(jarr, w.ib, w.ie, w.jb, w.je, eps2, tile, res);
+  force_store<I>(o, w.ib, w.ie, w.slot, res, POT, BS);
 }
 
 __global__ void fill_i32(int32_t* p, int64_t count, int32_t v) {
@@ -1445,20 +1423,13 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(const typename Vec4<T>::typ
 template <typename T, int BS, int I, int TJ, bool COMP>
 __global__ __launch_bounds__(BS) void adjoint_batched_kernel(const typename Vec4<T>::type* __restrict__ jadj,
                                                              const WorkUnit* __restrict__ units, int32_t n_units,
-                                                             int32_t* __restrict__ counter, T eps2, AdjOut o) {
+                                                             T eps2, AdjOut o) {
   __shared__ typename Vec4<T>::type tile[2 * TJ];
-  __shared__ int32_t next;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int32_t u = next;
-    if (u >= n_units) break;
-    const WorkUnit w = units[u];
-    double res[8][I], own[7][I];
-    adjoint_block<T, BS, I, TJ, COMP>(jadj, w.ib, w.ie, w.jb, w.je, eps2, tile, res, own);
-    adjoint_store<I>(o, w.ib, w.ie, w.slot, res, own, BS);
-  }
+  if ((int32_t)blockIdx.x >= n_units) return;  // one workgroup per unit, as force_batched_kernel
+  const WorkUnit w = units[blockIdx.x];
+  double res[8][I], own[7][I];
+  adjoint_block<T, BS, I, TJ, COMP>(jadj, w.ib, w.ie, w.jb, w.je, eps2, tile, res, own);
+  adjoint_store<I>(o, w.ib, w.ie, w.slot, res, own, BS);
 }
 
 // Sum of adjoint j-split partials (fixed order), combined and added into gpos/gmass.
@@ -1681,30 +1652,16 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(const float4* __res
   adj_sym_tile<W, I, COMP, ROT>(jadj, n, A, B, eps2, part, red);
 }
 
-// Persistent grid over the symmetric adjoint tiles of many systems (counter = 0 at launch).
+// One workgroup per symmetric adjoint tile of many systems (as force_sym_batched_kernel).
 template <int W, int I, bool COMP, int ROT>
 __global__ __launch_bounds__(W * 64) void adjoint_sym_batched_kernel(const float4* __restrict__ jadj,
                                                                      const SymUnit* __restrict__ units,
-                                                                     int32_t n_units, int32_t* __restrict__ counter,
-                                                                     float eps2, float* __restrict__ part) {
+                                                                     int32_t n_units, float eps2,
+                                                                     float* __restrict__ part) {
   __shared__ float red[2][W][4][64];
-  __shared__ int32_t next;
-  if (!counter) {  // one unit per workgroup, taken in launch order
-    if ((int32_t)blockIdx.x < n_units) {
-      const SymUnit su = units[blockIdx.x];
-      adj_sym_tile<W, I, COMP, ROT>(jadj + 2 * su.base, su.n, su.A, su.B, eps2, part + su.part_off, red);
-    }
-    return;
-  }
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int32_t u = next;
-    if (u >= n_units) break;
-    const SymUnit su = units[u];
-    adj_sym_tile<W, I, COMP, ROT>(jadj + 2 * su.base, su.n, su.A, su.B, eps2, part + su.part_off, red);
-  }
+  if ((int32_t)blockIdx.x >= n_units) return;
+  const SymUnit su = units[blockIdx.x];
+  adj_sym_tile<W, I, COMP, ROT>(jadj + 2 * su.base, su.n, su.A, su.B, eps2, part + su.part_off, red);
 }
 
 // Sum of the nb float slots (4 components) of every particle in double:
