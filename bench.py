@@ -538,7 +538,7 @@ def adjoint_leg(nb, torch, np, inputs, dev):
 
 def batched_leg(nb, torch, np, inputs, dev):
     """512 independent systems, N per system log-uniform in [64, 8192], cube or Plummer;
-    eps = 1e-2, dt = 1e-3, 50 KDK steps, FP32 compensated forward + adjoint: one persistent
+    eps = 1e-2, dt = 1e-3, 50 KDK steps, FP32 compensated forward + adjoint: one
     launch per batched pass against looping the single-system kernels."""
     log("batched leg")
     W = inputs.WORKLOADS["batch512"]
@@ -551,7 +551,7 @@ def batched_leg(nb, torch, np, inputs, dev):
     m = torch.from_numpy(b.mass).to(dev)
     res = {"workload": "batch512: 512 systems, N_s log-uniform [64, 8192] (sum N = %d, sum N^2 = %.3e), eps=1e-2, "
                        "50 KDK steps dt=1e-3, FP32 compensated" % (int(off[-1]), sum_n2)}
-    for name, flags in (("persistent", 0), ("looped", nb.FLAG_LOOP_SYSTEMS)):
+    for name, flags in (("one_launch", 0), ("looped", nb.FLAG_LOOP_SYSTEMS)):
         pos, vel = x0.clone(), v0.clone()
         acc, _ = nb.forces(pos, m, eps=W["eps"], precision="fp32c", offsets=off, flags=flags)
         ckpt, _ = nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], ckpt_every=10, eps=W["eps"], precision="fp32c",
@@ -579,12 +579,12 @@ def batched_leg(nb, torch, np, inputs, dev):
                      "forward_interactions_per_s": (W["steps"] + 1) * sum_n2 / (f_ms * 1e-3),
                      "adjoint_interactions_per_s_incl_recompute": (W["steps"] + 1) * sum_n2 / (b_ms * 1e-3)}
         res[name + "_final_pos"] = pos
-    d = float(torch.max(torch.abs(res["persistent_final_pos"] - res["looped_final_pos"])))
-    del res["persistent_final_pos"], res["looped_final_pos"]
-    res["max_abs_pos_diff_persistent_vs_looped"] = d
-    res["speedup_forward"] = res["looped"]["forward_ms"] / res["persistent"]["forward_ms"]
-    res["speedup_backward"] = res["looped"]["backward_ms"] / res["persistent"]["backward_ms"]
-    # forward without checkpoints: one persistent launch per pass against every step in one launch,
+    d = float(torch.max(torch.abs(res["one_launch_final_pos"] - res["looped_final_pos"])))
+    del res["one_launch_final_pos"], res["looped_final_pos"]
+    res["max_abs_pos_diff_one_launch_vs_looped"] = d
+    res["speedup_forward"] = res["looped"]["forward_ms"] / res["one_launch"]["forward_ms"]
+    res["speedup_backward"] = res["looped"]["backward_ms"] / res["one_launch"]["backward_ms"]
+    # forward without checkpoints: one launch per pass against every step in one launch,
     # on this mix and on a mix of tiny systems (4096 systems of 16-256 particles)
     res["rollout_no_checkpoints"] = whole_rollout_compare(nb, torch, np, b, W, sum_n2)
     tiny = inputs.batched_mix(4096, 7, nmin=16, nmax=256)

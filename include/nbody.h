@@ -78,7 +78,7 @@ typedef enum { NBODY_FP64 = 0, NBODY_FP32 = 1, NBODY_FP32_COMP = 2, NBODY_FP32_D
 
 /* config.flags */
 #define NBODY_FLAG_LOOP_SYSTEMS 1u /* batched calls: one plain launch per system
-                                      instead of one persistent launch (baseline) */
+                                      instead of one launch for all systems (baseline) */
 #define NBODY_FLAG_WHOLE_ROLLOUT 2u /* nbody_rollout / nbody_lj_rollout of a batch on
                                       symmetric tiles without an energy trace or
                                       checkpoints: every step in one launch, systems

@@ -159,7 +159,7 @@ BATCH_MIXES = [(4096, 16, 256, 7), (1024, 64, 2048, 8), (512, 64, 8192, 6)]
 
 
 def tune_batched(nb, torch, precision, log, mixes=BATCH_MIXES):
-    """Batched persistent force and adjoint passes on mixes of uneven systems (N_s
+    """Batched force and adjoint passes on mixes of uneven systems (N_s
     log-uniform), one table bucket per mix keyed by its largest system. Each candidate is
     timed inside a 10-step rollout (force) or a 10-step backward (adjoint), so the library's
     per-call host work (work-unit lists, uploads) is paid once per 10 passes as in use."""

@@ -614,7 +614,7 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
       } else {
         build_units(sys, tf, tmp);
         force_S = std::max(force_S, max_nsplit(tmp));
-        force_part = std::max(force_part, (size_t)max_nsplit(tmp) * 4 * nd);  // persistent kernels always write partials
+        force_part = std::max(force_part, (size_t)max_nsplit(tmp) * 4 * nd);  // batched one-sided units always write partials
       }
       units_bytes = std::max(units_bytes, tmp.unit_bytes());
       if (lw == law) ufs = std::move(tmp);

@@ -1104,7 +1104,7 @@ __global__ __launch_bounds__(W * 64) void rollout_sym_batched_kernel(
   }
 }
 
-// ----------------------------------------------------------------- batched persistent force pass
+// ----------------------------------------------------------------- batched one-sided force pass
 
 // One work unit: an i-tile of one system against one j-chunk of the same system.
 struct WorkUnit {

@@ -245,7 +245,7 @@ def test_lj_energy_conservation_paper_size(nb):
 
 
 def test_lj_batched_vs_oracle_and_loop(nb, oracle):
-    """Independent gases of uneven sizes in one persistent launch and in a per-system loop."""
+    """Independent gases of uneven sizes in one launch per pass and in a per-system loop."""
     sizes = [64, 300, 1, 0, 1500, 700]
     parts = [_gas(k, 900 + i) if k else (np.zeros((3, 0)), np.zeros(0), None, None) for i, k in enumerate(sizes)]
     off = np.zeros(len(sizes) + 1, dtype=np.int64)

@@ -410,7 +410,7 @@ def test_batched_rollout_energy(nb, oracle):
 
 def test_batched_symmetric_variants(nb, oracle):
     """The batched symmetric pass (every upper-triangle tile of every system in one
-    persistent launch, float tile partials per system), every variant forced through the
+    launch, float tile partials per system), every variant forced through the
     tile table, on systems that are empty, single, smaller than a block and several blocks
     with a ragged edge; against the oracle per system, with and without the potential."""
     sizes = [0, 1, 2, 63, 130, 0, 700, 2500, 1]
