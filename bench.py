@@ -603,7 +603,7 @@ def whole_rollout_compare(nb, torch, np, b, W, sum_n2):
     v0 = torch.from_numpy(b.vel).cuda()
     m = torch.from_numpy(b.mass).cuda()
     wr = {}
-    for name, flags in (("per_pass", 0), ("whole_rollout", nb.FLAG_WHOLE_ROLLOUT)):
+    for name, flags in (("per_pass", nb.FLAG_PER_PASS), ("whole_rollout", nb.FLAG_WHOLE_ROLLOUT)):
         pos, vel = x0.clone(), v0.clone()
         acc, _ = nb.forces(pos, m, eps=W["eps"], precision="fp32c", offsets=off)
         nb.rollout(pos, vel, m, acc, W["dt"], W["steps"], eps=W["eps"], precision="fp32c", offsets=off, flags=flags)

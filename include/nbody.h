@@ -84,9 +84,15 @@ typedef enum { NBODY_FP64 = 0, NBODY_FP32 = 1, NBODY_FP32_COMP = 2, NBODY_FP32_D
                                       checkpoints: every step in one launch, systems
                                       advancing independently (per-system waits on
                                       device counters); the trajectory is bitwise that
-                                      of the per-step path. Such a call waits for the
-                                      launch to finish (it reads back a device error
-                                      word). Ignored where it does not apply. */
+                                      of the per-step path. When some system spans
+                                      several tiles the call waits for the launch to
+                                      finish (it reads back a device error word).
+                                      Ignored where it does not apply. A batch whose
+                                      systems all fit one tile takes this path without
+                                      the flag (no waits, no read-back). */
+#define NBODY_FLAG_PER_PASS 4u      /* batched rollouts: one launch per pass even where
+                                      every step in one launch would be chosen (the
+                                      baseline of that choice; results are identical) */
 
 typedef struct {
   int32_t abi_version;     /* must equal NBODY_ABI_VERSION */

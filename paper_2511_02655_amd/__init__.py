@@ -28,6 +28,7 @@ KERNELS = {"force": 0, "adjoint": 1, "force_batched": 2, "adjoint_batched": 3, "
            "lj_force_batched": 5}
 FLAG_LOOP_SYSTEMS = 1
 FLAG_WHOLE_ROLLOUT = 2  # batched symmetric rollouts: every step in one launch
+FLAG_PER_PASS = 4  # batched rollouts: one launch per pass even where one launch for all steps is chosen
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPACE"}
 
 EXPORTED = ("nbody_abi_version", "nbody_last_error", "nbody_workspace_size", "nbody_forces", "nbody_step",

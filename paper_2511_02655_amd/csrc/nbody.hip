@@ -419,7 +419,7 @@ int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys, bool law_checks 
       return fail(NBODY_ERR_INVALID_ARG, "eps must be >= 1e-10 for the FP32 modes (got %g)", cfg->eps);
   }
   if (cfg->reserved != 0) return fail(NBODY_ERR_INVALID_ARG, "reserved must be 0");
-  if (cfg->flags & ~(NBODY_FLAG_LOOP_SYSTEMS | NBODY_FLAG_WHOLE_ROLLOUT))
+  if (cfg->flags & ~(NBODY_FLAG_LOOP_SYSTEMS | NBODY_FLAG_WHOLE_ROLLOUT | NBODY_FLAG_PER_PASS))
     return fail(NBODY_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
   if (n < 0) return fail(NBODY_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)n);
   if (n > ((int64_t)1 << 31)) return fail(NBODY_ERR_UNSUPPORTED, "n = %lld exceeds 2^31", (long long)n);
@@ -1315,6 +1315,7 @@ int whole_rollout(Ctx& c, double dt, int64_t steps, double* pos, double* vel, co
                     (const int64_t*)(c.ws + c.plan.off_partoff), (float)c.eps2, (float*)(c.ws + c.plan.off_part), c.ls,
                     acc, vel, 0.5 * dt, nx, (int32_t)steps, sy);
   LAUNCH_CHECK("rollout_sym_batched_kernel");
+  if (n_multi == 0) return NBODY_OK;  // no task waits on another: nothing can time out
   int32_t err = 0;
   HIP_TRY(hipMemcpyAsync(&err, sy.err, sizeof err, hipMemcpyDeviceToHost, c.st));
   HIP_TRY(hipStreamSynchronize(c.st));
@@ -1345,8 +1346,12 @@ int rollout_impl(Ctx& c, int64_t n, double dt, int64_t steps, int64_t ckpt_every
     TRY(energy_pass(c, vel, mass, pot, energy_trace));
   }
   const NextStep nx = next_step(c, dt, pos, mass);
-  if ((c.cfg->flags & NBODY_FLAG_WHOLE_ROLLOUT) && !energy_trace && !ckpt && steps > 0)
-    if (c.bat && !c.loop && c.uf.sym) return whole_rollout(c, dt, steps, pos, vel, mass, acc, nx);
+  // every step in one launch: on request, and by default when every system fits one tile (no
+  // workgroup then waits on another, and the launch beats one per pass)
+  if (!energy_trace && !ckpt && steps > 0 && c.bat && !c.loop && c.uf.sym &&
+      ((c.cfg->flags & NBODY_FLAG_WHOLE_ROLLOUT) ||
+       (!(c.cfg->flags & NBODY_FLAG_PER_PASS) && c.uf.n_solo == (int64_t)c.uf.ro_units.size())))
+    return whole_rollout(c, dt, steps, pos, vel, mass, acc, nx);
   bool staged = false;  // the previous pass already ran this step's kick, drift and staging
   for (int64_t s = 0; s < steps; ++s) {
     if (!staged) TRY(kick_drift(c, dt, pos, vel, acc, mass));

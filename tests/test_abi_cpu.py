@@ -116,8 +116,8 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails val
     (dict(offsets=[1, 5, 10]), 1, "offsets[0]"),
     (dict(offsets=[0, 5, 9]), 1, "must equal n"),
     (dict(flags=8), 1, "flags"),
-    (dict(flags=4), 1, "flags"),
-    (dict(flags=3 | 16), 1, "flags"),
+    (dict(flags=16), 1, "flags"),
+    (dict(flags=7 | 32), 1, "flags"),
     (dict(reserved=1), 1, "reserved"),
     (dict(), 4, "workspace is NULL"),
     (dict(ws=0x1000, ws_bytes=10), 4, "too small"),
@@ -217,7 +217,7 @@ def test_lj_ignores_gravity_constants(nb):
 def test_known_flags_accepted(nb):
     """The per-system loop and the whole-rollout flags pass validation (the call then stops
     at the missing workspace, the first check after the configuration)."""
-    for flags in (nb.FLAG_LOOP_SYSTEMS, nb.FLAG_WHOLE_ROLLOUT, nb.FLAG_LOOP_SYSTEMS | nb.FLAG_WHOLE_ROLLOUT):
+    for flags in (nb.FLAG_LOOP_SYSTEMS, nb.FLAG_WHOLE_ROLLOUT, nb.FLAG_PER_PASS, 7):
         c = _cfg(nb, flags=flags)
         assert nb.lib().nbody_forces(ctypes.byref(c), 10, FAKE, FAKE, FAKE, None) == 4
         assert "workspace is NULL" in nb.lib().nbody_last_error().decode()

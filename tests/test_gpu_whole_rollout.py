@@ -64,7 +64,7 @@ def test_whole_rollout_bitwise_equals_per_step(nb, prec):
         for v in _sym_batched(nb, prec):
             nb.set_tile_table([dict(kernel="force_batched", precision=prec, n_min=0, n_max=1 << 40, variant=v,
                                     j_split=1)])
-            ref = _run(nb, off, pos, vel, mass, 7, 0, prec)
+            ref = _run(nb, off, pos, vel, mass, 7, nb.FLAG_PER_PASS, prec)
             got = _run(nb, off, pos, vel, mass, 7, nb.FLAG_WHOLE_ROLLOUT, prec)
             for a, b in zip(ref[:3], got[:3]):
                 assert np.array_equal(a, b), (v, prec)
@@ -88,7 +88,7 @@ def test_whole_rollout_vs_oracle(nb, oracle):
 @pytest.mark.parametrize("steps", [0, 1, 2])
 def test_whole_rollout_few_steps(nb, steps):
     off, pos, vel, mass = _mixed_batch(3)
-    ref = _run(nb, off, pos, vel, mass, steps, 0, "fp32c")
+    ref = _run(nb, off, pos, vel, mass, steps, nb.FLAG_PER_PASS, "fp32c")
     got = _run(nb, off, pos, vel, mass, steps, nb.FLAG_WHOLE_ROLLOUT, "fp32c")
     for a, b in zip(ref[:3], got[:3]):
         assert np.array_equal(a, b)
@@ -136,7 +136,7 @@ def test_whole_rollout_lennard_jones_walls(nb):
     off = np.zeros(len(gases) + 1, dtype=np.int64)
     off[1:] = np.cumsum([g.n for g, _ in gases])
     outs = []
-    for flags in (0, nb.FLAG_WHOLE_ROLLOUT):
+    for flags in (nb.FLAG_PER_PASS, nb.FLAG_WHOLE_ROLLOUT):
         p, v, m = dev(pos), dev(vel), dev(mass)
         a, _ = nb.lj_forces(p, m, precision="fp32c", offsets=off)
         nb.lj_rollout(p, v, m, a, 2e-3, 30, box=(lo, hi), precision="fp32c", offsets=off, flags=flags)
@@ -154,7 +154,7 @@ def test_whole_rollout_many_systems(nb, name, steps, reps):
     b = inputs.make("batch512") if name == "batch512" else inputs.batched_mix(4096, 21, nmin=16, nmax=300)
     p, v, m = dev(b.pos), dev(b.vel), dev(b.mass)
     a, _ = nb.forces(p, m, eps=1e-2, precision="fp32c", offsets=b.offsets)
-    nb.rollout(p, v, m, a, 1e-3, steps, eps=1e-2, precision="fp32c", offsets=b.offsets)
+    nb.rollout(p, v, m, a, 1e-3, steps, eps=1e-2, precision="fp32c", offsets=b.offsets, flags=nb.FLAG_PER_PASS)
     ref = (host(p), host(v), host(a))
     for _ in range(reps):
         p, v, m = dev(b.pos), dev(b.vel), dev(b.mass)
@@ -163,3 +163,19 @@ def test_whole_rollout_many_systems(nb, name, steps, reps):
                    flags=nb.FLAG_WHOLE_ROLLOUT)
         for x, y in zip(ref, (host(p), host(v), host(a))):
             assert np.array_equal(x, y)
+
+
+def test_single_tile_batches_take_one_launch_by_default(nb):
+    """A batch whose systems all fit one tile runs every step in one launch without the flag
+    (no waits, no read-back); the result is bitwise that of one launch per pass."""
+    import torch
+    b = inputs.batched_mix(2048, 31, nmin=8, nmax=200)
+    outs = []
+    for flags in (nb.FLAG_PER_PASS, 0):
+        p, v, m = dev(b.pos), dev(b.vel), dev(b.mass)
+        a, _ = nb.forces(p, m, eps=1e-2, precision="fp32c", offsets=b.offsets)
+        nb.rollout(p, v, m, a, 1e-3, 30, eps=1e-2, precision="fp32c", offsets=b.offsets, flags=flags)
+        torch.cuda.synchronize()
+        outs.append((host(p), host(v), host(a)))
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
