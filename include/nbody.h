@@ -275,6 +275,13 @@ int nbody_tile_lookup(int32_t kernel, int32_t precision, int64_t n, int32_t *var
 const char *nbody_last_error(void); /* thread-local, valid until the next call on this thread */
 int nbody_abi_version(void);
 
+/* Probes (each a device-scope load and a short sleep) a wait of the whole-rollout launch
+ * (NBODY_FLAG_WHOLE_ROLLOUT) makes before it gives up; the launch then ends early and the
+ * call returns NBODY_ERR_DEVICE. Default 2^24 (seconds). probes >= 1, else
+ * NBODY_ERR_INVALID_ARG. For failure-path tests and for diagnosing a stalled launch;
+ * process-wide, applies to launches made after the call. */
+int nbody_set_wait_limit(int64_t probes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPAC
 EXPORTED = ("nbody_abi_version", "nbody_last_error", "nbody_workspace_size", "nbody_forces", "nbody_step",
             "nbody_rollout", "nbody_energy_momentum", "nbody_rollout_backward", "nbody_set_tile_table",
             "nbody_tile_variants", "nbody_tile_lookup", "nbody_lj_forces", "nbody_lj_rollout",
-            "nbody_rollout_backward_reversible", "nbody_diagnostics")
+            "nbody_rollout_backward_reversible", "nbody_diagnostics", "nbody_set_wait_limit")
 
 
 class NBodyError(RuntimeError):
@@ -114,6 +114,7 @@ def lib():
                                ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "nbody_lj_forces": ([C, ctypes.POINTER(LJParams), I64, P, P, P, P], ctypes.c_int),
         "nbody_lj_rollout": ([C, ctypes.POINTER(LJParams), I64, D, I64, P, P, P, P, P], ctypes.c_int),
+        "nbody_set_wait_limit": ([I64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -157,8 +158,17 @@ def _set_table(L, entries):
 
 
 def set_tile_table(entries: Sequence[dict]):
-    """Replace the tile table; entries are dicts with kernel, precision, n_min, n_max, variant, j_split."""
+    """Replace the tile table; entries are dicts with kernel, precision, n_min, n_max, variant, j_split.
+    An empty list selects the library's built-in defaults (restore_tile_table reloads the tuned table)."""
     _set_table(lib(), list(entries))
+
+
+def restore_tile_table():
+    """Reload the table loaded at start-up (NBODY_TILE_TABLE or tune/gfx950.json; the built-in
+    defaults when there is none)."""
+    L = lib()
+    _set_table(L, [])
+    _load_default_tiles(L)
 
 
 def tile_variants(kernel: str, precision: str):
@@ -167,6 +177,11 @@ def tile_variants(kernel: str, precision: str):
     if nv < 0:
         raise NBodyError(1, lib().nbody_last_error().decode())
     return [s.decode() for s in buf.raw.split(b"\0")[:nv]]
+
+
+def set_wait_limit(probes: int = 1 << 24) -> None:
+    """Probes a whole-rollout wait makes before it gives up (default 2^24)."""
+    _check(lib().nbody_set_wait_limit(int(probes)))
 
 
 def tile_lookup(kernel: str, precision: str, n: int):

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -21,6 +22,9 @@ using namespace nbody;
 namespace {
 
 thread_local std::string g_err;
+
+// Probes a whole-rollout wait makes before it gives up (nbody_set_wait_limit).
+std::atomic<int64_t> g_wait_limit{int64_t(1) << 24};
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
@@ -1236,6 +1240,13 @@ extern "C" {
 
 __attribute__((visibility("default"))) int nbody_abi_version(void) { return NBODY_ABI_VERSION; }
 
+__attribute__((visibility("default"))) int nbody_set_wait_limit(int64_t probes) {
+  g_err.clear();
+  if (probes < 1) return fail(NBODY_ERR_INVALID_ARG, "probes must be >= 1 (got %lld)", (long long)probes);
+  g_wait_limit.store(probes);
+  return NBODY_OK;
+}
+
 __attribute__((visibility("default"))) const char* nbody_last_error(void) { return g_err.c_str(); }
 
 __attribute__((visibility("default"))) int nbody_workspace_size(const nbody_config* cfg, int64_t n, int64_t steps,
@@ -1304,6 +1315,7 @@ int whole_rollout(Ctx& c, double dt, int64_t steps, double* pos, double* vel, co
   sy.err = words + 2;
   sy.tiles_done = words + 4;
   sy.red_done = words + 4 + c.sys.S;
+  sy.spin_limit = g_wait_limit.load();
   unsigned grid;
   const int64_t n_rtasks = (int64_t)c.uf.rtasks.size() / 2;
   const int64_t n_solo = c.uf.n_solo, n_multi = (int64_t)c.uf.ro_units.size() - n_solo;

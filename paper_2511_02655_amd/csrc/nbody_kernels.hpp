@@ -985,13 +985,13 @@ struct RolloutSync {
   int32_t* err;
   int32_t* tiles_done;
   int32_t* red_done;
+  int64_t spin_limit;  // probes before a wait gives up
 };
 
 // Bounded wait of one thread for *p >= v: agent-scope loads, each followed by a short sleep;
-// gives up (and sets err) after kSpinLimit probes, or when another workgroup has given up.
-constexpr int64_t kSpinLimit = 1ll << 24;
-__device__ __forceinline__ bool wait_at_least(const int32_t* p, int32_t v, int32_t* err) {
-  for (int64_t k = 0; k < kSpinLimit; ++k) {
+// gives up (and sets err) after limit probes, or when another workgroup has given up.
+__device__ __forceinline__ bool wait_at_least(const int32_t* p, int32_t v, int32_t* err, int64_t limit) {
+  for (int64_t k = 0; k < limit; ++k) {
     if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     __builtin_amdgcn_s_sleep(2);
@@ -1072,7 +1072,7 @@ __global__ __launch_bounds__(W * 64) void rollout_sym_batched_kernel(
     if (r < n_units) {
       const SymUnit su = units[n_solo + r];
       const int32_t chunks = (su.n + kRolloutChunk - 1) / kRolloutChunk;  // reduction tasks of the system
-      if (threadIdx.x == 0) ok_sh = t == 0 || wait_at_least(sy.red_done + su.sys, t * chunks, sy.err);
+      if (threadIdx.x == 0) ok_sh = t == 0 || wait_at_least(sy.red_done + su.sys, t * chunks, sy.err, sy.spin_limit);
       __syncthreads();
       if (!ok_sh) break;
       __threadfence();  // every thread: ordered after the positions staged by (s, t - 1)
@@ -1085,7 +1085,7 @@ __global__ __launch_bounds__(W * 64) void rollout_sym_batched_kernel(
       const int64_t b = sys_off[s], ns = sys_off[s + 1] - b;
       const int64_t l1 = l0 + kRolloutChunk < ns ? l0 + kRolloutChunk : ns;
       const int32_t nb = sys_nb[s];
-      if (threadIdx.x == 0) ok_sh = wait_at_least(sy.tiles_done + s, (t + 1) * (nb * (nb + 1) / 2), sy.err);
+      if (threadIdx.x == 0) ok_sh = wait_at_least(sy.tiles_done + s, (t + 1) * (nb * (nb + 1) / 2), sy.err, sy.spin_limit);
       __syncthreads();
       if (!ok_sh) break;
       __threadfence();  // every thread: ordered after the tiles' partial sums

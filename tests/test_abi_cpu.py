@@ -162,7 +162,7 @@ def test_tile_table_validation(nb):
         nb.set_tile_table([dict(kernel="force", precision="fp32c", n_min=0, n_max=10, variant=99, j_split=1)])
     with pytest.raises(nb.NBodyError):
         nb.set_tile_table([dict(kernel="force", precision="fp32c", n_min=5, n_max=1, variant=0, j_split=1)])
-    nb.set_tile_table([])
+    nb.restore_tile_table()
     v, s = nb.tile_lookup("force", "fp32c", 1 << 20)
     assert v >= 0 and s >= 1
 
@@ -237,3 +237,28 @@ def test_workspace_size_covers_whole_rollout_tables(nb):
         assert nb.lib().nbody_workspace_size(ctypes.byref(c), int(off[-1]), 10, 0, ctypes.byref(out)) == 0
         b.append(out.value)
     assert b[0] == b[1] and b[0] > 0
+
+
+def test_wait_limit_argument(nb):
+    assert nb.lib().nbody_set_wait_limit(0) == 1
+    assert "probes" in nb.lib().nbody_last_error().decode()
+    assert nb.lib().nbody_set_wait_limit(-5) == 1
+    assert nb.lib().nbody_set_wait_limit(1 << 24) == 0
+
+
+def test_restore_tile_table(nb):
+    """An empty table selects the built-in defaults; restore_tile_table reloads the tuned
+    table the binding loaded at start-up."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(nb.__file__), "tune", "gfx950.json")
+    tuned = [e for e in json.load(open(path))["entries"]
+             if e["kernel"] == "force" and e["precision"] == "fp32c" and e["n_min"] <= (1 << 20) <= e["n_max"]][0]
+    try:
+        nb.set_tile_table([])
+        builtin = nb.tile_lookup("force", "fp32c", 1 << 20)
+        nb.restore_tile_table()
+        assert nb.tile_lookup("force", "fp32c", 1 << 20) == (tuned["variant"], 1)
+        assert builtin != (tuned["variant"], 1)
+    finally:
+        nb.restore_tile_table()

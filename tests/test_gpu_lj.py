@@ -168,7 +168,7 @@ def test_lj_symmetric_kernel_vs_oracle(nb, oracle, n):
                     continue
                 check_lj(acc, pot, acc_ref, pot_ref, pos, mass, prec, bounds=bounds[prec])
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_lj10k_sampled_default_tiles(nb, oracle):
@@ -290,7 +290,7 @@ def test_lj_batched_symmetric(nb, oracle):
                     sl = slice(off[k], off[k + 1])
                     check_lj(acc[:, sl], pot[sl], refs[k][0], refs[k][1], pos[:, sl], mass[sl], prec)
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_lj_argument_errors(nb):

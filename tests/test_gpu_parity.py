@@ -317,7 +317,7 @@ def test_fused_energy_trace_equals_separate_passes(nb, case):
             nb.step(p2, v2, m, a2, dt, out_pot=pot, **kw)
             rows.append(host(nb.energy_momentum(p2, v2, m, pot=pot, **kw)))
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
     assert np.array_equal(host(p), host(p2)) and np.array_equal(host(v), host(v2))
     assert np.array_equal(host(trace), np.stack(rows)), np.max(np.abs(host(trace) - np.stack(rows)))
 
@@ -449,7 +449,7 @@ def test_batched_symmetric_variants(nb, oracle):
                             p_ = host(pot)[sl]
                             assert np.max(np.abs(p_ - refs[k][1]) / np.abs(refs[k][1])) <= TOL_P[prec], (v, prec)
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_batched_symmetric_rollout_matches_looped(nb, oracle):
@@ -470,7 +470,7 @@ def test_batched_symmetric_rollout_matches_looped(nb, oracle):
             outs.append((host(pos), host(tr)))
         assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
     x = outs[0][0]
     for s in range(len(off) - 1):
         sl = slice(off[s], off[s + 1])
@@ -733,7 +733,7 @@ def test_symmetric_adjoint_variants(nb, oracle, n):
                 for a, b in zip(out, out2):
                     assert np.array_equal(a, b)
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_batched_symmetric_adjoint(nb, oracle):
@@ -770,7 +770,7 @@ def test_batched_symmetric_adjoint(nb, oracle):
                     else:
                         assert _rel_l2(a[..., sl], b) <= 1e-4, (v, k)
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_autograd_function(nb, oracle):
@@ -822,7 +822,7 @@ def test_symmetric_kernel_vs_oracle(nb, oracle, n):
                     if want_pot:
                         assert np.max(np.abs(host(pot) - pot_ref) / np.abs(pot_ref)) <= TOL_P[prec], (v, prec)
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_symmetric_plummer_and_determinism(nb, oracle):
@@ -840,7 +840,7 @@ def test_symmetric_plummer_and_determinism(nb, oracle):
             assert e <= 1e-5, (v, e)
             assert np.max(np.abs(host(p1)[idx] - pot_ref) / np.abs(pot_ref)) <= 1e-6
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_symmetric_rollout_backward_invariance(nb, oracle):
@@ -866,7 +866,7 @@ def test_symmetric_rollout_backward_invariance(nb, oracle):
         for a, b in zip(res[0], ref):
             assert _rel_l2(a, b) <= 1e-4
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_step_potential_output(nb):

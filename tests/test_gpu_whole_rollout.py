@@ -69,7 +69,7 @@ def test_whole_rollout_bitwise_equals_per_step(nb, prec):
             for a, b in zip(ref[:3], got[:3]):
                 assert np.array_equal(a, b), (v, prec)
     finally:
-        nb.set_tile_table([])
+        nb.restore_tile_table()
 
 
 def test_whole_rollout_vs_oracle(nb, oracle):
@@ -179,3 +179,32 @@ def test_single_tile_batches_take_one_launch_by_default(nb):
         outs.append((host(p), host(v), host(a)))
     for x, y in zip(*outs):
         assert np.array_equal(x, y)
+
+
+def test_whole_rollout_wait_limit_reports_error(nb):
+    """Failure path, forced from the host: two large systems, so that a reduction task is
+    taken while its system's tiles still run and must wait; with a one-probe wait limit it
+    gives up, every workgroup leaves the launch, and the call returns the device error. With
+    the default limit restored the same rollout completes and matches one launch per pass
+    bitwise."""
+    b = inputs.batched_mix(2, 41, nmin=6000, nmax=8192)
+
+    def run(flags):
+        p, v, m = dev(b.pos), dev(b.vel), dev(b.mass)
+        a, _ = nb.forces(p, m, eps=1e-2, precision="fp32c", offsets=b.offsets)
+        nb.rollout(p, v, m, a, 1e-3, 5, eps=1e-2, precision="fp32c", offsets=b.offsets, flags=flags)
+        return host(p)
+
+    sym = [k for k, d in enumerate(nb.tile_variants("force_batched", "fp32c")) if "sym=1024" in d][0]
+    try:
+        nb.set_tile_table([dict(kernel="force_batched", precision="fp32c", n_min=0, n_max=1 << 40, variant=sym,
+                                j_split=1)])
+        nb.set_wait_limit(1)
+        with pytest.raises(nb.NBodyError) as ei:
+            run(nb.FLAG_WHOLE_ROLLOUT)
+        assert ei.value.code == 2 and "gave up" in str(ei.value)
+        nb.set_wait_limit()
+        assert np.array_equal(run(nb.FLAG_WHOLE_ROLLOUT), run(nb.FLAG_PER_PASS))
+    finally:
+        nb.set_wait_limit()
+        nb.restore_tile_table()
