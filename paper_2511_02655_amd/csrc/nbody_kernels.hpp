@@ -891,16 +891,38 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 // Sum of the nb float slots of every particle in double (fixed order), scaled by the
 // law's constants; optional potential and closing half-kick.
 // n: particles of the system (partial plane stride); stride: plane stride of acc/vel.
+// a[c] += slot s of component c, s = 0 .. nb-1 in order, for the particle at offset i of
+// planes of stride n (slot s, component c at (s * 4 + c) * n). The loads of 8 slots are issued
+// before their additions, which keep the slot order (so the sum is the plain loop's).
+template <int NC>
+__device__ __forceinline__ void sum_slots(const float* __restrict__ part, int64_t n, int64_t i, int32_t nb,
+                                          double a[4]) {
+  int32_t s = 0;
+  for (; s + 8 <= nb; s += 8) {
+    float v[8][NC];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[k][c] = part[((int64_t)(s + k) * 4 + c) * n + i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) a[c] += (double)v[k][c];
+  }
+  for (; s < nb; ++s)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
+}
+
 __global__ __launch_bounds__(kReduceBS) void reduce_sym(int64_t n, int64_t stride, int32_t nb,
                                                        const float* __restrict__ part, LawScale ls,
                                                        double* __restrict__ acc, double* __restrict__ pot,
                                                        double* __restrict__ vel, double hh, NextStep nx,
                                                        EnergyFuse ef) {
-  const int nc = pot ? 4 : 3;
   auto body = [&](int64_t i, double* en) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t s = 0; s < nb; ++s)
-      for (int c = 0; c < nc; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
+    if (pot) sum_slots<4>(part, n, i, nb, a);
+    else sum_slots<3>(part, n, i, nb, a);
     finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
   };
   if (ef.part) {  // grid (chunks, 1)
@@ -949,14 +971,13 @@ __global__ __launch_bounds__(kReduceBS) void reduce_sym_batched(int64_t n, int64
                                                                double* __restrict__ acc, double* __restrict__ pot,
                                                                double* __restrict__ vel, double hh, NextStep nx,
                                                                EnergyFuse ef) {
-  const int nc = pot ? 4 : 3;
   auto body = [&](int64_t i, int64_t s, double* en) {
     const int64_t b = sys_off[s], ns = sys_off[s + 1] - b, li = i - b;
     const int32_t nb = sys_nb[s];
     const float* ps = part + sys_part[s];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t k = 0; k < nb; ++k)
-      for (int c = 0; c < nc; ++c) a[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
+    if (pot) sum_slots<4>(ps, ns, li, nb, a);
+    else sum_slots<3>(ps, ns, li, nb, a);
     finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
   };
   if (ef.part) {  // grid (chunks, systems)
@@ -1094,9 +1115,7 @@ __global__ __launch_bounds__(W * 64) void rollout_sym_batched_kernel(
       if (t + 1 >= steps) nxt.kind = 0;  // the last step stages nothing
       for (int64_t li = l0 + threadIdx.x; li < l1; li += W * 64) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int32_t k = 0; k < nb; ++k)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) a[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
+        sum_slots<3>(ps, ns, li, nb, a);
         finish_particle(b + li, n, a, ls, acc, nullptr, vel, hh, nxt, nullptr, nullptr);
       }
       release_to(sy.red_done + s);
@@ -1690,9 +1709,7 @@ __global__ void adjoint_reduce_sym(int64_t n, int64_t stride, int32_t nb, const 
     ps = part + sys_part[lo];
   }
   double r[4] = {0, 0, 0, 0};
-  for (int32_t k = 0; k < nbs; ++k)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) r[c] += (double)ps[((int64_t)k * 4 + c) * ns + li];
+  sum_slots<4>(ps, ns, li, nbs, r);
 #pragma unroll
   for (int c = 0; c < 3; ++c) gpos[c * stride + i] += G * r[c];
   gmass[i] += -G * r[3];
