@@ -356,6 +356,28 @@ __device__ __forceinline__ void finish_particle(int64_t i, int64_t stride, const
   if (nx.kind) next_step_tail(nx, i, stride, ac, vel);
 }
 
+// a[c] += part[(p * NC + c) * n + i] for p = 0 .. S-1 in order (double partial planes of the
+// j-split passes); the loads of 4 splits are issued before their additions.
+template <int NC>
+__device__ __forceinline__ void sum_splits(const double* __restrict__ part, int64_t n, int64_t i, int32_t S,
+                                           double* a) {
+  int32_t p = 0;
+  for (; p + 4 <= S; p += 4) {
+    double v[4][NC];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[k][c] = part[((int64_t)(p + k) * NC + c) * n + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) a[c] += v[k][c];
+  }
+  for (; p < S; ++p)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a[c] += part[((int64_t)p * NC + c) * n + i];
+}
+
 // Sum of j-split partials (fixed order p = 0..S-1), scaled by the law's constants;
 // optional potential and optional closing half-kick v += hh a.
 //   part [S][4][n]: planes ax, ay, az, phi of every split.
@@ -372,9 +394,7 @@ __global__ __launch_bounds__(kReduceBS) void reduce_splits(int64_t count, int64_
   const int64_t n = stride;
   auto body = [&](int64_t i, int32_t s_cnt, double* en) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t p = 0; p < s_cnt; ++p)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a[c] += part[((int64_t)p * 4 + c) * n + i];
+    sum_splits<4>(part, n, i, s_cnt, a);
     finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
   };
   if (ef.part) {  // grid (chunks, systems)
@@ -1471,9 +1491,7 @@ __global__ void adjoint_reduce(int64_t count, int64_t stride, int32_t S, const d
     s_cnt = nsplit[lo];
   }
   double r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int32_t p = 0; p < s_cnt; ++p)
-#pragma unroll
-    for (int c = 0; c < 8; ++c) r[c] += part[((int64_t)p * 8 + c) * n + i];
+  sum_splits<8>(part, n, i, s_cnt, r);
   const auto a = jadj[2 * i];
   const auto l = jadj[2 * i + 1];
   const double m = (double)a.w;
