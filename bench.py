@@ -230,9 +230,13 @@ def main():
 
 
 def sample_sclk():
-    """Current GPU engine clock in MHz from rocm-smi (None when it cannot be read)."""
+    """Current GPU engine clock in MHz from rocm-smi (None when it cannot be read, and
+    under rocprofv3, which preloads its GPU-initialising library into every child process:
+    rocm-smi's interpreter would then be started by exec from an initialised process)."""
     import re
     import subprocess
+    if "ROCPROF_OUTPUT_PATH" in os.environ:
+        return None
     try:
         r = subprocess.run(["rocm-smi", "-g", "--json"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
                            text=True, timeout=20)

@@ -685,6 +685,13 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
   const float4 jpad = pad4<float, LAW>();
 
+  // The compensated variant with the potential keeps the low words of its compensated sums
+  // in LDS (a lane touches only its own words, once per sub-block), which takes 4I registers
+  // out of the pair loop; the arithmetic is that of the register form.
+  constexpr bool LO_LDS = COMP && POT;
+  __shared__ float lo_lds[LO_LDS ? W * NC * I * 64 : 1];
+  float* const lo_w = lo_lds + (LO_LDS ? w * NC * I * 64 + lane : 0);  // word (c, u): lo_w[(c * I + u) * 64]
+
   float xi[I], yi[I], zi[I], mi[I], xl[I], yl[I], zl[I];
   float ai[NC][I], hi[NC][I], lo[NC][I];
 #pragma unroll
@@ -704,7 +711,12 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
       zl[u] = in_vgpr(pl.z);
     }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) { ai[c][u] = 0.f; hi[c][u] = 0.f; lo[c][u] = 0.f; }
+    for (int c = 0; c < NC; ++c) {
+      ai[c][u] = 0.f;
+      hi[c][u] = 0.f;
+      if constexpr (LO_LDS) lo_w[(c * I + u) * 64] = 0.f;
+      else lo[c][u] = 0.f;
+    }
   }
 
   float4 nxt, nxtl = zero;
@@ -881,7 +893,8 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
           float s, e;
           two_sum(hi[c][u], ai[c][u], s, e);
           hi[c][u] = s;
-          lo[c][u] += e;
+          if constexpr (LO_LDS) lo_w[(c * I + u) * 64] += e;
+          else lo[c][u] += e;
           ai[c][u] = 0.f;
         }
     }
@@ -892,7 +905,9 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
     const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
     if (i < n)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) part[((int64_t)B * 4 + c) * n + i] = COMP ? hi[c][u] + lo[c][u] : ai[c][u];
+      for (int c = 0; c < NC; ++c)
+        part[((int64_t)B * 4 + c) * n + i] =
+            COMP ? hi[c][u] + (LO_LDS ? lo_w[(c * I + u) * 64] : lo[c][u]) : ai[c][u];
   }
 }
 
@@ -1527,6 +1542,14 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
   const float three = in_vgpr(3.f);
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 
+  // With 4 or more particles per lane the compensated sums (high and low words) live in LDS:
+  // a lane touches only its own words, once per sub-block, and the pair loop keeps 8I fewer
+  // registers (4 waves per SIMD at I = 4); the arithmetic is that of the register form.
+  constexpr bool HL_LDS = COMP && I >= 4;
+  __shared__ float hl_lds[HL_LDS ? W * 2 * 4 * I * 64 : 1];
+  // high word of (c, u): hl_w[(c * I + u) * 64]; low word: hl_w[((4 + c) * I + u) * 64]
+  float* const hl_w = hl_lds + (HL_LDS ? w * 2 * 4 * I * 64 + lane : 0);
+
   float xk[I], yk[I], zk[I], mk[I], lx[I], ly[I], lz[I];
   float ai[4][I], hi[4][I], lo[4][I];
 #pragma unroll
@@ -1544,7 +1567,16 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
     ly[u] = in_vgpr(l.y);
     lz[u] = in_vgpr(l.z);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) { ai[c][u] = 0.f; hi[c][u] = 0.f; lo[c][u] = 0.f; }
+    for (int c = 0; c < 4; ++c) {
+      ai[c][u] = 0.f;
+      if constexpr (HL_LDS) {
+        hl_w[(c * I + u) * 64] = 0.f;
+        hl_w[((4 + c) * I + u) * 64] = 0.f;
+      } else {
+        hi[c][u] = 0.f;
+        lo[c][u] = 0.f;
+      }
+    }
   }
 
   float4 nq = zero, nl = zero;
@@ -1663,9 +1695,16 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           float t, e;
-          two_sum(hi[c][u], ai[c][u], t, e);
-          hi[c][u] = t;
-          lo[c][u] += e;
+          if constexpr (HL_LDS) {
+            float& h = hl_w[(c * I + u) * 64];
+            two_sum(h, ai[c][u], t, e);
+            h = t;
+            hl_w[((4 + c) * I + u) * 64] += e;
+          } else {
+            two_sum(hi[c][u], ai[c][u], t, e);
+            hi[c][u] = t;
+            lo[c][u] += e;
+          }
           ai[c][u] = 0.f;
         }
     }
@@ -1676,7 +1715,12 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
     const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
     if (i < n)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) part[((int64_t)B * 4 + c) * n + i] = COMP ? hi[c][u] + lo[c][u] : ai[c][u];
+      for (int c = 0; c < 4; ++c) {
+        float v = ai[c][u];
+        if constexpr (HL_LDS) v = hl_w[(c * I + u) * 64] + hl_w[((4 + c) * I + u) * 64];
+        else if constexpr (COMP) v = hi[c][u] + lo[c][u];
+        part[((int64_t)B * 4 + c) * n + i] = v;
+      }
   }
 }
 
