@@ -927,20 +927,22 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 // law's constants; optional potential and closing half-kick.
 // n: particles of the system (partial plane stride); stride: plane stride of acc/vel.
 // a[c] += slot s of component c, s = 0 .. nb-1 in order, for the particle at offset i of
-// planes of stride n (slot s, component c at (s * 4 + c) * n). The loads of 8 slots are issued
-// before their additions, which keep the slot order (so the sum is the plain loop's).
-template <int NC>
+// planes of stride n (slot s, component c at (s * 4 + c) * n). The loads of K slots are issued
+// before their additions, which keep the slot order (so the sum is the plain loop's for any K).
+// K = 8 suits the single-system reduction (hundreds of slots per particle); kernels that hold
+// few slots per particle or share their registers with a pair loop take K = 1.
+template <int NC, int K = 8>
 __device__ __forceinline__ void sum_slots(const float* __restrict__ part, int64_t n, int64_t i, int32_t nb,
                                           double a[4]) {
   int32_t s = 0;
-  for (; s + 8 <= nb; s += 8) {
-    float v[8][NC];
+  for (; s + K <= nb; s += K) {
+    float v[K][NC];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int c = 0; c < NC; ++c) v[k][c] = part[((int64_t)(s + k) * 4 + c) * n + i];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int c = 0; c < NC; ++c) a[c] += (double)v[k][c];
   }
@@ -1011,8 +1013,8 @@ __global__ __launch_bounds__(kReduceBS) void reduce_sym_batched(int64_t n, int64
     const int32_t nb = sys_nb[s];
     const float* ps = part + sys_part[s];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    if (pot) sum_slots<4>(ps, ns, li, nb, a);
-    else sum_slots<3>(ps, ns, li, nb, a);
+    if (pot) sum_slots<4, 1>(ps, ns, li, nb, a);
+    else sum_slots<3, 1>(ps, ns, li, nb, a);
     finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
   };
   if (ef.part) {  // grid (chunks, systems)
@@ -1150,7 +1152,7 @@ __global__ __launch_bounds__(W * 64) void rollout_sym_batched_kernel(
       if (t + 1 >= steps) nxt.kind = 0;  // the last step stages nothing
       for (int64_t li = l0 + threadIdx.x; li < l1; li += W * 64) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
-        sum_slots<3>(ps, ns, li, nb, a);
+        sum_slots<3, 1>(ps, ns, li, nb, a);
         finish_particle(b + li, n, a, ls, acc, nullptr, vel, hh, nxt, nullptr, nullptr);
       }
       release_to(sy.red_done + s);
