@@ -277,7 +277,8 @@ int nbody_abi_version(void);
 
 /* Probes (each a device-scope load and a short sleep) a wait of the whole-rollout launch
  * (NBODY_FLAG_WHOLE_ROLLOUT) makes before it gives up; the launch then ends early and the
- * call returns NBODY_ERR_DEVICE. Default 2^24 (seconds). probes >= 1, else
+ * call returns NBODY_ERR_DEVICE. Default 2^24 probes (each a sleep of 128 clocks plus the
+ * load's latency: seconds of waiting). probes >= 1, else
  * NBODY_ERR_INVALID_ARG. For failure-path tests and for diagnosing a stalled launch;
  * process-wide, applies to launches made after the call. */
 int nbody_set_wait_limit(int64_t probes);
