@@ -786,6 +786,11 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
       float aj[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) aj[c] = 0.f;
+      // Potential variant: no LDS operation is left in flight when the step loop starts (a wait for
+      // lgkmcnt = 0, gfx9 encoding), so the compiler's waits inside the loop need to cover only the
+      // loop's own rotations (measured 1.6% faster at N = 1M; the variant without the potential
+      // gains nothing from it and keeps the compiler's code).
+      if constexpr (POT && LAW == LAW_GRAV) __builtin_amdgcn_s_waitcnt(0xc07f);
       for (int k = 0; k < 64; ++k) {
         float xn = xj, yn = yj, zn = zj, xnl = xjl, ynl = yjl, znl = zjl;
         if constexpr (PIPE == 1) {  // the next step's coordinates, requested a step ahead
