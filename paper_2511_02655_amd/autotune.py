@@ -115,7 +115,8 @@ def tune_force(nb, torch, precision, buckets, log, law="gravity"):
         best = _pick(cands, descs)
         lo, hi = _bounds(buckets, k, LJ_BUCKETS if law == "lj" else FORCE_BUCKETS)
         entries.append(dict(kernel=kname, precision=precision, n_min=lo, n_max=hi, variant=best[1],
-                            j_split=best[2], tuned_n=n, ms=best[0], interactions_per_s=best[3]))
+                            desc=descs[best[1]], j_split=best[2], tuned_n=n, ms=best[0],
+                            interactions_per_s=best[3]))
         nb.set_tile_table([])
     return entries
 
@@ -149,7 +150,7 @@ def tune_adjoint(nb, torch, precision, buckets, log):
                     best = (t, v, js)
         lo, hi = _bounds(buckets, k, ADJ_BUCKETS)
         entries.append(dict(kernel="adjoint", precision=precision, n_min=lo, n_max=hi, variant=best[1],
-                            j_split=best[2], tuned_n=n, ms=best[0]))
+                            desc=descs[best[1]], j_split=best[2], tuned_n=n, ms=best[0]))
         nb.set_tile_table([])
     return entries
 
@@ -164,7 +165,7 @@ def tune_batched(nb, torch, precision, log, mixes=BATCH_MIXES):
     timed inside a 10-step rollout (force) or a 10-step backward (adjoint), so the library's
     per-call host work (work-unit lists, uploads) is paid once per 10 passes as in use."""
     from . import inputs
-    results = []  # (kernel, nmax, best)
+    results = []  # (kernel, nmax, best, description of the best variant)
     for S, lo_n, hi_n, seed in mixes:
         b = inputs.batched_mix(S, seed, nmin=lo_n, nmax=hi_n)
         off = b.offsets
@@ -197,16 +198,16 @@ def tune_batched(nb, torch, precision, log, mixes=BATCH_MIXES):
                         kernel, precision, S, lo_n, hi_n, var, descs[var], jc, t))
                     if best is None or t < best[0]:
                         best = (t, var, jc)
-            results.append((kernel, nmax, best))
+            results.append((kernel, nmax, best, descs[best[1]]))
             nb.set_tile_table([])
     entries = []
     for kernel in ("force_batched", "adjoint_batched"):
-        rows = sorted([(nm, bst) for k, nm, bst in results if k == kernel])
-        sizes = [nm for nm, _ in rows]
-        for k, (nm, bst) in enumerate(rows):
+        rows = sorted([(nm, bst, d) for k, nm, bst, d in results if k == kernel])
+        sizes = [nm for nm, _, _ in rows]
+        for k, (nm, bst, d) in enumerate(rows):
             lo, hi = _bounds(sizes, k)
             entries.append(dict(kernel=kernel, precision=precision, n_min=lo, n_max=hi, variant=bst[1],
-                                j_split=bst[2], tuned_n=nm, ms=bst[0]))
+                                desc=d, j_split=bst[2], tuned_n=nm, ms=bst[0]))
     return entries
 
 

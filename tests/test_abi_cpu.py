@@ -246,6 +246,16 @@ def test_wait_limit_argument(nb):
     assert nb.lib().nbody_set_wait_limit(1 << 24) == 0
 
 
+def test_tuned_table_names_the_variants_it_was_tuned_with(nb):
+    """Every entry of the tuned table records the description of the variant it chose; the
+    index must still name that variant in this build (variant lists only ever grow at the end)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(nb.__file__), "tune", "gfx950.json")
+    for e in json.load(open(path))["entries"]:
+        assert nb.tile_variants(e["kernel"], e["precision"])[e["variant"]] == e["desc"], e
+
+
 def test_restore_tile_table(nb):
     """An empty table selects the built-in defaults; restore_tile_table reloads the tuned
     table the binding loaded at start-up."""
