@@ -272,3 +272,30 @@ def test_restore_tile_table(nb):
         assert builtin != (tuned["variant"], 1)
     finally:
         nb.restore_tile_table()
+
+
+def test_autotune_bucket_bounds_tile_the_size_axis():
+    """Tuned buckets split the particle-count axis at geometric midpoints, cover it from 0 to
+    2^40 without gaps or overlaps, and a partial re-tune keeps the standard list's ranges."""
+    from paper_2511_02655_amd import autotune as at
+    b = at.FORCE_BUCKETS
+    rng = [at._bounds(b, k) for k in range(len(b))]
+    assert rng[0][0] == 0 and rng[-1][1] == 1 << 40
+    for (lo, hi), (lo2, _) in zip(rng, rng[1:]):
+        assert lo2 == hi + 1
+    for k, n in enumerate(b):
+        assert rng[k][0] <= n <= rng[k][1]
+    assert at._bounds(b, 2) == (int((4096 * 16384) ** 0.5) + 1, int((16384 * 65536) ** 0.5))
+    # re-tuning one bucket alone against the standard list gives it the same range
+    assert at._bounds([16384], 0, b) == rng[2]
+
+
+def test_autotune_pick_prefers_larger_symmetric_blocks_within_slack():
+    """Among candidates within 1% of the fastest, the largest symmetric block wins (half the
+    partial-sum workspace per doubling); outside the slack the fastest wins."""
+    from paper_2511_02655_amd import autotune as at
+    descs = ["bs=256,i=1,tj=256", "bs=256,i=4,sym=1024,rot=lds", "bs=256,i=8,sym=2048,rot=lds,pipe"]
+    assert at._pick([(1.000, 0), (1.005, 1), (1.009, 2)], descs)[1] == 2
+    assert at._pick([(1.000, 0), (1.005, 1), (1.02, 2)], descs)[1] == 1
+    assert at._pick([(1.000, 1), (1.05, 2), (0.98, 0)], descs)[1] == 0
+    assert at._sym_edge(descs[2]) == 2048 and at._sym_edge(descs[0]) == 0
