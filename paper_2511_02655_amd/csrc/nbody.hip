@@ -468,7 +468,13 @@ struct Plan {
   size_t off_seg = 0, sz_seg = 0;
   size_t total = 0;
   int32_t e_chunks = 1;
+  int32_t e_steps = 1;  // steps whose energy partials a rollout keeps before one final sum
 };
+
+// A rollout with an energy trace sums the energy partials of up to this many steps in one
+// launch, keeping at most this many bytes of them.
+constexpr size_t kEnergySteps = 32;
+constexpr size_t kEnergyBytes = (size_t)8 << 20;
 
 struct UnitSet {
   std::vector<WorkUnit> units;     // one-sided units (i-tile x j-chunk)
@@ -675,8 +681,13 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
   const int64_t chunk_cap = std::max<int64_t>(16, 32768 / std::max<int64_t>(1, sys.S));
   int64_t chunks = std::min<int64_t>(std::max<int64_t>(1, cdiv(sys.max_n, 256)), chunk_cap);
   p.e_chunks = (int32_t)chunks;
+  // a rollout with an energy trace keeps the partials of up to kEnergySteps steps (at most
+  // kEnergyBytes) and sums them in one launch
+  const size_t step_e = (size_t)sys.S * chunks * 5 * dsz;
+  p.e_steps = (int32_t)std::max<size_t>(1, std::min<size_t>(kEnergySteps, kEnergyBytes / step_e));
   if (need & (NEED_ENERGY | NEED_ROLLOUT)) {
-    p.sz_epart = (size_t)sys.S * chunks * kDiag * dsz;  // energy (5) or diagnostics (10) partials
+    // energy (5) or diagnostics (10) partials of one state, or a rollout's kept energy partials
+    p.sz_epart = std::max((size_t)sys.S * chunks * kDiag * dsz, (size_t)p.e_steps * step_e);
     p.off_epart = take(p.sz_epart);
     p.sz_pot = (size_t)n * dsz;
     p.off_pot = take(p.sz_pot);
@@ -931,8 +942,22 @@ struct Fuse {
   const NextStep* nx = nullptr;  // the next step's kick, drift, walls and staging
   double* eout = nullptr;        // energy and momentum of the new state, [S][5] (needs pot and vel)
   const double* mass = nullptr;  // masses, with eout
+  int32_t eslot = -1;            // >= 0: leave the energy partials in kept slot eslot; the caller
+                                 // sums them later (flush_energy) instead of this pass
   bool done = false;             // set by force_pass: the pass had such a reduction and did all of it
 };
+
+// The energy rows of `count` consecutive states from the partials kept in slots 0 .. count-1:
+// out[t][S][5], one launch.
+int flush_energy(Ctx& c, int32_t count, double* out) {
+  if (count <= 0) return NBODY_OK;
+  const int32_t chunks = c.plan.e_chunks;
+  hipLaunchKernelGGL(energy_final<256>, dim3((unsigned)c.sys.S, (unsigned)count), dim3(256), 0, c.st, chunks,
+                     (const double*)(c.ws + c.plan.off_epart), out, (int64_t)c.sys.S * chunks * 5,
+                     (int64_t)c.sys.S * 5);
+  LAUNCH_CHECK("energy_final");
+  return NBODY_OK;
+}
 
 // Force pass on the staged j-array: acc = a, pot (nullable), vel += hh*acc when vel != NULL.
 // fz (nullable): work to fuse into the pass's per-particle reduction. A pass without one (a
@@ -949,7 +974,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
   if (fz) {
     nx = fz->nx;
     if (fz->eout) {
-      ef.part = (double*)(c.ws + c.plan.off_epart);
+      ef.part = (double*)(c.ws + c.plan.off_epart) + (fz->eslot > 0 ? (size_t)fz->eslot * c.sys.S * c.plan.e_chunks * 5 : 0);
       ef.mass = fz->mass;
       ef.chunks = c.plan.e_chunks;
     }
@@ -959,9 +984,9 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
   // after a reduction that carried the fused work, finish the energy sum
   auto fused_tail = [&]() -> int {
     if (!fz) return NBODY_OK;
-    if (ef.part) {
+    if (ef.part && fz->eslot < 0) {
       hipLaunchKernelGGL(energy_final<256>, dim3((unsigned)c.sys.S), dim3(256), 0, c.st, ef.chunks,
-                         (const double*)ef.part, fz->eout);
+                         (const double*)ef.part, fz->eout, (int64_t)0, (int64_t)0);
       LAUNCH_CHECK("energy_final");
     }
     fz->done = true;
@@ -1081,7 +1106,8 @@ int energy_pass(Ctx& c, const double* vel, const double* mass, const double* pot
                        dev_off, c.n, chunks, ep);
     LAUNCH_CHECK("energy_partial");
   }
-  hipLaunchKernelGGL(energy_final<256>, dim3((unsigned)c.sys.S), dim3(256), 0, c.st, chunks, ep, out);
+  hipLaunchKernelGGL(energy_final<256>, dim3((unsigned)c.sys.S), dim3(256), 0, c.st, chunks, ep, out, (int64_t)0,
+                     (int64_t)0);
   LAUNCH_CHECK("energy_final");
   return NBODY_OK;
 }
@@ -1365,6 +1391,8 @@ int rollout_impl(Ctx& c, int64_t n, double dt, int64_t steps, int64_t ckpt_every
        (!(c.cfg->flags & NBODY_FLAG_PER_PASS) && c.uf.n_solo == (int64_t)c.uf.ro_units.size())))
     return whole_rollout(c, dt, steps, pos, vel, mass, acc, nx);
   bool staged = false;  // the previous pass already ran this step's kick, drift and staging
+  int32_t kept = 0;     // fused steps whose energy partials wait in slots 0 .. kept-1
+  int64_t kept_from = 0;  // the first of them (its state is s + 1 = kept_from + 1)
   for (int64_t s = 0; s < steps; ++s) {
     if (!staged) TRY(kick_drift(c, dt, pos, vel, acc, mass));
     // the next step's first half rides on this pass unless the state at s + 1 is copied out
@@ -1375,9 +1403,21 @@ int rollout_impl(Ctx& c, int64_t n, double dt, int64_t steps, int64_t ckpt_every
     fz.nx = s + 1 < steps && !ckpt_due ? &nx : nullptr;
     fz.eout = energy_trace ? energy_trace + (s + 1) * S * 5 : nullptr;
     fz.mass = mass;
+    if (energy_trace) {
+      if (kept == 0) kept_from = s;
+      fz.eslot = kept;
+    }
     TRY(force_pass(c, acc, pot, vel, 0.5 * dt, &fz));
     staged = fz.done && fz.nx;
-    if (energy_trace && !fz.done) TRY(energy_pass(c, vel, mass, pot, fz.eout));
+    if (energy_trace) {
+      if (fz.done) ++kept;
+      // energy_pass reuses slot 0: sum what is kept first
+      if (!fz.done || kept == c.plan.e_steps || s + 1 == steps) {
+        TRY(flush_energy(c, kept, energy_trace + (kept_from + 1) * S * 5));
+        kept = 0;
+      }
+      if (!fz.done) TRY(energy_pass(c, vel, mass, pot, fz.eout));
+    }
     if (ckpt && (s + 1) % ckpt_every == 0) {
       double* slot = ckpt + (size_t)((s + 1) / ckpt_every) * 6 * n;
       TRY(copy_d2d(c, slot, pos, plane3));

@@ -1229,11 +1229,15 @@ __global__ __launch_bounds__(BS) void energy_partial(int64_t n, const double* __
     for (int c = 0; c < 5; ++c) part[(s * chunks + blockIdx.x) * 5 + c] = v[c];
 }
 
+// grid (S, T): state t of T reads its partials at part + t * part_step and writes its [S][5]
+// row at out + t * out_step.
 template <int BS>
 __global__ __launch_bounds__(BS) void energy_final(int32_t chunks, const double* __restrict__ part,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out, int64_t part_step, int64_t out_step) {
   __shared__ double sh[5 * (BS / 64)];
   const int64_t s = blockIdx.x;
+  part += (int64_t)blockIdx.y * part_step;
+  out += (int64_t)blockIdx.y * out_step;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < chunks; k += BS)
 #pragma unroll
