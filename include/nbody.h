@@ -3,9 +3,9 @@
  *
  * What is computed (per system; systems never interact):
  *   The paper's N-body miniapp evaluates the force between every pair of
- *   particles, N_p^2 pair interactions per evaluation (Sec. IV-B), moves the
+ *   particles, N_p^2 pair interactions per evaluation (Sec. V-B), moves the
  *   particles with a Verlet half-step integrator (Sec. II-A) and reduces the
- *   total energy over all particles inside the force pass (Sec. V, with and
+ *   total energy over all particles inside the force pass (Sec. VI, with and
  *   without that reduction). This library keeps that structure with
  *   Plummer-softened gravity as the pair law in place of Eq. (1):
  *       d_ij  = x_j - x_i,   s_ij = |d_ij|^2 + eps^2
@@ -122,8 +122,8 @@ int nbody_workspace_size(const nbody_config *cfg, int64_t n, int64_t steps, int6
                          size_t *bytes);
 
 /* All-pairs acceleration and, optionally, potential of every particle
- * (the force pass of Sec. IV-B; pot != NULL adds the fused per-particle
- * potential that the Sec. V energy reduction needs, pot == NULL is the
+ * (the force pass of Sec. V-B; pot != NULL adds the fused per-particle
+ * potential that the Sec. VI energy reduction needs, pot == NULL is the
  * variant without it).
  *   pos  [3][n] double, mass [n] double (any finite values; mass may be 0)
  *   acc  [3][n] double, out
@@ -152,7 +152,7 @@ int nbody_rollout(const nbody_config *cfg, int64_t n, double dt, int64_t steps, 
                   double *pos, double *vel, const double *mass, double *acc, double *ckpt,
                   double *energy_trace);
 
-/* Energy and linear momentum of every system (the energy reduction of Sec. V).
+/* Energy and linear momentum of every system (the energy reduction of Sec. VI).
  *   pot  nullable: the per-particle potential from nbody_forces (or, for the
  *        Lennard-Jones gas, from nbody_lj_forces); when NULL it is computed here
  *        with one gravity force pass at cfg->precision.

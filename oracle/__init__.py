@@ -9,7 +9,7 @@ particles, ascending-j sums with the self pair skipped); this module only
 builds that file with gcc and marshals numpy arrays through ctypes.
 
 Definitions (softened gravity in place of the paper's Lennard-Jones Eq. (1);
-all-pairs structure of Sec. IV-B; energy reduction of Sec. V; the Verlet
+all-pairs structure of Sec. V-B; energy reduction of Sec. VI; the Verlet
 half-step scheme of Sec. II-A read as kick-drift-kick):
     a_i   =  G sum_{j!=i} m_j d_ij s_ij^{-3/2},   d_ij = x_j - x_i, s_ij = |d_ij|^2 + eps^2
     phi_i = -G sum_{j!=i} m_j s_ij^{-1/2}
@@ -69,6 +69,8 @@ def _load():
     lib.oracle_kdk.restype = None
     lib.oracle_force_vjp.argtypes = [I64, P, P, D, D, P, P, P]
     lib.oracle_force_vjp.restype = None
+    lib.oracle_force_vjp_sample.argtypes = [I64, P, P, D, D, P, I64, P, P, P]
+    lib.oracle_force_vjp_sample.restype = None
     lib.oracle_rollout_adjoint.argtypes = [I64, D, D, D, I64, P, P, P, P, P, P, P, P]
     lib.oracle_rollout_adjoint.restype = None
     lib.oracle_loss_msd.argtypes = [I64, P, P, P]
@@ -158,6 +160,23 @@ def force_vjp(pos, mass, lam, G=1.0, eps=1e-2):
     gx = np.zeros((3, n))
     gm = np.zeros(n)
     _load().oracle_force_vjp(n, _p(pos), _p(mass), G, eps, _p(lam), _p(gx), _p(gm))
+    return gx, gm
+
+
+def force_vjp_sample(pos, mass, lam, idx, G=1.0, eps=1e-2):
+    """Rows idx of the force VJP: gx (3, k) and gm (k,) of particles idx (the full VJP's
+    per-particle sums, evaluated for the sample only)."""
+    mass = _f64(mass)
+    n = mass.shape[0]
+    pos = _f64(pos, (3, n))
+    lam = _f64(lam, (3, n))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    if idx.size and (idx.min() < 0 or idx.max() >= n):
+        raise IndexError("sample index out of range")
+    k = idx.shape[0]
+    gx = np.empty((3, k))
+    gm = np.empty(k)
+    _load().oracle_force_vjp_sample(n, _p(pos), _p(mass), G, eps, _p(lam), k, _p(idx), _p(gx), _p(gm))
     return gx, gm
 
 

@@ -10,10 +10,10 @@
  * per-particle sum runs over j in ascending order with j == i skipped, so the
  * result does not depend on the thread count.
  *
- * Physics. The paper's N-body miniapp (Sec. II-A, Sec. IV-B) computes the
+ * Physics. The paper's N-body miniapp (Sec. II-A, Sec. V-B) computes the
  * force between every pair of particles, N_p^2 operations per evaluation, and
  * advances positions with a Verlet half-step scheme; its total energy is a
- * reduction over all particles fused into the force pass (Sec. V). The pair
+ * reduction over all particles fused into the force pass (Sec. VI). The pair
  * law used here is Plummer-softened Newtonian gravity in place of the paper's
  * Lennard-Jones Eq. (1):
  *     d_ij  = x_j - x_i,   s_ij = |d_ij|^2 + eps^2
@@ -38,33 +38,42 @@
 
 #define EXPORT __attribute__((visibility("default")))
 
+/* Sums of one particle i against all j in [0, n), j != i, in ascending j:
+ * out = {sum m_j dx s^{-3/2}, sum m_j dy s^{-3/2}, sum m_j dz s^{-3/2}, -sum m_j s^{-1/2}}. */
+static void force_at(int64_t n, const double *pos, const double *mass, double eps2, int64_t i, double out[4])
+{
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double dx = X[j] - X[i];
+        double dy = Y[j] - Y[i];
+        double dz = Z[j] - Z[i];
+        double s = dx * dx + dy * dy + dz * dz + eps2;
+        double inv_r = 1.0 / sqrt(s);          /* s^{-1/2} */
+        double inv_r3 = inv_r / s;             /* s^{-3/2} */
+        ax += mass[j] * dx * inv_r3;
+        ay += mass[j] * dy * inv_r3;
+        az += mass[j] * dz * inv_r3;
+        ph -= mass[j] * inv_r;
+    }
+    out[0] = ax; out[1] = ay; out[2] = az; out[3] = ph;
+}
+
 /* a_i and phi_i for i in [i0, i1) against all j in [0, n), j != i.
  * acc: [3][n] (only rows i0..i1-1 written), pot: [n] or NULL. */
 static void forces_range(int64_t n, const double *pos, const double *mass, double G, double eps,
                          int64_t i0, int64_t i1, double *acc, double *pot)
 {
-    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
     const double eps2 = eps * eps;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = i0; i < i1; ++i) {
-        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            double dx = X[j] - X[i];
-            double dy = Y[j] - Y[i];
-            double dz = Z[j] - Z[i];
-            double s = dx * dx + dy * dy + dz * dz + eps2;
-            double inv_r = 1.0 / sqrt(s);          /* s^{-1/2} */
-            double inv_r3 = inv_r / s;             /* s^{-3/2} */
-            ax += mass[j] * dx * inv_r3;
-            ay += mass[j] * dy * inv_r3;
-            az += mass[j] * dz * inv_r3;
-            ph -= mass[j] * inv_r;
-        }
-        acc[i] = G * ax;
-        acc[n + i] = G * ay;
-        acc[2 * n + i] = G * az;
-        if (pot) pot[i] = G * ph;
+        double r[4];
+        force_at(n, pos, mass, eps2, i, r);
+        acc[i] = G * r[0];
+        acc[n + i] = G * r[1];
+        acc[2 * n + i] = G * r[2];
+        if (pot) pot[i] = G * r[3];
     }
 }
 
@@ -75,34 +84,22 @@ EXPORT void oracle_forces(int64_t n, const double *pos, const double *mass, doub
     forces_range(n, pos, mass, G, eps, 0, n, acc, pot);
 }
 
-/* Acceleration/potential of a chosen subset of particles against all j.
- * idx[k] names particle i; output rows are packed: acc_out [3][nidx], pot_out [nidx]. */
+/* Acceleration/potential of a chosen subset of particles against all j: the same
+ * per-particle sums as oracle_forces (force_at), so each sampled row equals the full
+ * call's row bitwise. idx[k] names particle i; output rows are packed:
+ * acc_out [3][nidx], pot_out [nidx] (nullable). */
 EXPORT void oracle_forces_sample(int64_t n, const double *pos, const double *mass, double G, double eps,
                                  int64_t nidx, const int64_t *idx, double *acc_out, double *pot_out)
 {
-    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
     const double eps2 = eps * eps;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t k = 0; k < nidx; ++k) {
-        const int64_t i = idx[k];
-        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            double dx = X[j] - X[i];
-            double dy = Y[j] - Y[i];
-            double dz = Z[j] - Z[i];
-            double s = dx * dx + dy * dy + dz * dz + eps2;
-            double inv_r = 1.0 / sqrt(s);
-            double inv_r3 = inv_r / s;
-            ax += mass[j] * dx * inv_r3;
-            ay += mass[j] * dy * inv_r3;
-            az += mass[j] * dz * inv_r3;
-            ph -= mass[j] * inv_r;
-        }
-        acc_out[k] = G * ax;
-        acc_out[nidx + k] = G * ay;
-        acc_out[2 * nidx + k] = G * az;
-        if (pot_out) pot_out[k] = G * ph;
+        double r[4];
+        force_at(n, pos, mass, eps2, idx[k], r);
+        acc_out[k] = G * r[0];
+        acc_out[nidx + k] = G * r[1];
+        acc_out[2 * nidx + k] = G * r[2];
+        if (pot_out) pot_out[k] = G * r[3];
     }
 }
 
@@ -159,39 +156,67 @@ EXPORT void oracle_kdk(int64_t n, double G, double eps, double dt, int64_t steps
  *   gm_k = -G sum_{j != k} s_kj^{-3/2} d_kj . lam_j,
  * with d_kj = x_j - x_k, s_kj = |d_kj|^2 + eps^2 and the softened tidal tensor
  *   T(d) = s^{-3/2} I - 3 s^{-5/2} d d^T  (the Jacobian of d s^{-3/2} w.r.t. d).
- * The results are ADDED into gx [3][n] and gm [n]. */
-EXPORT void oracle_force_vjp(int64_t n, const double *pos, const double *mass, double G, double eps,
-                             const double *lam, double *gx, double *gm)
+ * vjp_at: the unscaled sums of particle k, ascending j, out = {gx, gy, gz, gm}. */
+static void vjp_at(int64_t n, const double *pos, const double *mass, double eps2, const double *lam, int64_t k,
+                   double out[4])
 {
     const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
     const double *LX = lam, *LY = lam + n, *LZ = lam + 2 * n;
+    double gxx = 0.0, gxy = 0.0, gxz = 0.0, gmk = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == k) continue;
+        double dx = X[j] - X[k], dy = Y[j] - Y[k], dz = Z[j] - Z[k];
+        double s = dx * dx + dy * dy + dz * dz + eps2;
+        double inv_r = 1.0 / sqrt(s);
+        double s_m32 = inv_r / s;             /* s^{-3/2} */
+        double s_m52 = s_m32 / s;             /* s^{-5/2} */
+        /* u = m_k lam_j - m_j lam_k */
+        double ux = mass[k] * LX[j] - mass[j] * LX[k];
+        double uy = mass[k] * LY[j] - mass[j] * LY[k];
+        double uz = mass[k] * LZ[j] - mass[j] * LZ[k];
+        /* T(d) u = s^{-3/2} u - 3 s^{-5/2} d (d . u) */
+        double du = dx * ux + dy * uy + dz * uz;
+        gxx += s_m32 * ux - 3.0 * s_m52 * dx * du;
+        gxy += s_m32 * uy - 3.0 * s_m52 * dy * du;
+        gxz += s_m32 * uz - 3.0 * s_m52 * dz * du;
+        double dl = dx * LX[j] + dy * LY[j] + dz * LZ[j];
+        gmk -= s_m32 * dl;
+    }
+    out[0] = gxx; out[1] = gxy; out[2] = gxz; out[3] = gmk;
+}
+
+/* The full VJP: the results are ADDED into gx [3][n] and gm [n]. */
+EXPORT void oracle_force_vjp(int64_t n, const double *pos, const double *mass, double G, double eps,
+                             const double *lam, double *gx, double *gm)
+{
     const double eps2 = eps * eps;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < n; ++k) {
-        double gxx = 0.0, gxy = 0.0, gxz = 0.0, gmk = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == k) continue;
-            double dx = X[j] - X[k], dy = Y[j] - Y[k], dz = Z[j] - Z[k];
-            double s = dx * dx + dy * dy + dz * dz + eps2;
-            double inv_r = 1.0 / sqrt(s);
-            double s_m32 = inv_r / s;             /* s^{-3/2} */
-            double s_m52 = s_m32 / s;             /* s^{-5/2} */
-            /* u = m_k lam_j - m_j lam_k */
-            double ux = mass[k] * LX[j] - mass[j] * LX[k];
-            double uy = mass[k] * LY[j] - mass[j] * LY[k];
-            double uz = mass[k] * LZ[j] - mass[j] * LZ[k];
-            /* T(d) u = s^{-3/2} u - 3 s^{-5/2} d (d . u) */
-            double du = dx * ux + dy * uy + dz * uz;
-            gxx += s_m32 * ux - 3.0 * s_m52 * dx * du;
-            gxy += s_m32 * uy - 3.0 * s_m52 * dy * du;
-            gxz += s_m32 * uz - 3.0 * s_m52 * dz * du;
-            double dl = dx * LX[j] + dy * LY[j] + dz * LZ[j];
-            gmk -= s_m32 * dl;
-        }
-        gx[k] += G * gxx;
-        gx[n + k] += G * gxy;
-        gx[2 * n + k] += G * gxz;
-        gm[k] += G * gmk;
+        double r[4];
+        vjp_at(n, pos, mass, eps2, lam, k, r);
+        gx[k] += G * r[0];
+        gx[n + k] += G * r[1];
+        gx[2 * n + k] += G * r[2];
+        gm[k] += G * r[3];
+    }
+}
+
+/* The VJP's rows of the particles idx[0 .. nidx-1] only (the same per-particle sums as
+ * oracle_force_vjp, so each row equals the full call's bitwise when gx, gm start at 0);
+ * written (not added) packed: gx_out [3][nidx], gm_out [nidx]. */
+EXPORT void oracle_force_vjp_sample(int64_t n, const double *pos, const double *mass, double G, double eps,
+                                    const double *lam, int64_t nidx, const int64_t *idx, double *gx_out,
+                                    double *gm_out)
+{
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nidx; ++k) {
+        double r[4];
+        vjp_at(n, pos, mass, eps2, lam, idx[k], r);
+        gx_out[k] = 0.0 + G * r[0];
+        gx_out[nidx + k] = 0.0 + G * r[1];
+        gx_out[2 * nidx + k] = 0.0 + G * r[2];
+        gm_out[k] = 0.0 + G * r[3];
     }
 }
 

@@ -1,6 +1,6 @@
 // Device kernels of the all-pairs N-body hot path for gfx950 (CDNA4).
 //
-// Pair laws (all-pairs structure of Sec. IV-B), chosen at compile time (LAW):
+// Pair laws (all-pairs structure of Sec. V-B), chosen at compile time (LAW):
 //   LAW_GRAV  softened gravity: d = x_j - x_i, s = |d|^2 + eps^2,
 //             a_i = G sum_j m_j d s^{-3/2}, phi_i = -G sum_j m_j s^{-1/2};
 //   LAW_LJ    the Lennard-Jones law of Eq. (1) on coordinates staged in units of

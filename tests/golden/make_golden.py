@@ -5,8 +5,8 @@ regression anchor for the oracle and a stored expectation for the GPU tests:
 
   cube1k_oracle.txt   uniform cube, n = 1024, seed 1, G = 1, eps = 1e-2,
                       10 kick-drift-kick steps of dt = 1e-3 (the all-pairs force of
-                      Sec. IV-B with the Verlet half-step scheme of Sec. II-A and the
-                      energy reduction of Sec. V, softened gravity as the pair law).
+                      Sec. V-B with the Verlet half-step scheme of Sec. II-A and the
+                      energy reduction of Sec. VI, softened gravity as the pair law).
                       Rows for every 16th particle: initial a and phi, final x and v;
                       then the energy/momentum trace (KE, PE, Px, Py, Pz) per step.
 

@@ -358,3 +358,57 @@ def test_msd_loss_and_gradient(oracle):
     h = 1e-6
     fd = (oracle.loss_msd(x + h * d, y)[0] - oracle.loss_msd(x - h * d, y)[0]) / (2 * h)
     assert abs(fd - np.sum(grad * d)) < 1e-8
+
+
+# ---------------------------------------------------------------- sampled and batched oracle calls
+
+def test_forces_sample_equals_full_rows_bitwise(oracle):
+    """The sampled force routine returns, bitwise, the full call's rows of the sampled
+    particles (any order, repeats, first and last particle), so every check that uses a
+    sample inherits the full call's pins."""
+    pos, _, mass = _rand_system(700, 71)
+    acc, pot = oracle.forces(pos, mass, G=1.3, eps=0.02)
+    idx = np.array([699, 0, 5, 5, 350, 1, 698, 123], dtype=np.int64)
+    a_s, p_s = oracle.forces_sample(pos, mass, idx, G=1.3, eps=0.02)
+    assert a_s.shape == (3, idx.size) and p_s.shape == (idx.size,)
+    assert np.array_equal(a_s, acc[:, idx]) and np.array_equal(p_s, pot[idx])
+    a0, p0 = oracle.forces_sample(pos, mass, np.zeros(0, dtype=np.int64))
+    assert a0.shape == (3, 0) and p0.shape == (0,)
+    with pytest.raises(IndexError):
+        oracle.forces_sample(pos, mass, [700])
+
+
+def test_force_vjp_sample_equals_full_rows_bitwise(oracle):
+    """The sampled force VJP returns, bitwise, the full VJP's rows (accumulated from zero)
+    of the sampled particles."""
+    pos, _, mass = _rand_system(400, 72)
+    lam = np.random.Generator(np.random.PCG64(73)).normal(size=(3, 400))
+    gx, gm = oracle.force_vjp(pos, mass, lam, G=0.7, eps=0.05)
+    idx = np.array([399, 0, 17, 17, 200], dtype=np.int64)
+    gxs, gms = oracle.force_vjp_sample(pos, mass, lam, idx, G=0.7, eps=0.05)
+    assert np.array_equal(gxs, gx[:, idx]) and np.array_equal(gms, gm[idx])
+
+
+def test_forces_batched_is_per_system(oracle):
+    """Systems of a batch never interact: each system's rows equal, bitwise, a call on
+    that system alone (empty and single-particle systems included), and they differ from
+    the rows of the same particles evaluated as one joint system."""
+    sizes = [0, 5, 1, 0, 40, 17]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    pos, _, mass = _rand_system(n, 74)
+    acc, pot = oracle.forces_batched(pos, mass, off, eps=0.03)
+    joint, _ = oracle.forces(pos, mass, eps=0.03)
+    for k in range(len(sizes)):
+        sl = slice(off[k], off[k + 1])
+        if sizes[k] == 0:
+            continue
+        a, p = oracle.forces(pos[:, sl], mass[sl], eps=0.03)
+        assert np.array_equal(acc[:, sl], a) and np.array_equal(pot[sl], p)
+        if sizes[k] == 1:
+            assert np.all(acc[:, sl] == 0) and np.all(pot[sl] == 0)
+        else:
+            assert not np.allclose(acc[:, sl], joint[:, sl])
+    a_only, p_none = oracle.forces_batched(pos, mass, off, eps=0.03, want_pot=False)
+    assert p_none is None and np.array_equal(a_only, acc)
