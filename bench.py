@@ -318,16 +318,17 @@ def adjoint_1m_leg(nb, torch, np, pos0, mass, s, eps, prec):
 
 
 def force_errors(nb, torch, np, pos0, mass, s, eps, prec):
-    """Force error of this run's precision and of every other pair-math mode: each mode's
-    force pass (with potential) timed once and compared on every particle with the FP64 GPU
-    path; this run's mode also against the FP64 CPU oracle on a sample."""
-    import oracle
+    """Force error of every pair-math mode: each mode's force pass (without the potential)
+    timed once and compared on every particle with the FP64 GPU path; every mode's 64 worst
+    particles and a random sample also against the FP64 CPU oracle."""
     log("error leg")
     a64, p64 = nb.forces(pos0, mass, eps=eps, precision="fp64", want_pot=True)
     m = torch.sqrt((a64 ** 2).sum(0))
     rms = torch.sqrt((m ** 2).mean())
     n2 = float(s.n) ** 2
     modes = {}
+    results = {}
+    worst = set()
     for mode in ("fp32", "fp32c", "fp32ds", "fp64"):
         a32, p32 = nb.forces(pos0, mass, eps=eps, precision=mode, want_pot=True)
         torch.cuda.synchronize()
@@ -342,26 +343,43 @@ def force_errors(nb, torch, np, pos0, mass, s, eps, prec):
         e = d / torch.clamp(m, min=1e-6 * rms.item())
         modes[mode] = {"force_ms": ms, "interactions_per_s": n2 / (ms * 1e-3),
                        "pct_fp32_peak": 100.0 * FLOP_PER_INTERACTION * n2 / (ms * 1e-3) / PEAK_FP32,
-                       "max_e": float(e.max()), "p999_e": float(torch.quantile(e[::16].float(), 0.999)),
+                       "max_e": float(e.max()), "p999_e": float(torch.quantile(e.float(), 0.999)),
                        "max_abs_over_rms": float((d / rms).max()),
                        "phi_max_rel": float((torch.abs(p32 - p64) / torch.abs(p64)).max())}
-        if mode == prec:
-            mine = a32.clone()
-    g = np.random.Generator(np.random.PCG64(7))
-    idx = np.sort(g.choice(s.n, 32, replace=False))
-    ar, _ = oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
-    out = {}
-    for name, a_gpu in (("this_run_" + prec, mine), ("fp64", a64)):
-        a = a_gpu.cpu().numpy()[:, idx]
-        dd = np.sqrt(((a - ar) ** 2).sum(0))
-        mm = np.sqrt((ar ** 2).sum(0))
-        out[name] = float(np.max(dd / np.maximum(mm, 1e-6 * math.sqrt(np.mean(mm ** 2)))))
+        results[mode] = a32.cpu().numpy()
+        if mode != "fp64":
+            worst.update(torch.argsort(e)[-64:].cpu().numpy().tolist())
     return {
         "vs_fp64_gpu_all": modes[prec] if prec in modes else None,
         "modes_vs_fp64_gpu_all": modes,
-        "vs_oracle_sample32_max_e": out,
+        "vs_oracle_worst_and_sample": oracle_check(np, s, eps, {k: v for k, v in results.items()}, worst),
         "metric": "e_i = |a_i - a_i^ref| / max(|a_i^ref|, 1e-6 rms|a^ref|), all N particles unless noted",
     }
+
+
+def oracle_check(np, s, eps, results, worst, n_random=64):
+    """Each mode's worst particles (from the all-particle comparison with the FP64 GPU path)
+    plus a random sample and both ends against the CPU oracle: max e_i, and the largest ratio
+    of |da_i| to the per-particle rounding bound B_i of the FP32 pair paths."""
+    import oracle
+    from oracle import bounds
+    g = np.random.Generator(np.random.PCG64(7))
+    idx = np.unique(np.concatenate([np.asarray(sorted(worst), dtype=np.int64), g.choice(s.n, n_random, replace=False),
+                                    [0, s.n - 1]]))
+    ar, _ = oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
+    mm = np.sqrt((ar ** 2).sum(0))
+    floor = 1e-6 * math.sqrt(np.mean(mm ** 2))
+    out = {"particles": int(idx.size)}
+    for name, a_host in results.items():
+        a = a_host[:, idx]
+        dd = np.sqrt(((a - ar) ** 2).sum(0))
+        r = {"max_e": float(np.max(dd / np.maximum(mm, floor)))}
+        if name != "fp64":
+            B = bounds.fp32_force_bound(s.pos, s.mass, eps, accumulate_plain=(name == "fp32"),
+                                        exact_coords=(name == "fp32ds"), idx=idx)
+            r["max_err_over_bound"] = float(np.max(dd / B))
+        out[name] = r
+    return out
 
 
 def cube1k_leg(nb, torch, np, inputs, dev):
@@ -405,6 +423,20 @@ def plummer64k_leg(nb, torch, np, inputs, dev):
     v0 = torch.from_numpy(s.vel).to(dev)
     m = torch.from_numpy(s.mass).to(dev)
     res = {"workload": "plummer64k: Plummer N=65536, eps=1e-2, 100 KDK steps dt=1e-3"}
+    # forces at t = 0: every particle of every FP32 mode against the FP64 GPU path, and the
+    # worst particles of each against the oracle
+    a64, _ = nb.forces(x0, m, eps=W["eps"], precision="fp64")
+    mag = torch.sqrt((a64 ** 2).sum(0))
+    floor = 1e-6 * float(torch.sqrt((mag ** 2).mean()))
+    results, worst, ferr = {"fp64": a64.cpu().numpy()}, set(), {}
+    for mode in ("fp32c", "fp32ds", "fp32"):
+        a, _ = nb.forces(x0, m, eps=W["eps"], precision=mode)
+        e = torch.sqrt(((a - a64) ** 2).sum(0)) / torch.clamp(mag, min=floor)
+        ferr[mode] = {"max_e": float(e.max()), "p999_e": float(torch.quantile(e.float(), 0.999))}
+        results[mode] = a.cpu().numpy()
+        worst.update(torch.argsort(e)[-64:].cpu().numpy().tolist())
+    res["force_error_vs_fp64_gpu_all"] = ferr
+    res["force_error_vs_oracle_worst_and_sample"] = oracle_check(np, s, W["eps"], results, worst)
     finals = {}
     for mode in ("fp64", "fp32c", "fp32ds", "fp32"):
         pos, vel = x0.clone(), v0.clone()
@@ -523,9 +555,24 @@ def adjoint_leg(nb, torch, np, inputs, dev):
         fd[name] = {"fd": fdv, "adjoint_fp32c": float((g32[k] * d).sum()), "adjoint_fp64": float((g64[k] * d).sum()),
                     "rel_err_fp32c": abs(float((g32[k] * d).sum()) - fdv) / abs(fdv),
                     "rel_err_fp64": abs(float((g64[k] * d).sum()) - fdv) / abs(fdv)}
+    # the CPU oracle's discrete adjoint at the full configuration (its own FP64 forward
+    # trajectory and loss seed): rel-L2 and per particle
+    import oracle
+    log("adjoint leg: oracle gradient (full configuration)")
+    t0 = time.perf_counter()
+    xr, _, _, _ = oracle.kdk(s.pos, s.vel, s.mass, W["dt"], W["steps"], eps=W["eps"])
+    _, gxr = oracle.loss_msd(xr, inputs.gaussian_targets(s.n, W["target_seed"]))
+    ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, W["dt"], W["steps"], gxr, np.zeros_like(gxr), eps=W["eps"])
+    oracle_s = time.perf_counter() - t0
+    vs_oracle = {}
+    for pname, gg in (("fp32c", g32), ("fp64", g64)):
+        vs_oracle[pname] = {k: grad_errors(np, t.cpu().numpy(), r) for k, t, r in zip(("x0", "v0", "m"), gg, ref)}
     return {
         "workload": "merger2x8k: two Plummer spheres N=2x8192, eps=1e-2, 200 KDK steps dt=1e-3, ckpt every 20, "
                     "MSD loss to Gaussian targets; FP32 compensated",
+        "grad_vs_oracle": vs_oracle,
+        "oracle_seconds": oracle_s,
+        "oracle_threads": oracle.num_threads(),
         "forward_ms": fwd_ms,
         "backward_ms": bwd_ms,
         "adjoint_passes": adj_passes,
@@ -538,6 +585,17 @@ def adjoint_leg(nb, torch, np, inputs, dev):
         "checkpoint_bytes": int(ckpt.numel() * 8),
         "directional_vs_fp64_finite_differences": fd,
     }
+
+
+def grad_errors(np, a, b):
+    """rel-L2 of a against b and the per-particle error max_k |a_k - b_k| / max(|b_k|, f rms|b|)
+    (columns of (3, n) arrays are vectors) for the floors f = 1e-6 and 1e-3."""
+    d = np.sqrt(((a - b) ** 2).sum(0)) if b.ndim == 2 else np.abs(a - b)
+    mb = np.sqrt((b ** 2).sum(0)) if b.ndim == 2 else np.abs(b)
+    rms = math.sqrt(float(np.mean(mb ** 2)))
+    return {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            "per_particle_floor_1e-6": float(np.max(d / np.maximum(mb, 1e-6 * rms))),
+            "per_particle_floor_1e-3": float(np.max(d / np.maximum(mb, 1e-3 * rms)))}
 
 
 def batched_leg(nb, torch, np, inputs, dev):
