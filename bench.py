@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp32ds", "fp64"])
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp32ds", "fp32a", "fp64"])
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")

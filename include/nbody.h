@@ -73,8 +73,25 @@ typedef enum {
  *                    double-float coordinates (x = hi + lo, two floats), so it is
  *                    exact to the float rounding of the separation itself instead
  *                    of the coordinates; costs about 6 more float operations per
- *                    pair (adjoint passes run as NBODY_FP32_COMP). */
-typedef enum { NBODY_FP64 = 0, NBODY_FP32 = 1, NBODY_FP32_COMP = 2, NBODY_FP32_DS = 3 } nbody_precision;
+ *                    pair (adjoint passes run as NBODY_FP32_COMP).
+ *   NBODY_FP32_ADAPT as NBODY_FP32_COMP, with double-float separations only where
+ *                    they matter: a single system on symmetric tiles is ordered along a
+ *                    Morton curve on the device at every force pass (deterministic:
+ *                    unique keys), and only the 64-particle sub-block pairs whose
+ *                    bounding boxes lie within T = X_max / 256 of each other (X_max: the
+ *                    largest coordinate magnitude) take double-float separations; every
+ *                    other pair is at least T apart, so its float separation errs by at
+ *                    most 2 u X_max / T < 3.1e-5 relative. Results come back in the
+ *                    caller's order. Other paths (batches, one-sided small-n passes) run
+ *                    as NBODY_FP32_DS; adjoint passes as NBODY_FP32_COMP. A rollout with
+ *                    an energy trace reduces the energy in a separate pass. */
+typedef enum {
+  NBODY_FP64 = 0,
+  NBODY_FP32 = 1,
+  NBODY_FP32_COMP = 2,
+  NBODY_FP32_DS = 3,
+  NBODY_FP32_ADAPT = 4
+} nbody_precision;
 
 /* config.flags */
 #define NBODY_FLAG_LOOP_SYSTEMS 1u /* batched calls: one plain launch per system

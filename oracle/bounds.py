@@ -32,13 +32,20 @@ import numpy as np
 U32 = 2.0 ** -24
 
 
-def fp32_force_bound(pos, mass, eps, G=1.0, accumulate_plain=False, exact_coords=False, idx=None, chunk=512):
-    """B_i of every particle (idx None) or of the particles idx, against all j != i."""
+def fp32_force_bound(pos, mass, eps, G=1.0, accumulate_plain=False, exact_coords=False, idx=None, chunk=512,
+                     adaptive=False):
+    """B_i of every particle (idx None) or of the particles idx, against all j != i.
+
+    adaptive: the adaptive-separation mode. Every pair closer than T = X_max / 256 (X_max the
+    largest coordinate magnitude) lies in sub-blocks whose boxes are closer than T, so it takes
+    double-float separations (43 |d|); a pair at least T apart may take float separations, so it
+    keeps the coordinate term (the larger of the two)."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     mass = np.ascontiguousarray(mass, dtype=np.float64)
     n = mass.shape[0]
     rows = np.arange(n) if idx is None else np.asarray(idx, dtype=np.int64)
     xn = np.sqrt(np.sum(pos ** 2, axis=0))
+    T = np.max(np.abs(pos)) / 256.0 if n else 0.0
     B = np.empty(rows.shape[0])
     # keep the temporaries near chunk * n doubles
     step = max(1, min(chunk, (1 << 24) // max(n, 1)))
@@ -51,6 +58,9 @@ def fp32_force_bound(pos, mass, eps, G=1.0, accumulate_plain=False, exact_coords
         w[np.arange(r.shape[0]), r] = 0.0  # the self pair adds exactly 0 on the GPU (d = 0)
         if exact_coords:
             k = 43.0 * dn
+        elif adaptive:
+            far = dn >= 0.999 * T  # box distances are taken on float coordinates
+            k = np.where(far, 2 * math.sqrt(3.0) * (xn[r, None] + xn[None, :]) + 41.0 * dn, 43.0 * dn)
         else:
             k = 2 * math.sqrt(3.0) * (xn[r, None] + xn[None, :]) + (41 + (math.sqrt(n) if accumulate_plain else 0)) * dn
         B[k0:k0 + step] = U32 * G * np.sum(w * k, axis=1)

@@ -23,7 +23,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libnbody.so")
 
 NBODY_ABI_VERSION = 1
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32ds": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "fp32ds": 3, "fp32a": 4}
 KERNELS = {"force": 0, "adjoint": 1, "force_batched": 2, "adjoint_batched": 3, "lj_force": 4,
            "lj_force_batched": 5}
 FLAG_LOOP_SYSTEMS = 1

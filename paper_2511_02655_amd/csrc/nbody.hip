@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "nbody.h"
+#include "nbody_adapt.hpp"
 #include "nbody_kernels.hpp"
 
 using namespace nbody;
@@ -142,10 +143,18 @@ const AdjVariant kAdj64[] = {AV64(256, 1, 256), AV64(128, 1, 128), AV64(64, 1, 6
 // Symmetric FP32 force variants (each pair once), indices kNumForce32 + k in the
 // FORCE tile table.
 using SymFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part);
+using SymAdaptFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part,
+                            const AdaptIn& ad);
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 void launch_sym(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part) {
   hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE, ROT, LAW, PIPE>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2,
-                     part);
+                     part, AdaptIn{});
+}
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
+void launch_sym_adapt(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, float eps2, float* part,
+                      const AdaptIn& ad) {
+  hipLaunchKernelGGL((force_sym_kernel<W, I, POT, MODE, ROT, LAW, PIPE>), g, dim3(W * 64), 0, st, jarr, n, nb, eps2,
+                     part, ad);
 }
 using SymBatchedFn = void (*)(dim3, hipStream_t, const float4* jarr, const SymUnit* units, int32_t n_units,
                               float eps2, float* part);
@@ -174,6 +183,8 @@ struct SymVariant {
   int w, i, rot;      // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
   int pipe;           // coordinate rotation issued after phase 1 (0) or a step ahead (1)
   SymFn fn[2][2][3];  // [law][pot][mode]
+  SymAdaptFn afn[2][2];  // [law][pot]: the adaptive mode's off-diagonal tiles (single systems)
+  SymAdaptFn dfn[2][2];  // [law][pot]: its diagonal tiles
   SymBatchedFn bfn[2][2][3];
   RolloutFn rfn[2][3];  // whole batched rollout [law][mode] (no potential)
   const void* (*rptr[2][3])();
@@ -185,8 +196,13 @@ struct SymVariant {
    {SV32_POT(F, W, I, R, P, false, 1), SV32_POT(F, W, I, R, P, true, 1)}}
 #define SV32_RO(F, W, I, R, P, LAW) \
   { F<W, I, 0, R, LAW, P>, F<W, I, 1, R, LAW, P>, F<W, I, 2, R, LAW, P> }
+#define SV32_AD(W, I, R, P, M)                                                                             \
+  {{launch_sym_adapt<W, I, false, M, R, 0, P>, launch_sym_adapt<W, I, true, M, R, 0, P>},                  \
+   {launch_sym_adapt<W, I, false, M, R, 1, P>, launch_sym_adapt<W, I, true, M, R, 1, P>}}
 #define SV32P(W, I, R, P)                                                                                  \
-  SymVariant { W, I, R, P, SV32_ALL(launch_sym, W, I, R, P), SV32_ALL(launch_sym_batched, W, I, R, P),   \
+  SymVariant { W, I, R, P, SV32_ALL(launch_sym, W, I, R, P), SV32_AD(W, I, R, P, MODE_ADAPT),              \
+               SV32_AD(W, I, R, P, MODE_ADAPT_DIAG),                                                       \
+               SV32_ALL(launch_sym_batched, W, I, R, P),                                                   \
                {SV32_RO(launch_rollout, W, I, R, P, 0), SV32_RO(launch_rollout, W, I, R, P, 1)},          \
                {SV32_RO(rollout_ptr, W, I, R, P, 0), SV32_RO(rollout_ptr, W, I, R, P, 1)} }
 #define SV32(W, I, R) SV32P(W, I, R, 0)
@@ -227,11 +243,15 @@ constexpr int kNumAdj32 = sizeof(kAdj32) / sizeof(kAdj32[0]);
 constexpr int kNumAdj64 = sizeof(kAdj64) / sizeof(kAdj64[0]);
 
 bool is_fp64(int prec) { return prec == NBODY_FP64; }
-bool is_ds(int prec) { return prec == NBODY_FP32_DS; }
+bool is_adapt(int prec) { return prec == NBODY_FP32_ADAPT; }
+// double-float j-array layout (two float4 per particle): the double-float mode, and the
+// adaptive mode wherever it runs as the double-float mode (batches, one-sided passes)
+bool is_ds(int prec) { return prec == NBODY_FP32_DS || prec == NBODY_FP32_ADAPT; }
 // force-kernel mode index: 0 plain float / double, 1 compensated, 2 double-float separations
-int force_mode(int prec) { return prec == NBODY_FP32_COMP ? 1 : prec == NBODY_FP32_DS ? 2 : 0; }
-// adjoint kernels: compensated for both compensated modes
-int adj_comp(int prec) { return prec == NBODY_FP32_COMP || prec == NBODY_FP32_DS; }
+// (the adaptive mode's own symmetric path is launched separately)
+int force_mode(int prec) { return prec == NBODY_FP32_COMP ? 1 : is_ds(prec) ? 2 : 0; }
+// adjoint kernels: compensated for every compensated mode
+int adj_comp(int prec) { return prec == NBODY_FP32_COMP || is_ds(prec); }
 // bytes of one particle in the force j-array and in the adjoint j-array
 size_t jvec_bytes(int prec) { return is_fp64(prec) ? 32 : is_ds(prec) ? 32 : 16; }
 size_t jadj_bytes(int prec) { return is_fp64(prec) ? 64 : 32; }
@@ -362,9 +382,14 @@ bool find_entry(int kernel, int prec, int64_t n, Tile& out);
 
 Tile lookup_tile(int kernel, int prec, int64_t n) {
   Tile t;
-  if (find_entry(kernel, prec, n, t)) return t;
-  // a Lennard-Jones kernel without its own entry runs with the gravity kernel's tile
-  if (base_kernel(kernel) != kernel && find_entry(base_kernel(kernel), prec, n, t)) return t;
+  // the adaptive mode without entries of its own runs with the compensated mode's tiles (its
+  // float loop is the compensated one)
+  for (int p : {prec, is_adapt(prec) ? (int)NBODY_FP32_COMP : -1}) {
+    if (p < 0) continue;
+    if (find_entry(kernel, p, n, t)) return t;
+    // a Lennard-Jones kernel without its own entry runs with the gravity kernel's tile
+    if (base_kernel(kernel) != kernel && find_entry(base_kernel(kernel), p, n, t)) return t;
+  }
   return default_tile(kernel, prec, n);
 }
 
@@ -413,7 +438,7 @@ int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys, bool law_checks 
     return fail(NBODY_ERR_INVALID_ARG, "abi_version %d does not match library ABI %d", cfg->abi_version,
                 NBODY_ABI_VERSION);
   if (cfg->precision != NBODY_FP64 && cfg->precision != NBODY_FP32 && cfg->precision != NBODY_FP32_COMP &&
-      cfg->precision != NBODY_FP32_DS)
+      cfg->precision != NBODY_FP32_DS && cfg->precision != NBODY_FP32_ADAPT)
     return fail(NBODY_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
   if (law_checks) {
     if (!std::isfinite(cfg->G)) return fail(NBODY_ERR_INVALID_ARG, "G must be finite");
@@ -466,6 +491,12 @@ struct Plan {
   size_t off_accs = 0, sz_accs = 0;   // scratch acc [3][n]
   size_t off_xw = 0, off_vw = 0, off_aw = 0, sz_state = 0;
   size_t off_seg = 0, sz_seg = 0;
+  // adaptive mode (single system on symmetric tiles): sort keys, permutation, sub-block
+  // boxes, bounding-box partials and the box with T^2
+  bool adapt = false;
+  int64_t adapt_padded = 0;
+  int32_t adapt_bblocks = 0;
+  size_t off_keys = 0, off_perm = 0, off_box = 0, off_bbpart = 0, off_bbox = 0;
   size_t total = 0;
   int32_t e_chunks = 1;
   int32_t e_steps = 1;  // steps whose energy partials a rollout keeps before one final sum
@@ -675,6 +706,20 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
   p.off_jbuf = take(p.sz_jbuf);
   p.sz_part = std::max(force_part, adj_part);
   p.off_part = take(p.sz_part);
+  // the adaptive mode sorts a single system whose force pass runs on symmetric tiles
+  p.adapt = is_adapt(prec) && !bat && n > 0 &&
+            (lookup_tile(NBODY_KERNEL_FORCE, prec, n).sym >= 0 || lookup_tile(NBODY_KERNEL_LJ_FORCE, prec, n).sym >= 0);
+  if (p.adapt) {
+    int64_t P = kBitonicLocal;
+    while (P < n) P <<= 1;
+    p.adapt_padded = P;
+    p.adapt_bblocks = (int32_t)std::min<int64_t>(cdiv(n, kAdaptBS), 1024);
+    p.off_keys = take((size_t)P * sizeof(uint64_t));
+    p.off_perm = take((size_t)n * sizeof(uint32_t));
+    p.off_box = take((size_t)cdiv(n, kSub) * 2 * sizeof(float4));
+    p.off_bbpart = take((size_t)p.adapt_bblocks * 6 * sizeof(double));
+    p.off_bbox = take(8 * sizeof(double));
+  }
   // energy partials: chunks of 256 threads per system, about one particle per thread (the
   // energy can ride on a per-particle reduction, which needs that parallelism), with at most
   // max(16 S, 32768) chunks in all
@@ -739,6 +784,11 @@ struct Ctx {
   double eps2 = 0.0;  // softening^2 in staged units
   LawScale ls{};      // constants applied to the raw pair sums (mdiv set per call)
   Walls wl{};
+  // adaptive mode on symmetric tiles: the force pass sorts and stages the positions itself,
+  // from the state the last staging call named
+  bool adapt = false;
+  const double* src_pos = nullptr;
+  const double* src_mass = nullptr;
 
   LawScale ls_at(int64_t b) const {
     LawScale r = ls;
@@ -778,6 +828,7 @@ int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsi
   c.bat = c.sys.S > 1;
   c.loop = c.bat && (cfg->flags & NBODY_FLAG_LOOP_SYSTEMS);
   TRY(make_plan(cfg, c.sys, n, ckpt_every, need, c.plan, &c.uf, &c.ua, c.law));
+  c.adapt = c.plan.adapt && lookup_tile(force_kernel_id(c.law, false), cfg->precision, n).sym >= 0;
   if (n == 0) return NBODY_OK;
   if (!cfg->workspace) return fail(NBODY_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", c.plan.total);
   if (((uintptr_t)cfg->workspace) % kAlign)
@@ -874,6 +925,9 @@ inline dim3 grid1d(int64_t n, int bs = 256) { return dim3((unsigned)cdiv(std::ma
 // ------------------------------------------------------------------ passes
 
 int stage(Ctx& c, const double* pos, const double* mass) {
+  c.src_pos = pos;
+  c.src_mass = mass;
+  if (c.adapt) return NBODY_OK;  // sorted and staged by the force pass
   TRY(check_jbuf(c, jvec_bytes(c.cfg->precision), "stage_j"));
   void* j = c.ws + c.plan.off_jbuf;
   if (is_fp64(c.cfg->precision))
@@ -888,7 +942,9 @@ int stage(Ctx& c, const double* pos, const double* mass) {
 
 int kick_drift(Ctx& c, double dt, double* pos, double* vel, const double* acc, const double* mass) {
   TRY(check_jbuf(c, jvec_bytes(c.cfg->precision), "kick_drift_stage"));
-  void* j = c.ws + c.plan.off_jbuf;
+  c.src_pos = pos;
+  c.src_mass = mass;
+  void* j = c.adapt ? nullptr : c.ws + c.plan.off_jbuf;  // adaptive: staged in sorted order by the force pass
   if (is_fp64(c.cfg->precision))
     hipLaunchKernelGGL((kick_drift_stage<double, false>), grid1d(c.n), dim3(256), 0, c.st, c.n, 0.5 * dt, dt, pos, vel,
                        acc, mass, c.xs, c.wl, (D4*)j);
@@ -915,7 +971,7 @@ int persistent_grid(const void* kfn, int bs, int64_t units, unsigned& grid) {
 NextStep next_step(const Ctx& c, double dt, double* pos, const double* mass) {
   NextStep nx{};
   const int prec = c.cfg->precision;
-  nx.kind = is_fp64(prec) ? 2 : is_ds(prec) ? 3 : 1;
+  nx.kind = is_fp64(prec) ? 2 : c.adapt ? 4 : is_ds(prec) ? 3 : 1;
   nx.pos = pos;
   nx.mass = mass;
   nx.hh = 0.5 * dt;
@@ -959,6 +1015,71 @@ int flush_energy(Ctx& c, int32_t count, double* out) {
   return NBODY_OK;
 }
 
+// The adaptive mode's symmetric pass over the single system (n particles) at the positions the
+// last staging call named: bounding box and threshold, Morton keys, bitonic sort, sorted
+// staging with sub-block boxes, the tile kernel, and the per-particle reduction in sorted
+// order that writes every output at the particle's own index.
+template <typename Tail>
+int adapt_sym_pass(Ctx& c, const Tile& t, double* acc, double* pot, double* vel, double hh, const NextStep* nx,
+                   Tail&& tail) {
+  const int64_t n = c.n;
+  if (!c.src_pos || !c.src_mass) return fail(NBODY_ERR_DEVICE, "internal: adaptive pass without staged positions");
+  if (n > 0xffffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "the adaptive mode sorts at most 2^32 particles");
+  const SymVariant& sv = kSym32[t.sym];
+  const int64_t nb = cdiv(n, (int64_t)t.tj);
+  const int64_t off_tiles = nb * (nb - 1) / 2;  // off-diagonal tiles (the diagonal ones launch apart)
+  if (off_tiles > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many symmetric tiles");
+  TRY(check_part(c, (size_t)nb * 4 * n * sizeof(float), "force_sym_kernel (adaptive)"));
+  TRY(check_jbuf(c, 2 * sizeof(float4), "adapt_stage"));
+  const Plan& pl = c.plan;
+  if (!pl.adapt) return fail(NBODY_ERR_DEVICE, "internal: adaptive pass without its workspace");
+  uint64_t* keys = (uint64_t*)(c.ws + pl.off_keys);
+  uint32_t* perm = (uint32_t*)(c.ws + pl.off_perm);
+  float4* box = (float4*)(c.ws + pl.off_box);
+  double* bbox = (double*)(c.ws + pl.off_bbox);
+  float4* jhi = (float4*)(c.ws + pl.off_jbuf);
+  float4* jlo = jhi + n;
+  const int64_t P = pl.adapt_padded;
+  hipLaunchKernelGGL(adapt_bbox_partial, dim3((unsigned)pl.adapt_bblocks), dim3(kAdaptBS), 0, c.st, n, c.src_pos,
+                     (double*)(c.ws + pl.off_bbpart));
+  LAUNCH_CHECK("adapt_bbox_partial");
+  hipLaunchKernelGGL(adapt_bbox_final, dim3(1), dim3(kAdaptBS), 0, c.st, pl.adapt_bblocks,
+                     (const double*)(c.ws + pl.off_bbpart), c.xs, bbox);
+  LAUNCH_CHECK("adapt_bbox_final");
+  hipLaunchKernelGGL(adapt_keys, grid1d(P, kAdaptBS), dim3(kAdaptBS), 0, c.st, n, P, c.src_pos, (const double*)bbox,
+                     keys);
+  LAUNCH_CHECK("adapt_keys");
+  const unsigned lblocks = (unsigned)(P / kBitonicLocal);
+  hipLaunchKernelGGL(bitonic_local, dim3(lblocks), dim3(kBitonicBS), 0, c.st, keys);
+  LAUNCH_CHECK("bitonic_local");
+  for (int64_t k = 2 * (int64_t)kBitonicLocal; k <= P; k <<= 1) {
+    for (int64_t j = k >> 1; j >= kBitonicLocal; j >>= 1) {
+      hipLaunchKernelGGL(bitonic_global, grid1d(P / 2, kAdaptBS), dim3(kAdaptBS), 0, c.st, keys, P, k, j);
+      LAUNCH_CHECK("bitonic_global");
+    }
+    hipLaunchKernelGGL(bitonic_merge_local, dim3(lblocks), dim3(kBitonicBS), 0, c.st, keys, k);
+    LAUNCH_CHECK("bitonic_merge_local");
+  }
+  hipLaunchKernelGGL(adapt_stage, grid1d(cdiv(n, kSub) * kSub, kAdaptBS), dim3(kAdaptBS), 0, c.st, n,
+                     (const uint64_t*)keys, c.src_pos, c.src_mass, c.xs, perm, jhi, jlo, box);
+  LAUNCH_CHECK("adapt_stage");
+  float* pf = (float*)(c.ws + pl.off_part);
+  AdaptIn ad;
+  ad.jlo = jlo;
+  ad.box = box;
+  ad.thr = bbox + 6;
+  sv.dfn[c.law][pot != nullptr](dim3((unsigned)nb), c.st, jhi, n, (int32_t)nb, (float)c.eps2, pf, ad);
+  LAUNCH_CHECK("force_sym_kernel (adaptive, diagonal tiles)");
+  if (off_tiles > 0) {
+    sv.afn[c.law][pot != nullptr](dim3((unsigned)off_tiles), c.st, jhi, n, (int32_t)nb, (float)c.eps2, pf, ad);
+    LAUNCH_CHECK("force_sym_kernel (adaptive)");
+  }
+  hipLaunchKernelGGL(reduce_sym, grid1d(n), dim3(kReduceBS), 0, c.st, n, n, (int32_t)nb, (const float*)pf, c.ls, acc,
+                     pot, vel, hh, nx ? *nx : NextStep{}, EnergyFuse{}, (const uint32_t*)perm);
+  LAUNCH_CHECK("reduce_sym");
+  return tail();
+}
+
 // Force pass on the staged j-array: acc = a, pot (nullable), vel += hh*acc when vel != NULL.
 // fz (nullable): work to fuse into the pass's per-particle reduction. A pass without one (a
 // one-sided pass that writes accelerations directly) or the per-system loop fuses nothing and
@@ -970,6 +1091,9 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
     fz->done = false;
     if (c.loop || !vel || (fz->eout && (!pot || !fz->mass))) fz = nullptr;  // all systems or none; the
                                                                           // kick needs the velocities
+    // the adaptive mode's reduction runs in sorted order, so its energy sums would not be those
+    // of the separate energy pass: a traced step reduces its energy separately
+    if (fz && c.adapt && fz->eout) fz = nullptr;
   }
   if (fz) {
     nx = fz->nx;
@@ -1005,6 +1129,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
     const int64_t ns = e - b;
     if (ns == 0) return NBODY_OK;
     Tile t = lookup_tile(force_kernel_id(law, false), prec, ns);
+    if (t.sym >= 0 && c.adapt) return adapt_sym_pass(c, t, acc, pot, vel, hh, nx, fused_tail);
     if (t.sym >= 0) {
       const SymVariant& sv = kSym32[t.sym];
       const int64_t nb = cdiv(ns, (int64_t)t.tj);
@@ -1017,7 +1142,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
       LAUNCH_CHECK("force_sym_kernel");
       hipLaunchKernelGGL(reduce_sym, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n, (int32_t)nb, (const float*)pf,
                          c.ls_at(b), acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh,
-                         next_step_at(c, nx, b), ef);
+                         next_step_at(c, nx, b), ef, (const uint32_t*)nullptr);
       LAUNCH_CHECK("reduce_sym");
       return fused_tail();
     }
@@ -1616,7 +1741,7 @@ __attribute__((visibility("default"))) int nbody_set_tile_table(const nbody_tile
   for (int64_t k = 0; k < count; ++k) {
     const auto& e = entries[k];
     if (e.kernel < 0 || e.kernel >= kNumKernels) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad kernel", (long long)k);
-    if (e.precision < 0 || e.precision > 3) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad precision", (long long)k);
+    if (e.precision < 0 || e.precision > 4) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad precision", (long long)k);
     if (e.variant < 0 || e.variant >= num_variants(e.kernel, e.precision))
       return fail(NBODY_ERR_INVALID_ARG, "entry %lld: variant %d out of range", (long long)k, e.variant);
     if (e.j_split < 1 || e.n_min > e.n_max) return fail(NBODY_ERR_INVALID_ARG, "entry %lld: bad range/j_split", (long long)k);
@@ -1629,7 +1754,7 @@ __attribute__((visibility("default"))) int nbody_set_tile_table(const nbody_tile
 __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, int32_t precision, char* buf,
                                                                size_t cap) {
   g_err.clear();
-  if (kernel < 0 || kernel >= kNumKernels || precision < 0 || precision > 3) {
+  if (kernel < 0 || kernel >= kNumKernels || precision < 0 || precision > 4) {
     fail(NBODY_ERR_INVALID_ARG, "bad kernel/precision");
     return -1;
   }
@@ -1658,7 +1783,7 @@ __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, i
 __attribute__((visibility("default"))) int nbody_tile_lookup(int32_t kernel, int32_t precision, int64_t n,
                                                              int32_t* variant, int32_t* j_split) {
   g_err.clear();
-  if (kernel < 0 || kernel >= kNumKernels || precision < 0 || precision > 3 || !variant || !j_split)
+  if (kernel < 0 || kernel >= kNumKernels || precision < 0 || precision > 4 || !variant || !j_split)
     return fail(NBODY_ERR_INVALID_ARG, "bad arguments");
   Tile t = lookup_tile(kernel, precision, n);
   *variant = t.variant;

@@ -75,9 +75,10 @@ __global__ __launch_bounds__(kAdaptBS) void adapt_bbox_partial(int64_t n, const 
 
 // The bounding box from `blocks` partials (min and max are exact, so any order gives the
 // same box), and the threshold: bbox[0..5] = box, bbox[6] = T^2 (as a double) with
-// T = X_max / 256, X_max = the largest coordinate magnitude. One block of kAdaptBS threads.
+// T = X_max / 256, X_max = the largest coordinate magnitude, in staged units (coordinates
+// times xs). One block of kAdaptBS threads.
 __global__ __launch_bounds__(kAdaptBS) void adapt_bbox_final(int32_t blocks, const double* __restrict__ part,
-                                                             double* __restrict__ bbox) {
+                                                             double xs, double* __restrict__ bbox) {
   __shared__ double sh[6][kAdaptBS];
   const double inf = __builtin_inf();
   double v[6] = {inf, inf, inf, -inf, -inf, -inf};
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(kAdaptBS) void adapt_bbox_final(int32_t blocks, con
       bbox[c] = sh[c][0];
       xmax = fmax(xmax, fabs(sh[c][0]));
     }
-    const double t = xmax * (1.0 / 256.0);
+    const double t = xmax * xs * (1.0 / 256.0);
     bbox[6] = t * t;
   }
 }

@@ -50,6 +50,14 @@ __device__ __forceinline__ float in_vgpr(float x) {
   return r;
 }
 
+// An opaque copy of an int: address arithmetic built on it stays where it is written (the
+// compiler cannot hoist it out of a branch into registers held across a whole loop).
+__device__ __forceinline__ int opaque_int(int x) {
+  int r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 __device__ __forceinline__ double in_vgpr(double x) {
   double r;
   asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "v"(x));
@@ -184,7 +192,8 @@ struct Walls {
 };
 
 // First half of a KDK step fused with the staging of the new positions:
-//   v += hh a;  x += h v;  (walls);  jarr = (xs x, m) in pair precision.
+//   v += hh a;  x += h v;  (walls);  jarr = (xs x, m) in pair precision (jarr == nullptr:
+//   no staging; the adaptive mode stages in sorted order at its next force pass).
 template <typename T, bool DS>
 __global__ void kick_drift_stage(int64_t n, double hh, double h, double* __restrict__ pos,
                                  double* __restrict__ vel, const double* __restrict__ acc,
@@ -210,7 +219,7 @@ __global__ void kick_drift_stage(int64_t n, double hh, double h, double* __restr
     pos[c * n + i] = xc;
     x[c] = xc;
   }
-  put_j<T, DS>(jarr, i, x, mass[i], xs);
+  if (jarr) put_j<T, DS>(jarr, i, x, mass[i], xs);
 }
 
 // Constants of the pair law applied to the kernels' raw sums:
@@ -228,7 +237,8 @@ __device__ __forceinline__ double law_div(const LawScale& ls, int64_t i) { retur
 // v += hh a of step n, the opening kick v += hh a of step n+1, the drift x += h v, the
 // walls and the staging of x into the j-array - the same operations in the same order
 // as kick_drift_stage, so trajectories are bitwise those of the unfused loop.
-// kind: 0 none, 1 float j-array, 2 double, 3 double-float (two float4 per particle).
+// kind: 0 none, 1 float j-array, 2 double, 3 double-float (two float4 per particle),
+// 4 kick and drift without staging.
 struct NextStep {
   int32_t kind;
   int32_t pad;
@@ -262,7 +272,8 @@ __device__ __forceinline__ void next_step_tail(const NextStep& ns, int64_t i, in
   }
   if (ns.kind == 1) put_j<float, false>((float4*)ns.jarr, i, x, ns.mass[i], ns.xs);
   else if (ns.kind == 2) put_j<double, false>((D4*)ns.jarr, i, x, ns.mass[i], ns.xs);
-  else put_j<float, true>((float4*)ns.jarr, i, x, ns.mass[i], ns.xs);
+  else if (ns.kind == 3) put_j<float, true>((float4*)ns.jarr, i, x, ns.mass[i], ns.xs);
+  // kind 4: no staging (the adaptive mode stages in sorted order before its next pass)
 }
 
 // Block-wide sum of K doubles per thread in a fixed order (wave64 shuffle tree, then the
@@ -433,9 +444,23 @@ struct ForceOut {
   int64_t n_plane;
 };
 
-// Pair-math modes of the FP32 kernels: plain float sums, compensated sums, and
-// compensated sums with double-float separations.
-enum { MODE_PLAIN = 0, MODE_COMP = 1, MODE_DS = 2 };
+// Pair-math modes of the FP32 kernels: plain float sums, compensated sums, compensated
+// sums with double-float separations, and (symmetric single-system tiles only) compensated
+// sums with double-float separations where two sub-blocks are near (the adaptive mode:
+// MODE_ADAPT for the off-diagonal tiles, MODE_ADAPT_DIAG for the diagonal ones, which are
+// launched separately so that the double-float diagonal loop does not raise the register
+// count, and so lower the occupancy, of the off-diagonal kernel).
+enum { MODE_PLAIN = 0, MODE_COMP = 1, MODE_DS = 2, MODE_ADAPT = 3, MODE_ADAPT_DIAG = 4 };
+
+// Inputs of the adaptive mode, all in sorted order (see nbody_adapt.hpp): the low words of
+// the double-float coordinates, the bounding box of every 64-particle sub-block
+// (box[2q] = min corner, box[2q + 1] = max corner) and T^2, the squared box distance below
+// which two sub-blocks take double-float separations.
+struct AdaptIn {
+  const float4* jlo;
+  const float4* box;
+  const double* thr;
+};
 
 // One block's work: i in [ib, ie) (ie - ib <= BS*I) against j in [jb, je).
 // Returns the unscaled sums of every component in res[c][u] (c = ax, ay, az, phi).
@@ -666,18 +691,33 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 // PIPE chooses when a step's j coordinates are rotated: 0 right after they are consumed
 // (phase 1), 1 at the top of the step, a whole step ahead of their use. Both compute the
 // same values; which schedules better depends on the variant (measured by the tuner).
+//
+// Adaptive mode (particles in Morton order): every off-diagonal (wave, sub-block) iteration
+// whose i- and j-sub-block boxes lie within T of each other (a bit of the wave's near mask,
+// one ballot per tile; MODE_ADAPT) and every diagonal tile (MODE_ADAPT_DIAG) form their
+// separations from double-float coordinates, (hi_j - hi_i) + (lo_j - lo_i); all other
+// iterations run the compensated float loop unchanged (its low words in LDS, as in the
+// potential variant). The double-float loops take part of a lane's i-particles at a time
+// (the j-particles come home after 64 steps), so they need no more registers than the float
+// loop.
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE = 0>
 __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_t n, int32_t A, int32_t B,
                                          float eps2_arg, float* __restrict__ part,
-                                         float (&red)[2][W][POT ? 4 : 3][64]) {
+                                         float (&red)[2][W][POT ? 4 : 3][64], AdaptIn ad = AdaptIn{}) {
   constexpr bool COMP = MODE != MODE_PLAIN;
   constexpr bool DS = MODE == MODE_DS;
+  constexpr bool ADAPT_OFF = MODE == MODE_ADAPT;        // adaptive, off-diagonal tiles only
+  constexpr bool ADAPT_DIAG = MODE == MODE_ADAPT_DIAG;  // adaptive, diagonal tiles only
+  constexpr bool ADAPT = ADAPT_OFF || ADAPT_DIAG;
+  static_assert(!ADAPT || I % 2 == 0, "the adaptive double-float loops take part of the i-particles at a time");
+  constexpr int IH = I / 2 > 0 ? I / 2 : 1;   // i-particles per off-diagonal double-float pass
+  constexpr int IHD = I / 4 > 0 ? I / 4 : 1;  // i-particles per diagonal pass
   constexpr int NV = DS ? 2 : 1;
   constexpr int BI = W * 64 * I;
   constexpr int NC = POT ? 4 : 3;
   constexpr int NSUB = BI / 64;
 
-  const bool diag = (A == B);
+  const bool diag = ADAPT_DIAG ? true : ADAPT_OFF ? false : (A == B);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rot_src = ((lane - 1) & 63) << 2;  // rotation source lane (byte address) for ROT = 1
   const int64_t Abase = (int64_t)A * BI, Bbase = (int64_t)B * BI;
@@ -688,7 +728,7 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
   // The compensated variant with the potential keeps the low words of its compensated sums
   // in LDS (a lane touches only its own words, once per sub-block), which takes 4I registers
   // out of the pair loop; the arithmetic is that of the register form.
-  constexpr bool LO_LDS = COMP && POT;
+  constexpr bool LO_LDS = COMP && (POT || ADAPT);
   __shared__ float lo_lds[LO_LDS ? W * NC * I * 64 : 1];
   float* const lo_w = lo_lds + (LO_LDS ? w * NC * I * 64 + lane : 0);  // word (c, u): lo_w[(c * I + u) * 64]
 
@@ -725,6 +765,31 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
     nxt = load_or(jarr, NV * j, j < n, jpad);
     if constexpr (DS) nxtl = load_or(jarr, NV * j + 1, j < n, zero);
   }
+  // Adaptive mode: bit q of near_mask marks the j-sub-blocks q of block B whose boxes lie
+  // within T of one of this wave's I i-sub-blocks (lane q tests sub-block q; off-diagonal
+  // tiles have A < B, so block A is full).
+  uint64_t near_mask = 0;
+  if constexpr (ADAPT_OFF) {
+    {
+      const float T2 = (float)ad.thr[0];
+      const int64_t nsub_all = (n + 63) >> 6;
+      const int64_t jq = (int64_t)B * NSUB + lane;
+      bool nr = false;
+      if (lane < NSUB && jq < nsub_all) {
+        const float4 blo = ad.box[2 * jq], bhi = ad.box[2 * jq + 1];
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+          const int64_t iq = (int64_t)A * NSUB + w * I + u;
+          const float4 alo = ad.box[2 * iq], ahi = ad.box[2 * iq + 1];
+          const float gx = fmaxf(0.f, fmaxf(blo.x - ahi.x, alo.x - bhi.x));
+          const float gy = fmaxf(0.f, fmaxf(blo.y - ahi.y, alo.y - bhi.y));
+          const float gz = fmaxf(0.f, fmaxf(blo.z - ahi.z, alo.z - bhi.z));
+          nr = nr || (gx * gx + gy * gy + gz * gz < T2);
+        }
+      }
+      near_mask = __ballot(nr);
+    }
+  }
   // Only the sub-blocks of block B that hold particles are visited (block B is ragged
   // when it is the system's last). Off-diagonal tiles have A < B, so block A is full and
   // every wave has real i-particles; on a diagonal tile a wave whose i-particles are all
@@ -740,7 +805,61 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
       if constexpr (DS) nxtl = load_or(jarr, NV * j + 1, j < n, zero);
     }
     float xj = q.x, yj = q.y, zj = q.z, mj = q.w, xjl = ql.x, yjl = ql.y, zjl = ql.z;
-    if (diag) {
+    if (ADAPT_DIAG) {
+      // one-sided with double-float separations, a quarter of the i-particles at a time; the
+      // self pair is the step-0 pair of sub-block w*I + u
+      const int64_t jq = Bbase + (int64_t)sb * 64 + lane;
+      const float4 qlo = load_or(ad.jlo, jq, jq < n, zero);
+      float xjo = qlo.x, yjo = qlo.y, zjo = qlo.z;
+#pragma unroll
+      for (int h = 0; h < I / IHD; ++h) {
+        float xio[IHD], yio[IHD], zio[IHD];
+#pragma unroll
+        for (int v = 0; v < IHD; ++v) {
+          const int64_t i = Abase + (int64_t)w * 64 * I + (h * IHD + v) * 64 + lane;
+          const float4 l = ad.jlo[i < n ? i : n - 1];
+          xio[v] = l.x;
+          yio[v] = l.y;
+          zio[v] = l.z;
+        }
+        for (int k = 0; k < 64; ++k) {
+#pragma unroll
+          for (int v = 0; v < IHD; ++v) {
+            const int u = h * IHD + v;
+            const float dx = (xj - xi[u]) + (xjo - xio[v]);
+            const float dy = (yj - yi[u]) + (yjo - yio[v]);
+            const float dz = (zj - zi[u]) + (zjo - zio[v]);
+            const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, eps2)));
+            const bool self = (k == 0 && sb == w * I + u);
+            if constexpr (LAW == LAW_LJ) {
+              const float iv = __builtin_amdgcn_rcpf(r2);
+              const float q6 = (iv * iv) * iv;
+              float sv = (iv * q6) * __builtin_fmaf(-2.f, q6, 1.f);
+              sv = self ? 0.f : sv;
+              ai[0][u] = __builtin_fmaf(sv, dx, ai[0][u]);
+              ai[1][u] = __builtin_fmaf(sv, dy, ai[1][u]);
+              ai[2][u] = __builtin_fmaf(sv, dz, ai[2][u]);
+              if constexpr (POT) ai[3][u] += self ? 0.f : __builtin_fmaf(q6, q6, -q6);
+            } else {
+              const float ri = __builtin_amdgcn_rsqf(r2);
+              const float mr = mj * ri;
+              const float sv = (mr * ri) * ri;
+              ai[0][u] = __builtin_fmaf(sv, dx, ai[0][u]);
+              ai[1][u] = __builtin_fmaf(sv, dy, ai[1][u]);
+              ai[2][u] = __builtin_fmaf(sv, dz, ai[2][u]);
+              if constexpr (POT) ai[3][u] -= self ? 0.f : mr;
+            }
+          }
+          xj = rotate1<ROT>(xj, rot_src);
+          yj = rotate1<ROT>(yj, rot_src);
+          zj = rotate1<ROT>(zj, rot_src);
+          mj = rotate1<ROT>(mj, rot_src);
+          xjo = rotate1<ROT>(xjo, rot_src);
+          yjo = rotate1<ROT>(yjo, rot_src);
+          zjo = rotate1<ROT>(zjo, rot_src);
+        }
+      }
+    } else if (diag) {
       // one-sided: i-side only; the self pair is the step-0 pair of sub-block w*I + u
       for (int k = 0; k < 64; ++k) {
 #pragma unroll
@@ -786,12 +905,97 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
       float aj[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) aj[c] = 0.f;
+      bool near_done = false;
+      if constexpr (ADAPT_OFF) {
+        if ((near_mask >> sb) & 1) {
+          // double-float separations for this near sub-block pair, half of the i-particles at a
+          // time; the j accumulators keep adding across both halves (they come home after 64
+          // steps), the pair terms are those of the float loop below
+          const int64_t jq = Bbase + (int64_t)sb * 64 + lane;
+          const float4 qlo = load_or(ad.jlo, jq, jq < n, zero);
+          float xjo = qlo.x, yjo = qlo.y, zjo = qlo.z;
+          // the lane index through an opaque move: the addresses are formed here, not hoisted out
+          // of the sub-block loop into registers the float loop would then have to carry
+          const float4* lrow = ad.jlo + Abase + (int64_t)w * 64 * I + opaque_int(lane);
+#pragma unroll
+          for (int h = 0; h < I / IH; ++h) {
+            float xio[IH], yio[IH], zio[IH];
+#pragma unroll
+            for (int v = 0; v < IH; ++v) {
+              const float4 l = lrow[(h * IH + v) * 64];
+              xio[v] = l.x;
+              yio[v] = l.y;
+              zio[v] = l.z;
+            }
+            for (int k = 0; k < 64; ++k) {
+              float dx[IH], dy[IH], dz[IH], ri[IH];
+#pragma unroll
+              for (int v = 0; v < IH; ++v) {
+                const int u = h * IH + v;
+                dx[v] = (xj - xi[u]) + (xjo - xio[v]);
+                dy[v] = (yj - yi[u]) + (yjo - yio[v]);
+                dz[v] = (zj - zi[u]) + (zjo - zio[v]);
+                ri[v] = __builtin_fmaf(dx[v], dx[v], __builtin_fmaf(dy[v], dy[v], __builtin_fmaf(dz[v], dz[v], eps2)));
+              }
+              const float xn = rotate1<ROT>(xj, rot_src), yn = rotate1<ROT>(yj, rot_src), zn = rotate1<ROT>(zj, rot_src);
+              const float xno = rotate1<ROT>(xjo, rot_src), yno = rotate1<ROT>(yjo, rot_src),
+                          zno = rotate1<ROT>(zjo, rot_src);
+#pragma unroll
+              for (int v = 0; v < IH; ++v)
+                ri[v] = LAW == LAW_LJ ? __builtin_amdgcn_rcpf(ri[v]) : __builtin_amdgcn_rsqf(ri[v]);
+#pragma unroll
+              for (int v = 0; v < IH; ++v) {
+                const int u = h * IH + v;
+                if constexpr (LAW == LAW_LJ) {
+                  const float q6 = (ri[v] * ri[v]) * ri[v];
+                  const float kf = (ri[v] * q6) * __builtin_fmaf(-2.f, q6, 1.f);
+                  if constexpr (POT) {
+                    const float pv = __builtin_fmaf(q6, q6, -q6);
+                    ai[3][u] += pv;
+                    aj[3] += pv;
+                  }
+                  ai[0][u] = __builtin_fmaf(kf, dx[v], ai[0][u]);
+                  ai[1][u] = __builtin_fmaf(kf, dy[v], ai[1][u]);
+                  ai[2][u] = __builtin_fmaf(kf, dz[v], ai[2][u]);
+                  aj[0] = __builtin_fmaf(-kf, dx[v], aj[0]);
+                  aj[1] = __builtin_fmaf(-kf, dy[v], aj[1]);
+                  aj[2] = __builtin_fmaf(-kf, dz[v], aj[2]);
+                } else {
+                  const float r3 = ri[v] * (ri[v] * ri[v]);
+                  const float si = mj * r3;
+                  const float sj = mi[u] * r3;
+                  if constexpr (POT) {
+                    ai[3][u] -= mj * ri[v];
+                    aj[3] -= mi[u] * ri[v];
+                  }
+                  ai[0][u] = __builtin_fmaf(si, dx[v], ai[0][u]);
+                  ai[1][u] = __builtin_fmaf(si, dy[v], ai[1][u]);
+                  ai[2][u] = __builtin_fmaf(si, dz[v], ai[2][u]);
+                  aj[0] = __builtin_fmaf(-sj, dx[v], aj[0]);
+                  aj[1] = __builtin_fmaf(-sj, dy[v], aj[1]);
+                  aj[2] = __builtin_fmaf(-sj, dz[v], aj[2]);
+                }
+              }
+              xj = xn;
+              yj = yn;
+              zj = zn;
+              xjo = xno;
+              yjo = yno;
+              zjo = zno;
+              mj = rotate1<ROT>(mj, rot_src);
+#pragma unroll
+              for (int c = 0; c < NC; ++c) aj[c] = rotate1<ROT>(aj[c], rot_src);
+            }
+          }
+          near_done = true;
+        }
+      }
       // Potential variant: no LDS operation is left in flight when the step loop starts (a wait for
       // lgkmcnt = 0, gfx9 encoding), so the compiler's waits inside the loop need to cover only the
       // loop's own rotations (measured 1.6% faster at N = 1M; the variant without the potential
       // gains nothing from it and keeps the compiler's code).
       if constexpr (POT && LAW == LAW_GRAV) __builtin_amdgcn_s_waitcnt(0xc07f);
-      for (int k = 0; k < 64; ++k) {
+      for (int k = 0; k < (near_done ? 0 : 64); ++k) {
         float xn = xj, yn = yj, zn = zj, xnl = xjl, ynl = yjl, znl = zjl;
         if constexpr (PIPE == 1) {  // the next step's coordinates, requested a step ahead
           xn = rotate1<ROT>(xj, rot_src);
@@ -924,11 +1128,18 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
 // Single system: one workgroup per tile t of the nb(nb+1)/2 upper-triangle tiles.
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restrict__ jarr, int64_t n, int32_t nb,
-                                                           float eps2_arg, float* __restrict__ part) {
+                                                           float eps2_arg, float* __restrict__ part, AdaptIn ad) {
   __shared__ float red[2][W][POT ? 4 : 3][64];
   int32_t A, B;
-  tile_rc(blockIdx.x, nb, A, B);
-  sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr, n, A, B, eps2_arg, part, red);
+  if constexpr (MODE == MODE_ADAPT_DIAG) {  // one workgroup per diagonal tile
+    A = B = (int32_t)blockIdx.x;
+  } else if constexpr (MODE == MODE_ADAPT) {  // the nb (nb - 1) / 2 off-diagonal tiles
+    tile_rc(blockIdx.x, nb - 1, A, B);
+    ++B;
+  } else {
+    tile_rc(blockIdx.x, nb, A, B);
+  }
+  sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr, n, A, B, eps2_arg, part, red, ad);
 }
 
 // ----------------------------------------------------------------- symmetric pass: per-particle reduction
@@ -961,16 +1172,18 @@ __device__ __forceinline__ void sum_slots(const float* __restrict__ part, int64_
     for (int c = 0; c < NC; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
 }
 
+// perm (nullable): the slot planes are in sorted order (the adaptive mode) and position p
+// holds particle perm[p], whose outputs are written at its own index.
 __global__ __launch_bounds__(kReduceBS) void reduce_sym(int64_t n, int64_t stride, int32_t nb,
                                                        const float* __restrict__ part, LawScale ls,
                                                        double* __restrict__ acc, double* __restrict__ pot,
                                                        double* __restrict__ vel, double hh, NextStep nx,
-                                                       EnergyFuse ef) {
-  auto body = [&](int64_t i, double* en) {
+                                                       EnergyFuse ef, const uint32_t* __restrict__ perm) {
+  auto body = [&](int64_t p, double* en) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    if (pot) sum_slots<4>(part, n, i, nb, a);
-    else sum_slots<3>(part, n, i, nb, a);
-    finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
+    if (pot) sum_slots<4>(part, n, p, nb, a);
+    else sum_slots<3>(part, n, p, nb, a);
+    finish_particle(perm ? (int64_t)perm[p] : p, stride, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
   };
   if (ef.part) {  // grid (chunks, 1)
     energy_chunk(0, n, 0, ef, body);

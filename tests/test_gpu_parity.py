@@ -7,10 +7,11 @@ Tolerances (force error e_i = |da_i| / max(|a_i|, 1e-6 rms|a|)):
                        arithmetic, float sums between compensated folds), on every particle
                        of small systems and on the worst particles of the large ones
   Plummer workloads    every particle against the FP64 GPU path, max e_i per mode:
-                       N = 65536, eps = 1e-2: compensated and double-float 1e-5, plain 1e-4;
-                       N = 1048576, eps = 1e-3: double-float 1e-5; compensated and plain
-                       1e-3 (a particle with a partner closer than ~eps carries the float
-                       rounding of its coordinates, u |x| / eps ~ 6e-5 |x| relative per pair)
+                       N = 65536, eps = 1e-2: compensated, double-float and adaptive 1e-5,
+                       plain 1e-4; N = 1048576, eps = 1e-3: double-float and adaptive 1e-5;
+                       compensated and plain 1e-3 (a particle with a partner closer than
+                       ~eps carries the float rounding of its coordinates, u |x| / eps
+                       ~ 6e-5 |x| relative per pair)
 Gradients: rel-L2 over each array and, per particle, |dg_k| / max(|g_k|, f rms|g|) with
   f = 1e-6 for position and velocity cotangents (3-vectors) and f = 1e-3 for mass
   cotangents (scalar sums of terms of both signs: a particle whose mass cotangent cancels
@@ -29,8 +30,8 @@ from paper_2511_02655_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TOL_F = {"fp64": 1e-12, "fp32c": 1e-5, "fp32": 1e-4, "fp32ds": 1e-5}
-TOL_P = {"fp64": 1e-12, "fp32c": 1e-6, "fp32": 1e-5, "fp32ds": 1e-6}
+TOL_F = {"fp64": 1e-12, "fp32c": 1e-5, "fp32": 1e-4, "fp32ds": 1e-5, "fp32a": 1e-5}
+TOL_P = {"fp64": 1e-12, "fp32c": 1e-6, "fp32": 1e-5, "fp32ds": 1e-6, "fp32a": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -139,8 +140,8 @@ def test_newton_third_law_gpu(nb):
     assert np.max(np.abs(total)) < 1e-12 * np.abs(a * s.mass).sum()
 
 
-TOL_FULL = {"plummer64k": {"fp32c": 1e-5, "fp32ds": 1e-5, "fp32": 1e-4},
-            "plummer1m": {"fp32c": 1e-3, "fp32ds": 1e-5, "fp32": 1e-3}}
+TOL_FULL = {"plummer64k": {"fp32c": 1e-5, "fp32ds": 1e-5, "fp32": 1e-4, "fp32a": 1e-5},
+            "plummer1m": {"fp32c": 1e-3, "fp32ds": 1e-5, "fp32": 1e-3, "fp32a": 1e-5}}
 
 
 @pytest.mark.parametrize("wl", ["plummer64k", "plummer1m"])
@@ -162,7 +163,7 @@ def test_plummer_every_particle(nb, oracle, wl):
     floor = 1e-6 * float(torch.sqrt((mag ** 2).mean()))
     res = {}
     pick = set()
-    for prec in ("fp32c", "fp32ds", "fp32"):
+    for prec in ("fp32c", "fp32ds", "fp32", "fp32a"):
         a, p = nb.forces(x, m, eps=eps, precision=prec, want_pot=True)
         e = torch.sqrt(((a - a64) ** 2).sum(0)) / torch.clamp(mag, min=floor)
         pe = float((torch.abs(p - p64) / torch.abs(p64)).max())
@@ -181,9 +182,10 @@ def test_plummer_every_particle(nb, oracle, wl):
     acc_ref, pot_ref = oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
     assert force_err(host(a64)[:, idx], acc_ref) <= TOL_F["fp64"]
     assert np.max(np.abs(host(p64)[idx] - pot_ref) / np.abs(pot_ref)) <= TOL_P["fp64"]
-    for prec in ("fp32c", "fp32ds", "fp32"):
-        B = fp32_bound(s.pos, s.mass, eps, accumulate_plain=(prec == "fp32"), exact_coords=(prec == "fp32ds"),
-                       idx=idx)
+    for prec in ("fp32c", "fp32ds", "fp32", "fp32a"):
+        from oracle import bounds
+        B = bounds.fp32_force_bound(s.pos, s.mass, eps, accumulate_plain=(prec == "fp32"),
+                                    exact_coords=(prec == "fp32ds"), adaptive=(prec == "fp32a"), idx=idx)
         d = np.sqrt(np.sum((res[prec][:, idx] - acc_ref) ** 2, axis=0))
         print("%s %s: worst |da_i| / B_i on %d sampled particles %.3f" % (wl, prec, idx.size, np.max(d / B)))
         assert np.max(d / B) <= 1.0, prec
