@@ -157,6 +157,24 @@ int nbody_forces(const nbody_config *cfg, int64_t n, const double *pos, const do
 int nbody_step(const nbody_config *cfg, int64_t n, double dt, double *pos, double *vel,
                const double *mass, double *acc, double *pot);
 
+/* ---- allocation-free step ----
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. The same step as nbody_step (same kernels, bitwise
+ * the same results) with its workspace taken from a static device array of
+ * NBODY_NOALLOC_SCRATCH_BYTES per GPU, which the library holds until the process ends; the
+ * library neither allocates nor frees memory in this call (the first call on a device only
+ * looks up the array's device address).
+ *   cfg->workspace must be NULL and cfg->workspace_bytes 0 (else NBODY_ERR_INVALID_ARG);
+ *   a single system only (n_systems == 1, offsets NULL; else NBODY_ERR_UNSUPPORTED);
+ *   n whose step needs more than NBODY_NOALLOC_SCRATCH_BYTES of workspace (the size
+ *   nbody_workspace_size(cfg, n, 1, 0) reports: about 90 000 particles with the tuned tiles
+ *   in FP32) returns NBODY_ERR_WORKSPACE before any device work.
+ * Every call on one GPU shares that GPU's array (nothing in it needs to start at zero): calls
+ * that overlap on one GPU (other host threads, other streams without ordering) race. */
+#define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int nbody_step_noalloc(const nbody_config *cfg, int64_t n, double dt, double *pos, double *vel,
+                       const double *mass, double *acc, double *pot);
+
 /* `steps` KDK steps (steps >= 0), state in place.
  *   acc   in: a(x_0) (e.g. from nbody_forces), out: a(x_steps)
  *   ckpt  nullable, [steps/ckpt_every + 1][6][n] doubles: (x planes, v planes)

@@ -34,7 +34,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPAC
 EXPORTED = ("nbody_abi_version", "nbody_last_error", "nbody_workspace_size", "nbody_forces", "nbody_step",
             "nbody_rollout", "nbody_energy_momentum", "nbody_rollout_backward", "nbody_set_tile_table",
             "nbody_tile_variants", "nbody_tile_lookup", "nbody_lj_forces", "nbody_lj_rollout",
-            "nbody_rollout_backward_reversible", "nbody_diagnostics", "nbody_set_wait_limit")
+            "nbody_rollout_backward_reversible", "nbody_diagnostics", "nbody_set_wait_limit",
+            "nbody_step_noalloc")
 
 
 class NBodyError(RuntimeError):
@@ -103,6 +104,7 @@ def lib():
         "nbody_workspace_size": ([C, I64, I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "nbody_forces": ([C, I64, P, P, P, P], ctypes.c_int),
         "nbody_step": ([C, I64, D, P, P, P, P, P], ctypes.c_int),
+        "nbody_step_noalloc": ([C, I64, D, P, P, P, P, P], ctypes.c_int),
         "nbody_rollout": ([C, I64, D, I64, I64, P, P, P, P, P, P], ctypes.c_int),
         "nbody_energy_momentum": ([C, I64, P, P, P, P, P], ctypes.c_int),
         "nbody_diagnostics": ([C, I64, P, P, P, P, P, P], ctypes.c_int),
@@ -302,6 +304,16 @@ def step(pos, vel, mass, acc, dt, *, G=1.0, eps=1e-2, precision="fp32c", offsets
     c.workspace(n, device=mass.device)
     _check(lib().nbody_step(ctypes.byref(c.cfg), n, float(dt), _dptr(pos, "pos", (3, n)), _dptr(vel, "vel", (3, n)),
                             _dptr(mass, "mass"), _dptr(acc, "acc", (3, n)), _dptr(out_pot, "pot", (n,))))
+
+
+def step_noalloc(pos, vel, mass, acc, dt, *, G=1.0, eps=1e-2, precision="fp32c", out_pot=None, stream=None):
+    """nbody_step without a workspace: the library's static device scratch serves it (single
+    systems whose step fits NBODY_NOALLOC_SCRATCH_BYTES)."""
+    n = _n_of(mass)
+    c = _Cfg(precision, G, eps, None, 0, stream)
+    _check(lib().nbody_step_noalloc(ctypes.byref(c.cfg), n, float(dt), _dptr(pos, "pos", (3, n)),
+                                    _dptr(vel, "vel", (3, n)), _dptr(mass, "mass"), _dptr(acc, "acc", (3, n)),
+                                    _dptr(out_pot, "pot", (n,))))
 
 
 def rollout(pos, vel, mass, acc, dt, steps, *, ckpt_every=0, energy_trace=False, G=1.0, eps=1e-2,

@@ -1443,6 +1443,64 @@ __attribute__((visibility("default"))) int nbody_step(const nbody_config* cfg, i
 
 }  // extern "C"
 
+// ------------------------------------------------------------------ allocation-free step
+
+// The workspace of nbody_step_noalloc: a file-scope device array, one copy per GPU the library
+// runs on, held until the process ends. In host code its name is only a stand-in: its device
+// address comes from hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[NBODY_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the first call on a device).
+int scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NBODY_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p) % kAlign) return fail(NBODY_ERR_DEVICE, "scratch array address unusable");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+__attribute__((visibility("default"))) int nbody_step_noalloc(const nbody_config* cfg, int64_t n, double dt,
+                                                              double* pos, double* vel, const double* mass,
+                                                              double* acc, double* pot) {
+  g_err.clear();
+  if (!cfg) return fail(NBODY_ERR_INVALID_ARG, "cfg is NULL");
+  if (cfg->workspace || cfg->workspace_bytes)
+    return fail(NBODY_ERR_INVALID_ARG, "nbody_step_noalloc takes no workspace: workspace must be NULL and "
+                                       "workspace_bytes 0");
+  if (cfg->n_systems != 1 || cfg->offsets)
+    return fail(NBODY_ERR_UNSUPPORTED, "nbody_step_noalloc serves a single system (n_systems == 1, offsets NULL)");
+  size_t need = 0;
+  TRY(nbody_workspace_size(cfg, n, 1, 0, &need));
+  if (need > (size_t)NBODY_NOALLOC_SCRATCH_BYTES)
+    return fail(NBODY_ERR_WORKSPACE, "n = %lld needs %zu bytes of scratch; the static scratch of "
+                                     "nbody_step_noalloc holds %zu (use nbody_step with a workspace)",
+                (long long)n, need, (size_t)NBODY_NOALLOC_SCRATCH_BYTES);
+  if (n == 0) return NBODY_OK;
+  nbody_config c = *cfg;
+  TRY(scratch_address(&c.workspace));
+  c.workspace_bytes = NBODY_NOALLOC_SCRATCH_BYTES;
+  return nbody_step(&c, n, dt, pos, vel, mass, acc, pot);
+}
+
+}  // extern "C"
+
 namespace {
 
 // Every step of a batched rollout on symmetric tiles in one launch (see

@@ -299,3 +299,20 @@ def test_autotune_pick_prefers_larger_symmetric_blocks_within_slack():
     assert at._pick([(1.000, 0), (1.005, 1), (1.02, 2)], descs)[1] == 1
     assert at._pick([(1.000, 1), (1.05, 2), (0.98, 0)], descs)[1] == 0
     assert at._sym_edge(descs[2]) == 2048 and at._sym_edge(descs[0]) == 0
+
+
+def test_step_noalloc_rejections_before_device_work(nb):
+    """The allocation-free step refuses, on the host and before any HIP call, a caller workspace,
+    batches, and systems whose step needs more than the static scratch."""
+    L = nb.lib()
+    z = ctypes.c_void_p(0)
+    c = _cfg(nb, ws=ctypes.c_void_p(256), ws_bytes=1 << 20)
+    assert L.nbody_step_noalloc(ctypes.byref(c), 10, 1e-3, z, z, z, z, None) == 1
+    assert b"workspace" in L.nbody_last_error()
+    c = _cfg(nb, offsets=[0, 5, 10])
+    assert L.nbody_step_noalloc(ctypes.byref(c), 10, 1e-3, z, z, z, z, None) == 3
+    c = _cfg(nb)
+    assert L.nbody_step_noalloc(ctypes.byref(c), 1 << 21, 1e-3, z, z, z, z, None) == 4
+    assert b"static scratch" in L.nbody_last_error()
+    # zero particles: nothing to do, OK without touching a device
+    assert L.nbody_step_noalloc(ctypes.byref(c), 0, 1e-3, z, z, z, z, None) == 0
