@@ -380,7 +380,30 @@ Tile lookup_tile(int kernel, int prec, int64_t n);
 // Entry of the table for exactly this kernel id (no fallback); false when none matches.
 bool find_entry(int kernel, int prec, int64_t n, Tile& out);
 
+// Symmetric tiles keep one float slot per (particle, other block): nb * 4 * n * 4 bytes, O(n^2).
+// A single-system pass whose slots would exceed this many bytes runs one-sided instead (its
+// workspace grows as O(n)): the tuned table's symmetric entries reach this size near 1.5M particles.
+constexpr double kSymPartCap = 16.0 * (double)(1ull << 30);
+
+Tile lookup_tile_raw(int kernel, int prec, int64_t n);
+
 Tile lookup_tile(int kernel, int prec, int64_t n) {
+  Tile t = lookup_tile_raw(kernel, prec, n);
+  const int bk = base_kernel(kernel);
+  const bool single = bk == NBODY_KERNEL_FORCE || bk == NBODY_KERNEL_ADJOINT;
+  if (single && t.sym >= 0 && (double)cdiv(std::max<int64_t>(n, 1), (int64_t)t.tj) * 16.0 * (double)n > kSymPartCap) {
+    // the one-sided variant of the built-in defaults, one j-range per block column
+    Tile o{};
+    o.variant = 0;
+    o.sym = -1;
+    variant_shape(kernel, prec, o.variant, o.bs, o.i, o.tj);
+    o.j_split = 1;
+    return o;
+  }
+  return t;
+}
+
+Tile lookup_tile_raw(int kernel, int prec, int64_t n) {
   Tile t;
   // the adaptive mode without entries of its own runs with the compensated mode's tiles (its
   // float loop is the compensated one)

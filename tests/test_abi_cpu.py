@@ -312,7 +312,24 @@ def test_step_noalloc_rejections_before_device_work(nb):
     c = _cfg(nb, offsets=[0, 5, 10])
     assert L.nbody_step_noalloc(ctypes.byref(c), 10, 1e-3, z, z, z, z, None) == 3
     c = _cfg(nb)
-    assert L.nbody_step_noalloc(ctypes.byref(c), 1 << 21, 1e-3, z, z, z, z, None) == 4
+    assert L.nbody_step_noalloc(ctypes.byref(c), 1 << 23, 1e-3, z, z, z, z, None) == 4
     assert b"static scratch" in L.nbody_last_error()
     # zero particles: nothing to do, OK without touching a device
     assert L.nbody_step_noalloc(ctypes.byref(c), 0, 1e-3, z, z, z, z, None) == 0
+
+
+def test_workspace_stays_linear_beyond_the_symmetric_cap(nb):
+    """Symmetric tiles keep O(n^2 / block) float slots; past 16 GiB of them a single-system pass
+    runs one-sided, so the workspace of a 4M-particle call is O(n) (and smaller than at 1M)."""
+    for prec in (1, 2, 4):  # plain, compensated, adaptive FP32
+        rc, w1m = _ws_size(nb, _cfg(nb, precision=prec), 1 << 20)
+        assert rc == 0 and w1m > (1 << 33)  # ~8.6 GB of tile partials on the tuned 2048-particle tiles
+        rc, w4m = _ws_size(nb, _cfg(nb, precision=prec), 1 << 22)
+        assert rc == 0 and w4m < 200 * (1 << 22) and w4m < w1m
+        rc, wb = _ws_size(nb, _cfg(nb, precision=prec), 1 << 22, 10, 5)  # with a backward pass
+        assert rc == 0 and wb < 1000 * (1 << 22)
+    v = ctypes.c_int32()
+    sp = ctypes.c_int32()
+    for kernel in (0, 1):
+        assert nb.lib().nbody_tile_lookup(kernel, 2, 1 << 22, ctypes.byref(v), ctypes.byref(sp)) == 0
+        assert "sym=" not in nb.tile_variants(["force", "adjoint"][kernel], "fp32c")[v.value]
