@@ -209,7 +209,8 @@ struct SymVariant {
 const SymVariant kSym32[] = {SV32(8, 4, 0), SV32(4, 4, 0), SV32(8, 2, 0), SV32(4, 2, 0), SV32(2, 4, 0),
                              SV32(8, 4, 1), SV32(4, 4, 1), SV32(4, 8, 0), SV32(4, 8, 1), SV32(2, 4, 1),
                              SV32(4, 2, 1), SV32(2, 2, 1), SV32P(8, 4, 1, 1), SV32P(4, 8, 1, 1),
-                             SV32P(4, 4, 1, 1), SV32(1, 4, 1)};
+                             SV32P(4, 4, 1, 1), SV32(1, 4, 1), SV32(1, 2, 1), SV32(1, 2, 0), SV32(1, 2, 2),
+                             SV32(1, 4, 2), SV32(2, 2, 2), SV32(2, 4, 2)};
 constexpr int kNumSym32 = sizeof(kSym32) / sizeof(kSym32[0]);
 
 // Symmetric FP32 adjoint variants, indices kNumAdj32 + k in the ADJOINT tables.
@@ -234,7 +235,8 @@ struct AdjSymVariant {
         {launch_adj_sym_batched<W, I, false, R>, launch_adj_sym_batched<W, I, true, R>}                  \
   }
 const AdjSymVariant kAdjSym32[] = {SA32(4, 2, 1), SA32(2, 2, 1), SA32(4, 4, 1), SA32(2, 4, 1), SA32(8, 2, 1),
-                                   SA32(4, 2, 0), SA32(2, 4, 0), SA32(1, 4, 1)};
+                                   SA32(4, 2, 0), SA32(2, 4, 0), SA32(1, 4, 1), SA32(1, 2, 1), SA32(1, 2, 0),
+                                   SA32(1, 2, 2), SA32(1, 4, 2)};
 constexpr int kNumAdjSym32 = sizeof(kAdjSym32) / sizeof(kAdjSym32[0]);
 
 constexpr int kNumForce32 = sizeof(kForce32) / sizeof(kForce32[0]);
@@ -1850,8 +1852,8 @@ __attribute__((visibility("default"))) int nbody_tile_variants(int32_t kernel, i
       int sw = 0, si = 0, srot = 0;
       if (sv >= 0) sym_shape(kernel, sv, sw, si, srot);
       const bool pipe = sv >= 0 && is_force_kernel(kernel) && kSym32[sv].pipe;
-      int len = sv >= 0 ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d%s%s", bs, i, tj, srot ? ",rot=lds" : "",
-                                   pipe ? ",pipe" : "")
+      int len = sv >= 0 ? snprintf(tmp, sizeof tmp, "bs=%d,i=%d,sym=%d%s%s", bs, i, tj,
+                                   srot == 1 ? ",rot=lds" : srot == 2 ? ",rot=mix" : "", pipe ? ",pipe" : "")
                         : snprintf(tmp, sizeof tmp, "bs=%d,i=%d,tj=%d", bs, i, tj);
       if (pos + len + 1 > cap) break;
       memcpy(buf + pos, tmp, len + 1);

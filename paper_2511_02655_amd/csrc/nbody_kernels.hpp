@@ -249,14 +249,42 @@ struct NextStep {
   void* jarr;
 };
 
-// vel planes already hold v after the closing kick of particle i; a = its acceleration.
+// The state a per-particle reduction needs besides the particle's sums, loaded before the sums'
+// own loads so that all of them are in flight together (a reduction over few particles is bound by
+// memory round trips): the divisor of the law (a mass, or 1), the velocity, and for the fused
+// next step the position and the mass; the energy's mass.
+struct PState {
+  double md, em, m;
+  double v[3], x[3];
+};
+
+__device__ __forceinline__ PState load_state(int64_t i, int64_t stride, const LawScale& ls,
+                                             const double* __restrict__ vel, const NextStep& nx,
+                                             const double* __restrict__ emass, bool en) {
+  PState ps{};
+  ps.md = law_div(ls, i);
+  if (vel)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ps.v[c] = vel[c * stride + i];
+  if (nx.kind) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ps.x[c] = nx.pos[c * stride + i];
+    if (nx.kind != 4) ps.m = nx.mass[i];
+  }
+  if (en) ps.em = emass[i];
+  return ps;
+}
+
+// The next step's first half for particle i, whose closing-kicked velocity is v (the value just
+// written to the velocity planes) and whose position is x0: kick, drift, walls, staging.
 __device__ __forceinline__ void next_step_tail(const NextStep& ns, int64_t i, int64_t n, const double a[3],
+                                               const double v_in[3], const double x0[3], double m,
                                                double* __restrict__ vel) {
   double x[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double v = vel[c * n + i] + ns.hh * a[c];
-    double xc = ns.pos[c * n + i] + ns.h * v;
+    double v = v_in[c] + ns.hh * a[c];
+    double xc = x0[c] + ns.h * v;
     if (ns.wl.on) {
       if (xc < ns.wl.lo[c]) {
         xc = 2.0 * ns.wl.lo[c] - xc;
@@ -270,9 +298,9 @@ __device__ __forceinline__ void next_step_tail(const NextStep& ns, int64_t i, in
     ns.pos[c * n + i] = xc;
     x[c] = xc;
   }
-  if (ns.kind == 1) put_j<float, false>((float4*)ns.jarr, i, x, ns.mass[i], ns.xs);
-  else if (ns.kind == 2) put_j<double, false>((D4*)ns.jarr, i, x, ns.mass[i], ns.xs);
-  else if (ns.kind == 3) put_j<float, true>((float4*)ns.jarr, i, x, ns.mass[i], ns.xs);
+  if (ns.kind == 1) put_j<float, false>((float4*)ns.jarr, i, x, m, ns.xs);
+  else if (ns.kind == 2) put_j<double, false>((D4*)ns.jarr, i, x, m, ns.xs);
+  else if (ns.kind == 3) put_j<float, true>((float4*)ns.jarr, i, x, m, ns.xs);
   // kind 4: no staging (the adaptive mode stages in sorted order before its next pass)
 }
 
@@ -340,21 +368,22 @@ __device__ __forceinline__ void energy_chunk(int64_t b, int64_t e, int64_t s, co
     for (int c = 0; c < 5; ++c) ef.part[(s * ef.chunks + blockIdx.x) * 5 + c] = en[c];
 }
 
-// The common end of the per-particle reductions, given particle i's raw sums a[4]:
-// acceleration, closing half kick v += hh a (vel != nullptr), potential (pot != nullptr),
-// its energy terms (en != nullptr; needs pot, vel and emass) and the next step's first half.
+// The common end of the per-particle reductions, given particle i's raw sums a[4] and its state
+// ps (load_state): acceleration, closing half kick v += hh a (vel != nullptr), potential (pot !=
+// nullptr), its energy terms (en != nullptr; needs pot, vel and emass) and the next step's first
+// half.
 __device__ __forceinline__ void finish_particle(int64_t i, int64_t stride, const double a[4], const LawScale& ls,
                                                 double* __restrict__ acc, double* __restrict__ pot,
                                                 double* __restrict__ vel, double hh, const NextStep& nx,
-                                                const double* __restrict__ emass, double* en) {
-  const double md = law_div(ls, i);
+                                                double* en, const PState& ps) {
+  const double md = ps.md;
   double ac[3], v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     ac[c] = ls.ca * a[c] / md;
     acc[c * stride + i] = ac[c];
     if (vel) {
-      v[c] = vel[c * stride + i] + hh * ac[c];
+      v[c] = ps.v[c] + hh * ac[c];
       vel[c * stride + i] = v[c];
     }
   }
@@ -363,30 +392,43 @@ __device__ __forceinline__ void finish_particle(int64_t i, int64_t stride, const
     phi = ls.cp * a[3] / md;
     pot[i] = phi;
   }
-  if (en) energy_terms(emass[i], v[0], v[1], v[2], phi, en);
-  if (nx.kind) next_step_tail(nx, i, stride, ac, vel);
+  if (en) energy_terms(ps.em, v[0], v[1], v[2], phi, en);
+  if (nx.kind) next_step_tail(nx, i, stride, ac, v, ps.x, ps.m, vel);
+}
+
+// The same with the state loaded here (kernels whose registers a pair loop shares).
+__device__ __forceinline__ void finish_particle(int64_t i, int64_t stride, const double a[4], const LawScale& ls,
+                                                double* __restrict__ acc, double* __restrict__ pot,
+                                                double* __restrict__ vel, double hh, const NextStep& nx,
+                                                const double* __restrict__ emass, double* en) {
+  const PState ps = load_state(i, stride, ls, vel, nx, emass, en != nullptr);
+  finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, en, ps);
 }
 
 // a[c] += part[(p * NC + c) * n + i] for p = 0 .. S-1 in order (double partial planes of the
-// j-split passes); the loads of 4 splits are issued before their additions.
-template <int NC>
+// j-split passes). The loads of K splits are issued before their additions, so ceil(S / K)
+// memory round trips serve the whole sum while the additions keep the split order; the splits
+// past S in the last round add +0.0, which leaves a sum that starts at +0.0 unchanged (in
+// round-to-nearest a sum is -0.0 only when both terms are), so the result is that of the plain
+// loop for any K.
+template <int NC, int K = 16>
 __device__ __forceinline__ void sum_splits(const double* __restrict__ part, int64_t n, int64_t i, int32_t S,
                                            double* a) {
-  int32_t p = 0;
-  for (; p + 4 <= S; p += 4) {
-    double v[4][NC];
+  for (int32_t p = 0; p < S; p += K) {
+    double v[K][NC];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) v[k][c] = part[((int64_t)(p + k) * NC + c) * n + i];
+      for (int c = 0; c < NC; ++c) {
+        const int32_t q = p + k < S ? p + k : S - 1;  // in bounds: every load issues unconditionally
+        const double x = part[((int64_t)q * NC + c) * n + i];
+        v[k][c] = p + k < S ? x : 0.0;
+      }
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int c = 0; c < NC; ++c) a[c] += v[k][c];
   }
-  for (; p < S; ++p)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) a[c] += part[((int64_t)p * NC + c) * n + i];
 }
 
 // Sum of j-split partials (fixed order p = 0..S-1), scaled by the law's constants;
@@ -404,9 +446,10 @@ __global__ __launch_bounds__(kReduceBS) void reduce_splits(int64_t count, int64_
                                                           EnergyFuse ef) {
   const int64_t n = stride;
   auto body = [&](int64_t i, int32_t s_cnt, double* en) {
+    const PState ps = load_state(i, n, ls, vel, nx, ef.mass, en != nullptr);
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     sum_splits<4>(part, n, i, s_cnt, a);
-    finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
+    finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, en, ps);
   };
   if (ef.part) {  // grid (chunks, systems)
     const int64_t s = blockIdx.y;
@@ -647,11 +690,15 @@ __device__ __forceinline__ float wave_ror1_lds(float v, int src_byte) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
 }
 
+// ROT: 0 DPP, 1 LDS crossbar, 2 mixed (coordinates and masses through the LDS crossbar, whose
+// latency a step ahead hides; the j accumulators, which the next step needs at once, through DPP).
 template <int ROT>
 __device__ __forceinline__ float rotate1(float v, int src_byte) {
   if constexpr (ROT == 0) return wave_ror1(v);
   else return wave_ror1_lds(v, src_byte);
 }
+template <int ROT> constexpr int rot_coord() { return ROT == 2 ? 1 : ROT; }
+template <int ROT> constexpr int rot_acc() { return ROT == 2 ? 0 : ROT; }
 
 // Tile t of the upper triangle (A <= B) of an nb x nb block grid, row-major:
 // row A holds tiles B = A .. nb-1, and rows before A hold A*nb - A*(A-1)/2 tiles.
@@ -847,16 +894,16 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
               ai[0][u] = __builtin_fmaf(sv, dx, ai[0][u]);
               ai[1][u] = __builtin_fmaf(sv, dy, ai[1][u]);
               ai[2][u] = __builtin_fmaf(sv, dz, ai[2][u]);
-              if constexpr (POT) ai[3][u] -= self ? 0.f : mr;
+              if constexpr (POT) ai[3][u] = self ? ai[3][u] : __builtin_fmaf(-mj, ri, ai[3][u]);
             }
           }
-          xj = rotate1<ROT>(xj, rot_src);
-          yj = rotate1<ROT>(yj, rot_src);
-          zj = rotate1<ROT>(zj, rot_src);
-          mj = rotate1<ROT>(mj, rot_src);
-          xjo = rotate1<ROT>(xjo, rot_src);
-          yjo = rotate1<ROT>(yjo, rot_src);
-          zjo = rotate1<ROT>(zjo, rot_src);
+          xj = rotate1<rot_coord<ROT>()>(xj, rot_src);
+          yj = rotate1<rot_coord<ROT>()>(yj, rot_src);
+          zj = rotate1<rot_coord<ROT>()>(zj, rot_src);
+          mj = rotate1<rot_coord<ROT>()>(mj, rot_src);
+          xjo = rotate1<rot_coord<ROT>()>(xjo, rot_src);
+          yjo = rotate1<rot_coord<ROT>()>(yjo, rot_src);
+          zjo = rotate1<rot_coord<ROT>()>(zjo, rot_src);
         }
       }
     } else if (diag) {
@@ -888,17 +935,19 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
             ai[0][u] = __builtin_fmaf(s, dx, ai[0][u]);
             ai[1][u] = __builtin_fmaf(s, dy, ai[1][u]);
             ai[2][u] = __builtin_fmaf(s, dz, ai[2][u]);
-            if (POT) ai[3][u] -= (k == 0 && sb == w * I + u) ? 0.f : mr;
+            // explicitly fused, as in the two-sided loop: an implicit contraction would depend on
+            // how the compiler unrolls the loop (the self test folds away in later copies)
+            if (POT) ai[3][u] = (k == 0 && sb == w * I + u) ? ai[3][u] : __builtin_fmaf(-mj, ri, ai[3][u]);
           }
         }
-        xj = rotate1<ROT>(xj, rot_src);
-        yj = rotate1<ROT>(yj, rot_src);
-        zj = rotate1<ROT>(zj, rot_src);
-        mj = rotate1<ROT>(mj, rot_src);
+        xj = rotate1<rot_coord<ROT>()>(xj, rot_src);
+        yj = rotate1<rot_coord<ROT>()>(yj, rot_src);
+        zj = rotate1<rot_coord<ROT>()>(zj, rot_src);
+        mj = rotate1<rot_coord<ROT>()>(mj, rot_src);
         if constexpr (DS) {
-          xjl = rotate1<ROT>(xjl, rot_src);
-          yjl = rotate1<ROT>(yjl, rot_src);
-          zjl = rotate1<ROT>(zjl, rot_src);
+          xjl = rotate1<rot_coord<ROT>()>(xjl, rot_src);
+          yjl = rotate1<rot_coord<ROT>()>(yjl, rot_src);
+          zjl = rotate1<rot_coord<ROT>()>(zjl, rot_src);
         }
       }
     } else {
@@ -937,9 +986,9 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
                 dz[v] = (zj - zi[u]) + (zjo - zio[v]);
                 ri[v] = __builtin_fmaf(dx[v], dx[v], __builtin_fmaf(dy[v], dy[v], __builtin_fmaf(dz[v], dz[v], eps2)));
               }
-              const float xn = rotate1<ROT>(xj, rot_src), yn = rotate1<ROT>(yj, rot_src), zn = rotate1<ROT>(zj, rot_src);
-              const float xno = rotate1<ROT>(xjo, rot_src), yno = rotate1<ROT>(yjo, rot_src),
-                          zno = rotate1<ROT>(zjo, rot_src);
+              const float xn = rotate1<rot_coord<ROT>()>(xj, rot_src), yn = rotate1<rot_coord<ROT>()>(yj, rot_src), zn = rotate1<rot_coord<ROT>()>(zj, rot_src);
+              const float xno = rotate1<rot_coord<ROT>()>(xjo, rot_src), yno = rotate1<rot_coord<ROT>()>(yjo, rot_src),
+                          zno = rotate1<rot_coord<ROT>()>(zjo, rot_src);
 #pragma unroll
               for (int v = 0; v < IH; ++v)
                 ri[v] = LAW == LAW_LJ ? __builtin_amdgcn_rcpf(ri[v]) : __builtin_amdgcn_rsqf(ri[v]);
@@ -965,8 +1014,8 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
                   const float si = mj * r3;
                   const float sj = mi[u] * r3;
                   if constexpr (POT) {
-                    ai[3][u] -= mj * ri[v];
-                    aj[3] -= mi[u] * ri[v];
+                    ai[3][u] = __builtin_fmaf(-mj, ri[v], ai[3][u]);
+                    aj[3] = __builtin_fmaf(-mi[u], ri[v], aj[3]);
                   }
                   ai[0][u] = __builtin_fmaf(si, dx[v], ai[0][u]);
                   ai[1][u] = __builtin_fmaf(si, dy[v], ai[1][u]);
@@ -982,9 +1031,9 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
               xjo = xno;
               yjo = yno;
               zjo = zno;
-              mj = rotate1<ROT>(mj, rot_src);
+              mj = rotate1<rot_coord<ROT>()>(mj, rot_src);
 #pragma unroll
-              for (int c = 0; c < NC; ++c) aj[c] = rotate1<ROT>(aj[c], rot_src);
+              for (int c = 0; c < NC; ++c) aj[c] = rotate1<rot_acc<ROT>()>(aj[c], rot_src);
             }
           }
           near_done = true;
@@ -998,13 +1047,13 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
       for (int k = 0; k < (near_done ? 0 : 64); ++k) {
         float xn = xj, yn = yj, zn = zj, xnl = xjl, ynl = yjl, znl = zjl;
         if constexpr (PIPE == 1) {  // the next step's coordinates, requested a step ahead
-          xn = rotate1<ROT>(xj, rot_src);
-          yn = rotate1<ROT>(yj, rot_src);
-          zn = rotate1<ROT>(zj, rot_src);
+          xn = rotate1<rot_coord<ROT>()>(xj, rot_src);
+          yn = rotate1<rot_coord<ROT>()>(yj, rot_src);
+          zn = rotate1<rot_coord<ROT>()>(zj, rot_src);
           if constexpr (DS) {
-            xnl = rotate1<ROT>(xjl, rot_src);
-            ynl = rotate1<ROT>(yjl, rot_src);
-            znl = rotate1<ROT>(zjl, rot_src);
+            xnl = rotate1<rot_coord<ROT>()>(xjl, rot_src);
+            ynl = rotate1<rot_coord<ROT>()>(yjl, rot_src);
+            znl = rotate1<rot_coord<ROT>()>(zjl, rot_src);
           }
         }
         // phase 1: separations and r^2 of the I pairs; phase 2: their square roots;
@@ -1023,13 +1072,13 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
           ri[u] = __builtin_fmaf(dx[u], dx[u], __builtin_fmaf(dy[u], dy[u], __builtin_fmaf(dz[u], dz[u], eps2)));
         }
         if constexpr (PIPE == 0) {  // consumed: pass them on while phases 2 and 3 run
-          xn = rotate1<ROT>(xj, rot_src);
-          yn = rotate1<ROT>(yj, rot_src);
-          zn = rotate1<ROT>(zj, rot_src);
+          xn = rotate1<rot_coord<ROT>()>(xj, rot_src);
+          yn = rotate1<rot_coord<ROT>()>(yj, rot_src);
+          zn = rotate1<rot_coord<ROT>()>(zj, rot_src);
           if constexpr (DS) {
-            xnl = rotate1<ROT>(xjl, rot_src);
-            ynl = rotate1<ROT>(yjl, rot_src);
-            znl = rotate1<ROT>(zjl, rot_src);
+            xnl = rotate1<rot_coord<ROT>()>(xjl, rot_src);
+            ynl = rotate1<rot_coord<ROT>()>(yjl, rot_src);
+            znl = rotate1<rot_coord<ROT>()>(zjl, rot_src);
           }
         }
 #pragma unroll
@@ -1064,8 +1113,8 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
           const float si = mj * r3;
           const float sj = mi[u] * r3;
           if (POT) {
-            ai[3][u] -= mj * ri[u];
-            aj[3] -= mi[u] * ri[u];
+            ai[3][u] = __builtin_fmaf(-mj, ri[u], ai[3][u]);
+            aj[3] = __builtin_fmaf(-mi[u], ri[u], aj[3]);
           }
           ai[0][u] = __builtin_fmaf(si, dx[u], ai[0][u]);
           ai[1][u] = __builtin_fmaf(si, dy[u], ai[1][u]);
@@ -1082,9 +1131,9 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
           yjl = ynl;
           zjl = znl;
         }
-        mj = rotate1<ROT>(mj, rot_src);
+        mj = rotate1<rot_coord<ROT>()>(mj, rot_src);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) aj[c] = rotate1<ROT>(aj[c], rot_src);
+        for (int c = 0; c < NC; ++c) aj[c] = rotate1<rot_acc<ROT>()>(aj[c], rot_src);
       }
       // j-side of this sub-block: sum the W waves in wave order, write slot A
 #pragma unroll
@@ -1149,27 +1198,29 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 // n: particles of the system (partial plane stride); stride: plane stride of acc/vel.
 // a[c] += slot s of component c, s = 0 .. nb-1 in order, for the particle at offset i of
 // planes of stride n (slot s, component c at (s * 4 + c) * n). The loads of K slots are issued
-// before their additions, which keep the slot order (so the sum is the plain loop's for any K).
-// K = 8 suits the single-system reduction (hundreds of slots per particle); kernels that hold
-// few slots per particle or share their registers with a pair loop take K = 1.
-template <int NC, int K = 8>
+// before their additions, so ceil(nb / K) memory round trips serve the sum (the single-system
+// reductions run few waves for small systems and are bound by those round trips) while the
+// additions keep the slot order; slots past nb in the last round add +0.0, which leaves the sum
+// unchanged (it starts at +0.0 and is never -0.0 in round-to-nearest), so the result is that of
+// the plain loop for any K. Kernels that share their registers with a pair loop take K = 1.
+template <int NC, int K = 32>
 __device__ __forceinline__ void sum_slots(const float* __restrict__ part, int64_t n, int64_t i, int32_t nb,
                                           double a[4]) {
-  int32_t s = 0;
-  for (; s + K <= nb; s += K) {
+  for (int32_t s = 0; s < nb; s += K) {
     float v[K][NC];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) v[k][c] = part[((int64_t)(s + k) * 4 + c) * n + i];
+      for (int c = 0; c < NC; ++c) {
+        const int32_t q = s + k < nb ? s + k : nb - 1;  // in bounds: every load issues unconditionally
+        const float x = part[((int64_t)q * 4 + c) * n + i];
+        v[k][c] = s + k < nb ? x : 0.f;
+      }
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int c = 0; c < NC; ++c) a[c] += (double)v[k][c];
   }
-  for (; s < nb; ++s)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) a[c] += (double)part[((int64_t)s * 4 + c) * n + i];
 }
 
 // perm (nullable): the slot planes are in sorted order (the adaptive mode) and position p
@@ -1180,10 +1231,12 @@ __global__ __launch_bounds__(kReduceBS) void reduce_sym(int64_t n, int64_t strid
                                                        double* __restrict__ vel, double hh, NextStep nx,
                                                        EnergyFuse ef, const uint32_t* __restrict__ perm) {
   auto body = [&](int64_t p, double* en) {
+    const int64_t i = perm ? (int64_t)perm[p] : p;
+    const PState ps = load_state(i, stride, ls, vel, nx, ef.mass, en != nullptr);
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     if (pot) sum_slots<4>(part, n, p, nb, a);
     else sum_slots<3>(part, n, p, nb, a);
-    finish_particle(perm ? (int64_t)perm[p] : p, stride, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
+    finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, en, ps);
   };
   if (ef.part) {  // grid (chunks, 1)
     energy_chunk(0, n, 0, ef, body);
@@ -1234,11 +1287,12 @@ __global__ __launch_bounds__(kReduceBS) void reduce_sym_batched(int64_t n, int64
   auto body = [&](int64_t i, int64_t s, double* en) {
     const int64_t b = sys_off[s], ns = sys_off[s + 1] - b, li = i - b;
     const int32_t nb = sys_nb[s];
-    const float* ps = part + sys_part[s];
+    const float* pp = part + sys_part[s];
+    const PState st = load_state(i, n, ls, vel, nx, ef.mass, en != nullptr);
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    if (pot) sum_slots<4, 1>(ps, ns, li, nb, a);
-    else sum_slots<3, 1>(ps, ns, li, nb, a);
-    finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, ef.mass, en);
+    if (pot) sum_slots<4, 1>(pp, ns, li, nb, a);
+    else sum_slots<3, 1>(pp, ns, li, nb, a);
+    finish_particle(i, n, a, ls, acc, pot, vel, hh, nx, en, st);
   };
   if (ef.part) {  // grid (chunks, systems)
     const int64_t s = blockIdx.y;
@@ -1718,7 +1772,7 @@ __global__ __launch_bounds__(BS) void adjoint_batched_kernel(const typename Vec4
 // Sum of adjoint j-split partials (fixed order), combined and added into gpos/gmass.
 //   part [S][8][n]; jadj gives m_k and l_k of particle k.
 template <typename T>
-__global__ void adjoint_reduce(int64_t count, int64_t stride, int32_t S, const double* __restrict__ part,
+__global__ __launch_bounds__(256) void adjoint_reduce(int64_t count, int64_t stride, int32_t S, const double* __restrict__ part,
                                const typename Vec4<T>::type* __restrict__ jadj, double G,
                                double* __restrict__ gpos, double* __restrict__ gmass, int64_t n_sys,
                                const int64_t* __restrict__ sys_off, const int32_t* __restrict__ nsplit) {
@@ -1734,15 +1788,20 @@ __global__ void adjoint_reduce(int64_t count, int64_t stride, int32_t S, const d
     }
     s_cnt = nsplit[lo];
   }
-  double r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  sum_splits<8>(part, n, i, s_cnt, r);
+  // the particle's own state first, so that its loads are in flight with the sums'
   const auto a = jadj[2 * i];
   const auto l = jadj[2 * i + 1];
+  double g0[4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g0[c] = gpos[c * n + i];
+  g0[3] = gmass[i];
+  double r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  sum_splits<8, 4>(part, n, i, s_cnt, r);
   const double m = (double)a.w;
   const double lk[3] = {(double)l.x, (double)l.y, (double)l.z};
 #pragma unroll
-  for (int c = 0; c < 3; ++c) gpos[c * n + i] += G * (m * r[c] - r[3] * lk[c] - r[4 + c]);
-  gmass[i] += -G * r[7];
+  for (int c = 0; c < 3; ++c) gpos[c * n + i] = g0[c] + G * (m * r[c] - r[3] * lk[c] - r[4 + c]);
+  gmass[i] = g0[3] + -G * r[7];
 }
 
 // ----------------------------------------------------------------- symmetric adjoint pass (FP32)
@@ -1851,19 +1910,19 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
           ai[2][u] += __builtin_fmaf(am, ljz, __builtin_fmaf(-bm, lz[u], -(cc * dz)));
           ai[3][u] = __builtin_fmaf(r3, pp, ai[3][u]);
         }
-        xj = rotate1<ROT>(xj, rot_src);
-        yj = rotate1<ROT>(yj, rot_src);
-        zj = rotate1<ROT>(zj, rot_src);
-        mj = rotate1<ROT>(mj, rot_src);
-        ljx = rotate1<ROT>(ljx, rot_src);
-        ljy = rotate1<ROT>(ljy, rot_src);
-        ljz = rotate1<ROT>(ljz, rot_src);
+        xj = rotate1<rot_coord<ROT>()>(xj, rot_src);
+        yj = rotate1<rot_coord<ROT>()>(yj, rot_src);
+        zj = rotate1<rot_coord<ROT>()>(zj, rot_src);
+        mj = rotate1<rot_coord<ROT>()>(mj, rot_src);
+        ljx = rotate1<rot_coord<ROT>()>(ljx, rot_src);
+        ljy = rotate1<rot_coord<ROT>()>(ljy, rot_src);
+        ljz = rotate1<rot_coord<ROT>()>(ljz, rot_src);
       }
     } else {
       float aj[4] = {0.f, 0.f, 0.f, 0.f};
       for (int k = 0; k < 64; ++k) {
         // the next step's coordinates are requested first, a whole step ahead of use
-        const float xn = rotate1<ROT>(xj, rot_src), yn = rotate1<ROT>(yj, rot_src), zn = rotate1<ROT>(zj, rot_src);
+        const float xn = rotate1<rot_coord<ROT>()>(xj, rot_src), yn = rotate1<rot_coord<ROT>()>(yj, rot_src), zn = rotate1<rot_coord<ROT>()>(zj, rot_src);
         float dx[I], dy[I], dz[I], rr[I];
 #pragma unroll
         for (int u = 0; u < I; ++u) {
@@ -1898,12 +1957,12 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
         xj = xn;
         yj = yn;
         zj = zn;
-        mj = rotate1<ROT>(mj, rot_src);
-        ljx = rotate1<ROT>(ljx, rot_src);
-        ljy = rotate1<ROT>(ljy, rot_src);
-        ljz = rotate1<ROT>(ljz, rot_src);
+        mj = rotate1<rot_coord<ROT>()>(mj, rot_src);
+        ljx = rotate1<rot_coord<ROT>()>(ljx, rot_src);
+        ljy = rotate1<rot_coord<ROT>()>(ljy, rot_src);
+        ljz = rotate1<rot_coord<ROT>()>(ljz, rot_src);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) aj[c] = rotate1<ROT>(aj[c], rot_src);
+        for (int c = 0; c < 4; ++c) aj[c] = rotate1<rot_acc<ROT>()>(aj[c], rot_src);
       }
       // j-side of this sub-block: the W waves summed in wave order, written to slot A
 #pragma unroll
@@ -1978,7 +2037,7 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_batched_kernel(const float
 // gpos += G gx, gmass += -G M. Single system: n particles (partial plane
 // stride), stride = plane stride of gpos; batched (n_sys > 0): system of particle i found
 // by binary search, its nb and partial offset from sys_nb / sys_part.
-__global__ void adjoint_reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* __restrict__ part,
+__global__ __launch_bounds__(256) void adjoint_reduce_sym(int64_t n, int64_t stride, int32_t nb, const float* __restrict__ part,
                                    double G, double* __restrict__ gpos,
                                    double* __restrict__ gmass, int64_t n_sys, const int64_t* __restrict__ sys_off,
                                    const int32_t* __restrict__ sys_nb, const int64_t* __restrict__ sys_part) {
@@ -1999,11 +2058,15 @@ __global__ void adjoint_reduce_sym(int64_t n, int64_t stride, int32_t nb, const 
     nbs = sys_nb[lo];
     ps = part + sys_part[lo];
   }
+  double g0[4];  // loaded before the sums, so that the loads are in flight together
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g0[c] = gpos[c * stride + i];
+  g0[3] = gmass[i];
   double r[4] = {0, 0, 0, 0};
   sum_slots<4>(ps, ns, li, nbs, r);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) gpos[c * stride + i] += G * r[c];
-  gmass[i] += -G * r[3];
+  for (int c = 0; c < 3; ++c) gpos[c * stride + i] = g0[c] + G * r[c];
+  gmass[i] = g0[3] + -G * r[3];
 }
 
 }  // namespace nbody
