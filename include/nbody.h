@@ -159,16 +159,21 @@ int nbody_step(const nbody_config *cfg, int64_t n, double dt, double *pos, doubl
 
 /* ---- allocation-free step ----
  * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
- * loops, harnesses that forbid hipMalloc. The same step as nbody_step (same kernels, bitwise
- * the same results) with its workspace taken from a static device array of
- * NBODY_NOALLOC_SCRATCH_BYTES per GPU, which the library holds until the process ends; the
- * library neither allocates nor frees memory in this call (the first call on a device only
- * looks up the array's device address).
+ * loops, harnesses that forbid hipMalloc. The same step as nbody_step with its workspace taken
+ * from a static device array of NBODY_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
+ * until the process ends; the library neither allocates nor frees memory in this call (the
+ * first call on a device only looks up the array's device address).
+ * Tiles: where the partial sums of the tile nbody_step would use fit the array (with 512 bytes
+ * per particle left for the rest of the step), the same tile, so bitwise the same results;
+ * otherwise the tile table's tile for the largest systems (its largest block, fewest partial
+ * sums) when that fits, else the one-sided pass with as many j-ranges as fit (workspace linear
+ * in n). Those differ from nbody_step only in the order of the floating-point sums.
  *   cfg->workspace must be NULL and cfg->workspace_bytes 0 (else NBODY_ERR_INVALID_ARG);
  *   a single system only (n_systems == 1, offsets NULL; else NBODY_ERR_UNSUPPORTED);
- *   n whose step needs more than NBODY_NOALLOC_SCRATCH_BYTES of workspace (the size
- *   nbody_workspace_size(cfg, n, 1, 0) reports: about 90 000 particles with the tuned tiles
- *   in FP32) returns NBODY_ERR_WORKSPACE before any device work.
+ *   n whose step needs more than NBODY_NOALLOC_SCRATCH_BYTES of workspace even one-sided
+ *   with one j-range (beyond about 1.9 million particles in FP64 and in the double-float and
+ *   adaptive modes, 2.5 million in the other FP32 modes) returns NBODY_ERR_WORKSPACE before
+ *   any device work.
  * Every call on one GPU shares that GPU's array (nothing in it needs to start at zero): calls
  * that overlap on one GPU (other host threads, other streams without ordering) race. */
 #define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)

@@ -383,9 +383,13 @@ Tile lookup_tile(int kernel, int prec, int64_t n);
 bool find_entry(int kernel, int prec, int64_t n, Tile& out);
 
 // Symmetric tiles keep one float slot per (particle, other block): nb * 4 * n * 4 bytes, O(n^2).
-// A single-system pass whose slots would exceed this many bytes runs one-sided instead (its
-// workspace grows as O(n)): the tuned table's symmetric entries reach this size near 1.5M particles.
+// A single-system pass whose slots would exceed the cap runs on the table's tile for the largest
+// systems (the largest block, so the fewest slots) when that fits, else one-sided (its workspace
+// grows as O(n)). The default cap is reached near 1.5M particles by the tuned table's symmetric
+// entries; the allocation-free step lowers it (on its own thread, for its own call) to what its
+// static scratch holds.
 constexpr double kSymPartCap = 16.0 * (double)(1ull << 30);
+thread_local double g_sym_cap = kSymPartCap;
 
 Tile lookup_tile_raw(int kernel, int prec, int64_t n);
 
@@ -393,7 +397,12 @@ Tile lookup_tile(int kernel, int prec, int64_t n) {
   Tile t = lookup_tile_raw(kernel, prec, n);
   const int bk = base_kernel(kernel);
   const bool single = bk == NBODY_KERNEL_FORCE || bk == NBODY_KERNEL_ADJOINT;
-  if (single && t.sym >= 0 && (double)cdiv(std::max<int64_t>(n, 1), (int64_t)t.tj) * 16.0 * (double)n > kSymPartCap) {
+  auto slot_bytes = [&](const Tile& x) { return (double)cdiv(std::max<int64_t>(n, 1), (int64_t)x.tj) * 16.0 * (double)n; };
+  if (single && t.sym >= 0 && slot_bytes(t) > g_sym_cap) {
+    if (bk == NBODY_KERNEL_FORCE) {
+      const Tile big = lookup_tile_raw(kernel, prec, (int64_t)1 << 40);
+      if (big.sym >= 0 && slot_bytes(big) <= g_sym_cap) return big;
+    }
     // the one-sided variant of the built-in defaults, one j-range per block column
     Tile o{};
     o.variant = 0;
@@ -402,6 +411,10 @@ Tile lookup_tile(int kernel, int prec, int64_t n) {
     o.j_split = 1;
     return o;
   }
+  // one-sided: the j-range partials ([S][4][n] doubles, [S][8][n] for the adjoint) under the cap
+  const double per_split = (bk == NBODY_KERNEL_ADJOINT ? 64.0 : 32.0) * (double)std::max<int64_t>(n, 1);
+  if (single && t.sym < 0 && (double)t.j_split * per_split > g_sym_cap)
+    t.j_split = std::max<int64_t>(1, (int64_t)(g_sym_cap / per_split));
   return t;
 }
 
@@ -1511,6 +1524,14 @@ __attribute__((visibility("default"))) int nbody_step_noalloc(const nbody_config
                                        "workspace_bytes 0");
   if (cfg->n_systems != 1 || cfg->offsets)
     return fail(NBODY_ERR_UNSUPPORTED, "nbody_step_noalloc serves a single system (n_systems == 1, offsets NULL)");
+  // Tiles whose partial-sum slots leave the scratch room for the rest of the step's workspace
+  // (under 512 bytes per particle): lookup_tile takes the largest-block or the one-sided tile
+  // where the tuned one does not fit. The cap holds for this thread until the call returns.
+  struct CapGuard {
+    double saved = g_sym_cap;
+    ~CapGuard() { g_sym_cap = saved; }
+  } cap_guard;
+  g_sym_cap = std::max(0.0, (double)NBODY_NOALLOC_SCRATCH_BYTES - 512.0 * (double)n);
   size_t need = 0;
   TRY(nbody_workspace_size(cfg, n, 1, 0, &need));
   if (need > (size_t)NBODY_NOALLOC_SCRATCH_BYTES)
