@@ -878,12 +878,78 @@ int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsi
   return NBODY_OK;
 }
 
-// Host staging for the batched metadata (system offsets, split counts, work
-// units): pinned host memory, reused once the previous upload has completed.
+// Host staging for the batched metadata (system offsets, split counts, work units): a ring of
+// pinned host buffers, each reused once the upload that last read it has completed (its event).
+// Calls on other streams (or devices) take other buffers, so they do not wait for each other;
+// a call waits only when every buffer of its device still feeds an upload in flight (then for the
+// oldest). The buffers are held until the process ends.
+constexpr int kStageSlots = 8;
+struct StageSlot {
+  void* buf = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;  // recorded after the slot's last upload
+  int device = -1;
+  uint64_t last_use = 0;
+  bool in_use = false;  // a call is filling it (between acquire_stage and release_stage)
+};
 std::mutex g_stage_mu;
-void* g_stage = nullptr;
-size_t g_stage_bytes = 0;
-hipEvent_t g_stage_done = nullptr;
+StageSlot g_stage[kStageSlots];
+uint64_t g_stage_clock = 0;
+
+void release_stage(StageSlot* sl);
+
+// A slot of the current device whose last upload has completed, at least `total` bytes; the
+// caller owns it until release_stage.
+int acquire_stage(size_t total, StageSlot*& out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  StageSlot* pick = nullptr;
+  bool wait = false;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    StageSlot* oldest = nullptr;
+    for (auto& sl : g_stage) {
+      if (sl.in_use || (sl.device != -1 && sl.device != dev)) continue;
+      if (sl.device == -1 || hipEventQuery(sl.done) == hipSuccess) {
+        pick = &sl;
+        break;
+      }
+      if (!oldest || sl.last_use < oldest->last_use) oldest = &sl;
+    }
+    if (!pick && !oldest)
+      return fail(NBODY_ERR_UNSUPPORTED, "host staging: all %d buffers busy or bound to other devices", kStageSlots);
+    if (!pick) {  // every free slot of this device still feeds an upload: wait for the oldest
+      pick = oldest;
+      wait = true;
+    }
+    pick->last_use = ++g_stage_clock;
+    pick->in_use = true;
+  }
+  hipError_t e = hipSuccess;
+  if (wait) e = hipEventSynchronize(pick->done);
+  if (e == hipSuccess && pick->device == -1) {
+    e = hipEventCreateWithFlags(&pick->done, hipEventDisableTiming);
+    if (e == hipSuccess) pick->device = dev;
+  }
+  if (e == hipSuccess && total > pick->bytes) {
+    if (pick->buf) e = hipHostFree(pick->buf);
+    pick->buf = nullptr;
+    pick->bytes = 0;
+    if (e == hipSuccess) e = hipHostMalloc(&pick->buf, total, hipHostMallocDefault);
+    if (e == hipSuccess) pick->bytes = total;
+  }
+  if (e != hipSuccess) {
+    release_stage(pick);
+    return fail(NBODY_ERR_DEVICE, "host staging: %s", hipGetErrorString(e));
+  }
+  out = pick;
+  return NBODY_OK;
+}
+
+void release_stage(StageSlot* sl) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  sl->in_use = false;
+}
 
 int upload_meta(Ctx& c) {
   if (!c.bat || c.loop) return NBODY_OK;
@@ -898,17 +964,13 @@ int upload_meta(Ctx& c) {
   const size_t b_ro = c.uf.sym ? c.uf.ro_units.size() * sizeof(SymUnit) : 0;
   const size_t total = align_up(b_off) + align_up(b_ns) + align_up(b_poff) + align_up(b_units) + align_up(b_uadj) +
                        align_up(b_poffa) + align_up(b_rt) + align_up(b_ro);
-  std::lock_guard<std::mutex> lk(g_stage_mu);
-  if (g_stage_done) HIP_TRY(hipEventSynchronize(g_stage_done));  // previous upload has read the staging
-  if (total > g_stage_bytes) {
-    if (g_stage) HIP_TRY(hipHostFree(g_stage));
-    g_stage = nullptr;
-    g_stage_bytes = 0;
-    HIP_TRY(hipHostMalloc(&g_stage, total, hipHostMallocDefault));
-    g_stage_bytes = total;
-  }
-  if (!g_stage_done) HIP_TRY(hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming));
-  char* h = (char*)g_stage;
+  StageSlot* slot = nullptr;
+  TRY(acquire_stage(total, slot));
+  struct Release {
+    StageSlot* s;
+    ~Release() { release_stage(s); }
+  } release{slot};
+  char* h = (char*)slot->buf;
   int64_t* h_off = (int64_t*)h;
   int32_t* h_ns = (int32_t*)(h + align_up(b_off));
   int64_t* h_poff = (int64_t*)(h + align_up(b_off) + align_up(b_ns));
@@ -939,7 +1001,7 @@ int upload_meta(Ctx& c) {
     HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_partoff_adj, h_poffa, b_poffa, hipMemcpyHostToDevice, c.st));
   if (b_rt) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_rtasks, h_rt, b_rt, hipMemcpyHostToDevice, c.st));
   if (b_ro) HIP_TRY(hipMemcpyAsync(c.ws + c.plan.off_units_ro, h_ro, b_ro, hipMemcpyHostToDevice, c.st));
-  HIP_TRY(hipEventRecord(g_stage_done, c.st));
+  HIP_TRY(hipEventRecord(slot->done, c.st));
   return NBODY_OK;
 }
 
