@@ -807,7 +807,7 @@ def cpu_baseline(np, s, eps, target_s=12.0):
                       "restricted to the sample), %.1f s" % (k2, s.n, t2),
             "value_1_thread": k1 * float(s.n) / t3, "sample_1_thread": "%d particles, %.1f s" % (k1, t3),
             "host_cpus_visible": os.cpu_count(), "cpu_model": model,
-            "build": "gcc -O2 -fopenmp (oracle/__init__.py), OpenMP over target particles"}
+            "build": "gcc -O3 -march=x86-64-v3 -fopenmp -ffp-contract=off -fno-fast-math (oracle/__init__.py), OpenMP over target particles"}
 
 
 if __name__ == "__main__":
