@@ -1174,7 +1174,7 @@ int adapt_sym_pass(Ctx& c, const Tile& t, double* acc, double* pot, double* vel,
     sv.afn[c.law][pot != nullptr](dim3((unsigned)off_tiles), c.st, jhi, n, (int32_t)nb, (float)c.eps2, pf, ad);
     LAUNCH_CHECK("force_sym_kernel (adaptive)");
   }
-  hipLaunchKernelGGL(reduce_sym, grid1d(n), dim3(kReduceBS), 0, c.st, n, n, (int32_t)nb, (const float*)pf, c.ls, acc,
+  hipLaunchKernelGGL(reduce_sym, grid1d(n, 64), dim3(kReduceBS), 0, c.st, n, n, (int32_t)nb, (const float*)pf, c.ls, acc,
                      pot, vel, hh, nx ? *nx : NextStep{}, EnergyFuse{}, (const uint32_t*)perm);
   LAUNCH_CHECK("reduce_sym");
   return tail();
@@ -1240,7 +1240,9 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
       sv.fn[law][pot_on][mode](dim3((unsigned)tiles), c.st, (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b, ns,
                                (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("force_sym_kernel");
-      hipLaunchKernelGGL(reduce_sym, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n, (int32_t)nb, (const float*)pf,
+      // reduce_sym: the energy's chunk grid, else blocks of four waves for 64 particles
+      hipLaunchKernelGGL(reduce_sym, ef.part ? rgrid(ns) : grid1d(ns, 64), dim3(kReduceBS), 0, c.st, ns,
+                         n, (int32_t)nb, (const float*)pf,
                          c.ls_at(b), acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh,
                          next_step_at(c, nx, b), ef, (const uint32_t*)nullptr);
       LAUNCH_CHECK("reduce_sym");

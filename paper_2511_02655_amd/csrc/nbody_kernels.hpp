@@ -1223,27 +1223,87 @@ __device__ __forceinline__ void sum_slots(const float* __restrict__ part, int64_
   }
 }
 
+// The single-system slot sums in four interleaved groups: group g of the particle at offset i
+// sums slots g, g + 4, g + 8, ... (< nb) in order, in double; the particle's sum is then
+// (p0 + p1) + (p2 + p3). The loads of K slots of the group are issued before their additions;
+// slots past nb in the last round are loaded from a valid slot and replaced by +0.0 (exact, as in
+// sum_slots).
+template <int NC, int K = 16>
+__device__ __forceinline__ void sum_slot_group(const float* __restrict__ part, int64_t n, int64_t i, int32_t nb,
+                                               int g, double p[4]) {
+  for (int32_t s0 = g; s0 < nb; s0 += 4 * K) {
+    float v[K][NC];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int32_t s = s0 + 4 * k;
+        const float x = part[((int64_t)(s < nb ? s : s0) * 4 + c) * n + i];
+        v[k][c] = s < nb ? x : 0.f;
+      }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) p[c] += (double)v[k][c];
+  }
+}
+
 // perm (nullable): the slot planes are in sorted order (the adaptive mode) and position p
 // holds particle perm[p], whose outputs are written at its own index.
+// Without the energy: blocks of four waves for 64 positions, wave g summing slot group g; wave 0
+// adds the four groups and finishes the particle (a grid of ceil(n / 64) blocks: four times the
+// waves of one thread per particle, a quarter of the dependent loads each, which at small n,
+// where the sum is bound by memory round trips, takes most of its time away).
+// With the energy fused: one thread per particle sums the four groups in turn, the same sums
+// in the same order (so trajectories do not depend on whether the energy is traced).
 __global__ __launch_bounds__(kReduceBS) void reduce_sym(int64_t n, int64_t stride, int32_t nb,
                                                        const float* __restrict__ part, LawScale ls,
                                                        double* __restrict__ acc, double* __restrict__ pot,
                                                        double* __restrict__ vel, double hh, NextStep nx,
                                                        EnergyFuse ef, const uint32_t* __restrict__ perm) {
-  auto body = [&](int64_t p, double* en) {
-    const int64_t i = perm ? (int64_t)perm[p] : p;
-    const PState ps = load_state(i, stride, ls, vel, nx, ef.mass, en != nullptr);
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    if (pot) sum_slots<4>(part, n, p, nb, a);
-    else sum_slots<3>(part, n, p, nb, a);
-    finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, en, ps);
-  };
+  static_assert(kReduceBS == 256, "four waves of 64 positions");
   if (ef.part) {  // grid (chunks, 1)
-    energy_chunk(0, n, 0, ef, body);
+    energy_chunk(0, n, 0, ef, [&](int64_t p, double* en) {
+      const int64_t i = perm ? (int64_t)perm[p] : p;
+      const PState ps = load_state(i, stride, ls, vel, nx, ef.mass, en != nullptr);
+      double q[4][4] = {};
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        if (pot) sum_slot_group<4>(part, n, p, nb, g, q[g]);
+        else sum_slot_group<3>(part, n, p, nb, g, q[g]);
+      }
+      double a[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c] = (q[0][c] + q[1][c]) + (q[2][c] + q[3][c]);
+      finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, en, ps);
+    });
     return;
   }
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) body(i, nullptr);
+  __shared__ double sh[3][4][64];
+  const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = p < n;
+  int64_t i = 0;
+  PState ps{};
+  if (g == 0 && live) {
+    i = perm ? (int64_t)perm[p] : p;
+    ps = load_state(i, stride, ls, vel, nx, ef.mass, false);
+  }
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    if (pot) sum_slot_group<4>(part, n, p, nb, g, q);
+    else sum_slot_group<3>(part, n, p, nb, g, q);
+  }
+  if (g > 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sh[g - 1][c][lane] = q[c];
+  __syncthreads();
+  if (g == 0 && live) {
+    double a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = (q[c] + sh[0][c][lane]) + (sh[1][c][lane] + sh[2][c][lane]);
+    finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, nullptr, ps);
+  }
 }
 
 // ----------------------------------------------------------------- batched symmetric pass
