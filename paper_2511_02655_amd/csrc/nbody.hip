@@ -1394,10 +1394,9 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
       const float4* ja = (const float4*)jadj + 2 * b;
       sv.fn[comp](dim3((unsigned)tiles), c.st, ja, ns, (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("adjoint_sym_kernel");
-      hipLaunchKernelGGL(adjoint_reduce_sym, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)nb, (const float*)pf,
-                         c.cfg->G, gpos + b, gmass + b, (int64_t)0, (const int64_t*)nullptr, (const int32_t*)nullptr,
-                         (const int64_t*)nullptr);
-      LAUNCH_CHECK("adjoint_reduce_sym");
+      hipLaunchKernelGGL(adjoint_reduce_sym_groups, grid1d(ns, 64), dim3(256), 0, c.st, ns, n, (int32_t)nb,
+                         (const float*)pf, c.cfg->G, gpos + b, gmass + b);
+      LAUNCH_CHECK("adjoint_reduce_sym_groups");
       return NBODY_OK;
     }
     int64_t S, jc;

@@ -1248,13 +1248,37 @@ __device__ __forceinline__ void sum_slot_group(const float* __restrict__ part, i
   }
 }
 
+// All four groups in one thread: the slots in order, K at a time (K a multiple of 4), slot s
+// added to group s mod 4 - the same four sums as sum_slot_group, with the loads of K slots in
+// flight together.
+template <int NC, int K = 32>
+__device__ __forceinline__ void sum_slot_groups(const float* __restrict__ part, int64_t n, int64_t i, int32_t nb,
+                                                double p[4][4]) {
+  static_assert(K % 4 == 0, "whole groups per round");
+  for (int32_t s0 = 0; s0 < nb; s0 += K) {
+    float v[K][NC];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int32_t s = s0 + k;
+        const float x = part[((int64_t)(s < nb ? s : s0) * 4 + c) * n + i];
+        v[k][c] = s < nb ? x : 0.f;
+      }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) p[k & 3][c] += (double)v[k][c];
+  }
+}
+
 // perm (nullable): the slot planes are in sorted order (the adaptive mode) and position p
 // holds particle perm[p], whose outputs are written at its own index.
 // Without the energy: blocks of four waves for 64 positions, wave g summing slot group g; wave 0
 // adds the four groups and finishes the particle (a grid of ceil(n / 64) blocks: four times the
 // waves of one thread per particle, a quarter of the dependent loads each, which at small n,
 // where the sum is bound by memory round trips, takes most of its time away).
-// With the energy fused: one thread per particle sums the four groups in turn, the same sums
+// With the energy fused: one thread per particle sums the four groups together, the same sums
 // in the same order (so trajectories do not depend on whether the energy is traced).
 __global__ __launch_bounds__(kReduceBS) void reduce_sym(int64_t n, int64_t stride, int32_t nb,
                                                        const float* __restrict__ part, LawScale ls,
@@ -1267,11 +1291,8 @@ __global__ __launch_bounds__(kReduceBS) void reduce_sym(int64_t n, int64_t strid
       const int64_t i = perm ? (int64_t)perm[p] : p;
       const PState ps = load_state(i, stride, ls, vel, nx, ef.mass, en != nullptr);
       double q[4][4] = {};
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        if (pot) sum_slot_group<4>(part, n, p, nb, g, q[g]);
-        else sum_slot_group<3>(part, n, p, nb, g, q[g]);
-      }
+      if (pot) sum_slot_groups<4>(part, n, p, nb, q);
+      else sum_slot_groups<3>(part, n, p, nb, q);
       double a[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) a[c] = (q[0][c] + q[1][c]) + (q[2][c] + q[3][c]);
@@ -2127,6 +2148,38 @@ __global__ __launch_bounds__(256) void adjoint_reduce_sym(int64_t n, int64_t str
 #pragma unroll
   for (int c = 0; c < 3; ++c) gpos[c * stride + i] = g0[c] + G * r[c];
   gmass[i] = g0[3] + -G * r[3];
+}
+
+// The single-system form: four waves per 64 particles, wave g summing slot group g (as in
+// reduce_sym); wave 0 adds the groups, (p0 + p1) + (p2 + p3), and updates the gradients.
+__global__ __launch_bounds__(256) void adjoint_reduce_sym_groups(int64_t n, int64_t stride, int32_t nb,
+                                                                const float* __restrict__ part, double G,
+                                                                double* __restrict__ gpos,
+                                                                double* __restrict__ gmass) {
+  __shared__ double sh[3][4][64];
+  const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = i < n;
+  double g0[4] = {0.0, 0.0, 0.0, 0.0};
+  if (g == 0 && live) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g0[c] = gpos[c * stride + i];
+    g0[3] = gmass[i];
+  }
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  if (live) sum_slot_group<4>(part, n, i, nb, g, q);
+  if (g > 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sh[g - 1][c][lane] = q[c];
+  __syncthreads();
+  if (g == 0 && live) {
+    double r[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) r[c] = (q[c] + sh[0][c][lane]) + (sh[1][c][lane] + sh[2][c][lane]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gpos[c * stride + i] = g0[c] + G * r[c];
+    gmass[i] = g0[3] + -G * r[3];
+  }
 }
 
 }  // namespace nbody
