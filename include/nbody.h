@@ -110,6 +110,20 @@ typedef enum {
 #define NBODY_FLAG_PER_PASS 4u      /* batched rollouts: one launch per pass even where
                                       every step in one launch would be chosen (the
                                       baseline of that choice; results are identical) */
+#define NBODY_FLAG_SYM_ROUNDS 8u    /* single-system FP32 force passes on the round schedule:
+                                      symmetric tiles of 1024-particle blocks run in rounds
+                                      of disjoint block pairs (circle method), K consecutive
+                                      rounds per launch (K = 4 where the workspace allows,
+                                      else 2 or 1), each tile adding its sums to per-particle
+                                      double accumulators (K copies, one per round of a
+                                      launch), so the workspace is linear in n (32 K bytes
+                                      per particle for the sums) instead of one float slot
+                                      per particle and block. Deterministic for a given K;
+                                      not bitwise the slot schedule's sums (another order).
+                                      The library takes this schedule by itself where the
+                                      slot schedule's partial sums would exceed its cap
+                                      (16 GiB, near 1.5 million particles). The adaptive mode
+                                      runs as the double-float mode on it (no sort). */
 
 typedef struct {
   int32_t abi_version;     /* must equal NBODY_ABI_VERSION */
@@ -163,17 +177,18 @@ int nbody_step(const nbody_config *cfg, int64_t n, double dt, double *pos, doubl
  * from a static device array of NBODY_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
  * until the process ends; the library neither allocates nor frees memory in this call (the
  * first call on a device only looks up the array's device address).
- * Tiles: where the partial sums of the tile nbody_step would use fit the array (with 512 bytes
- * per particle left for the rest of the step), the same tile, so bitwise the same results;
- * otherwise the tile table's tile for the largest systems (its largest block, fewest partial
- * sums) when that fits, else the one-sided pass with as many j-ranges as fit (workspace linear
- * in n). Those differ from nbody_step only in the order of the floating-point sums.
+ * Tiles: the first of these whose whole workspace fits the array: the tile nbody_step would use
+ * (bitwise the same results); the tile table's tile for the largest systems (its largest block,
+ * fewest partial sums); the round schedule (NBODY_FLAG_SYM_ROUNDS: workspace linear in n); the
+ * one-sided pass with as many j-ranges as fit (FP64, which has no symmetric tiles, takes its
+ * tuned tile or this one). The later ones differ from nbody_step only in the order of the
+ * floating-point sums.
  *   cfg->workspace must be NULL and cfg->workspace_bytes 0 (else NBODY_ERR_INVALID_ARG);
  *   a single system only (n_systems == 1, offsets NULL; else NBODY_ERR_UNSUPPORTED);
  *   n whose step needs more than NBODY_NOALLOC_SCRATCH_BYTES of workspace even one-sided
  *   with one j-range (beyond about 1.9 million particles in FP64 and in the double-float and
- *   adaptive modes, 2.5 million in the other FP32 modes) returns NBODY_ERR_WORKSPACE before
- *   any device work.
+ *   adaptive modes, 2.5 million in the other FP32 modes; the round schedule serves up to about
+ *   1.33 and 1.58 million) returns NBODY_ERR_WORKSPACE before any device work.
  * Every call on one GPU shares that GPU's array (nothing in it needs to start at zero): calls
  * that overlap on one GPU (other host threads, other streams without ordering) race. */
 #define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)

@@ -29,6 +29,7 @@ KERNELS = {"force": 0, "adjoint": 1, "force_batched": 2, "adjoint_batched": 3, "
 FLAG_LOOP_SYSTEMS = 1
 FLAG_WHOLE_ROLLOUT = 2  # batched symmetric rollouts: every step in one launch
 FLAG_PER_PASS = 4  # batched rollouts: one launch per pass even where one launch for all steps is chosen
+FLAG_SYM_ROUNDS = 8  # single-system FP32 force passes on the round schedule (workspace linear in n)
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DEVICE", 3: "UNSUPPORTED", 4: "WORKSPACE"}
 
 EXPORTED = ("nbody_abi_version", "nbody_last_error", "nbody_workspace_size", "nbody_forces", "nbody_step",

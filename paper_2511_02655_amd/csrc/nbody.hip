@@ -179,6 +179,30 @@ void launch_rollout(dim3 g, hipStream_t st, const float4* jarr, const SymUnit* u
 }
 template <int W, int I, int MODE, int ROT, int LAW, int PIPE>
 const void* rollout_ptr() { return (const void*)&rollout_sym_batched_kernel<W, I, MODE, ROT, LAW, PIPE>; }
+// The round schedule (single systems, workspace linear in n) on one fixed tile: 4 waves, 4
+// particles per lane, 1024-particle blocks, LDS-crossbar rotation - at the sizes that need it
+// (beyond ~1.5M particles) a round holds ~750-1000 tiles, and a launch of K rounds K times that.
+constexpr int kRoundW = 4, kRoundI = 4, kRoundBlock = kRoundW * 64 * kRoundI;
+// Rounds per launch (accumulator copies, 32 bytes per particle each): 4 where the copies and a
+// margin of 128 bytes per particle for the rest of the workspace fit the partial-sum cap, else 2,
+// else 1.
+int round_copies(int64_t n, double cap) {
+  const double nn = (double)std::max<int64_t>(n, 1);
+  for (int k : {4, 2})
+    if ((32.0 * k + 128.0) * nn <= cap) return k;
+  return 1;
+}
+using RoundFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, int32_t nbr, int32_t r,
+                         float eps2, double* acc64);
+template <bool POT, int MODE, int LAW>
+void launch_round(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, int32_t nbr, int32_t r, float eps2,
+                  double* acc64) {
+  hipLaunchKernelGGL((force_sym_round_kernel<kRoundW, kRoundI, POT, MODE, 1, LAW, 0>), g, dim3(kRoundW * 64), 0, st,
+                     jarr, n, nb, nbr, r, eps2, acc64);
+}
+#define RND_POT(POT, LAW) \
+  { launch_round<POT, 0, LAW>, launch_round<POT, 1, LAW>, launch_round<POT, 2, LAW> }
+const RoundFn kRound[2][2][3] = {{RND_POT(false, 0), RND_POT(true, 0)}, {RND_POT(false, 1), RND_POT(true, 1)}};
 struct SymVariant {
   int w, i, rot;      // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
   int pipe;           // coordinate rotation issued after phase 1 (0) or a step ahead (1)
@@ -330,6 +354,7 @@ struct Tile {
   int bs, i, tj;
   int64_t j_split;  // single: number of j-ranges; batched: j-chunk length
   int sym = -1;     // symmetric variant index (single-system FP32 force only)
+  bool rounds = false;  // single-system FP32 force on the round schedule (workspace linear in n)
 };
 
 int g_num_cu = 0;
@@ -383,25 +408,42 @@ Tile lookup_tile(int kernel, int prec, int64_t n);
 bool find_entry(int kernel, int prec, int64_t n, Tile& out);
 
 // Symmetric tiles keep one float slot per (particle, other block): nb * 4 * n * 4 bytes, O(n^2).
-// A single-system pass whose slots would exceed the cap runs on the table's tile for the largest
-// systems (the largest block, so the fewest slots) when that fits, else one-sided (its workspace
-// grows as O(n)). The default cap is reached near 1.5M particles by the tuned table's symmetric
-// entries; the allocation-free step lowers it (on its own thread, for its own call) to what its
-// static scratch holds.
+// A single-system force pass whose slots would exceed the cap runs on the table's tile for the
+// largest systems (the largest block, so the fewest slots) when that fits, else on the round
+// schedule (4 doubles per particle) when that fits, else one-sided (no partial sums with one
+// j-range); an adjoint pass runs one-sided. The default cap is reached near 1.5M particles by the
+// tuned table's symmetric entries. The allocation-free step (on its own thread, for its own call)
+// sets the cap to its static scratch and a level that skips the first choices of that order:
+// 1 starts at the largest block, 2 at the round schedule, 3 at the one-sided pass.
 constexpr double kSymPartCap = 16.0 * (double)(1ull << 30);
 thread_local double g_sym_cap = kSymPartCap;
+thread_local int g_sym_level = 0;
 
 Tile lookup_tile_raw(int kernel, int prec, int64_t n);
+
+// A single-system force pass on the round schedule (the fields a one-sided tile would have, so
+// no path mistakes it for the slot schedule).
+Tile rounds_tile(int kernel, int prec) {
+  Tile r{};
+  r.variant = 0;
+  r.sym = -1;
+  variant_shape(kernel, prec, 0, r.bs, r.i, r.tj);
+  r.j_split = 1;
+  r.rounds = true;
+  return r;
+}
 
 Tile lookup_tile(int kernel, int prec, int64_t n) {
   Tile t = lookup_tile_raw(kernel, prec, n);
   const int bk = base_kernel(kernel);
   const bool single = bk == NBODY_KERNEL_FORCE || bk == NBODY_KERNEL_ADJOINT;
   auto slot_bytes = [&](const Tile& x) { return (double)cdiv(std::max<int64_t>(n, 1), (int64_t)x.tj) * 16.0 * (double)n; };
-  if (single && t.sym >= 0 && slot_bytes(t) > g_sym_cap) {
+  if (single && t.sym >= 0 && (g_sym_level > 0 || slot_bytes(t) > g_sym_cap)) {
     if (bk == NBODY_KERNEL_FORCE) {
       const Tile big = lookup_tile_raw(kernel, prec, (int64_t)1 << 40);
-      if (big.sym >= 0 && slot_bytes(big) <= g_sym_cap) return big;
+      if (g_sym_level <= 1 && big.sym >= 0 && slot_bytes(big) <= g_sym_cap) return big;
+      // the round schedule's accumulators: 4 doubles per particle
+      if (g_sym_level <= 2 && 32.0 * (double)std::max<int64_t>(n, 1) <= g_sym_cap) return rounds_tile(kernel, prec);
     }
     // the one-sided variant of the built-in defaults, one j-range per block column
     Tile o{};
@@ -416,6 +458,13 @@ Tile lookup_tile(int kernel, int prec, int64_t n) {
   if (single && t.sym < 0 && (double)t.j_split * per_split > g_sym_cap)
     t.j_split = std::max<int64_t>(1, (int64_t)(g_sym_cap / per_split));
   return t;
+}
+
+// The tile of a single-system force pass under cfg: NBODY_FLAG_SYM_ROUNDS puts every FP32 pass on
+// the round schedule.
+Tile single_force_tile(const nbody_config* cfg, int kernel, int prec, int64_t n) {
+  if ((cfg->flags & NBODY_FLAG_SYM_ROUNDS) && !is_fp64(prec)) return rounds_tile(kernel, prec);
+  return lookup_tile(kernel, prec, n);
 }
 
 Tile lookup_tile_raw(int kernel, int prec, int64_t n) {
@@ -486,7 +535,7 @@ int check_cfg(const nbody_config* cfg, int64_t n, Systems& sys, bool law_checks 
       return fail(NBODY_ERR_INVALID_ARG, "eps must be >= 1e-10 for the FP32 modes (got %g)", cfg->eps);
   }
   if (cfg->reserved != 0) return fail(NBODY_ERR_INVALID_ARG, "reserved must be 0");
-  if (cfg->flags & ~(NBODY_FLAG_LOOP_SYSTEMS | NBODY_FLAG_WHOLE_ROLLOUT | NBODY_FLAG_PER_PASS))
+  if (cfg->flags & ~(NBODY_FLAG_LOOP_SYSTEMS | NBODY_FLAG_WHOLE_ROLLOUT | NBODY_FLAG_PER_PASS | NBODY_FLAG_SYM_ROUNDS))
     return fail(NBODY_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
   if (n < 0) return fail(NBODY_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)n);
   if (n > ((int64_t)1 << 31)) return fail(NBODY_ERR_UNSUPPORTED, "n = %lld exceeds 2^31", (long long)n);
@@ -665,6 +714,8 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
   UnitSet& uas = ua ? *ua : local_a;
   // partial sums of one system of ns particles under tile t (0 when written directly)
   auto single_force_part = [&](const Tile& t, int64_t ns) -> size_t {
+    if (t.rounds)  // the round schedule's accumulator copies
+      return (size_t)round_copies(ns, g_sym_cap) * 4 * (size_t)ns * sizeof(double);
     if (t.sym >= 0) {
       const int64_t nb = cdiv(ns, (int64_t)t.tj);
       return (size_t)nb * 4 * (size_t)ns * sizeof(float);
@@ -731,13 +782,15 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
       int64_t ns = sys.off[s + 1] - sys.off[s];
       if (ns == 0) continue;
       for (int lw : {LAW_GRAV, LAW_LJ})
-        force_part = std::max(force_part, single_force_part(lookup_tile(force_kernel_id(lw, false), prec, ns), ns));
+        force_part =
+            std::max(force_part, single_force_part(single_force_tile(cfg, force_kernel_id(lw, false), prec, ns), ns));
       if (need & NEED_BACKWARD)
         adj_part = std::max(adj_part, single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns), ns));
     }
   } else {
     for (int lw : {LAW_GRAV, LAW_LJ})
-      force_part = std::max(force_part, single_force_part(lookup_tile(force_kernel_id(lw, false), prec, n), n));
+      force_part =
+          std::max(force_part, single_force_part(single_force_tile(cfg, force_kernel_id(lw, false), prec, n), n));
     if (need & NEED_BACKWARD) adj_part = single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, n), n);
   }
   p.sz_jbuf = (size_t)n * std::max(jvec_bytes(prec), (need & NEED_BACKWARD) ? jadj_bytes(prec) : (size_t)0);
@@ -746,7 +799,8 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
   p.off_part = take(p.sz_part);
   // the adaptive mode sorts a single system whose force pass runs on symmetric tiles
   p.adapt = is_adapt(prec) && !bat && n > 0 &&
-            (lookup_tile(NBODY_KERNEL_FORCE, prec, n).sym >= 0 || lookup_tile(NBODY_KERNEL_LJ_FORCE, prec, n).sym >= 0);
+            (single_force_tile(cfg, NBODY_KERNEL_FORCE, prec, n).sym >= 0 ||
+             single_force_tile(cfg, NBODY_KERNEL_LJ_FORCE, prec, n).sym >= 0);
   if (p.adapt) {
     int64_t P = kBitonicLocal;
     while (P < n) P <<= 1;
@@ -866,7 +920,7 @@ int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsi
   c.bat = c.sys.S > 1;
   c.loop = c.bat && (cfg->flags & NBODY_FLAG_LOOP_SYSTEMS);
   TRY(make_plan(cfg, c.sys, n, ckpt_every, need, c.plan, &c.uf, &c.ua, c.law));
-  c.adapt = c.plan.adapt && lookup_tile(force_kernel_id(c.law, false), cfg->precision, n).sym >= 0;
+  c.adapt = c.plan.adapt && single_force_tile(cfg, force_kernel_id(c.law, false), cfg->precision, n).sym >= 0;
   if (n == 0) return NBODY_OK;
   if (!cfg->workspace) return fail(NBODY_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", c.plan.total);
   if (((uintptr_t)cfg->workspace) % kAlign)
@@ -1228,7 +1282,33 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
   auto single = [&](int64_t b, int64_t e) -> int {
     const int64_t ns = e - b;
     if (ns == 0) return NBODY_OK;
-    Tile t = lookup_tile(force_kernel_id(law, false), prec, ns);
+    Tile t = single_force_tile(c.cfg, force_kernel_id(law, false), prec, ns);
+    if (t.rounds) {
+      // round schedule: zero the K accumulator copies, the diagonal tiles, then nbr - 1 rounds
+      // of disjoint block pairs, K per launch, then the per-particle end (copies added, scale,
+      // kick, next step, energy)
+      const int64_t nb = cdiv(ns, (int64_t)kRoundBlock), nbr = nb + (nb & 1);
+      if (nbr > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many blocks for the round schedule");
+      const int K = round_copies(ns, g_sym_cap);
+      TRY(check_part(c, (size_t)K * 4 * ns * sizeof(double), "force_sym_round_kernel"));
+      double* a64 = (double*)(c.ws + c.plan.off_part);
+      hipLaunchKernelGGL(fill_f64, grid1d(K * 4 * ns), dim3(256), 0, c.st, a64, K * 4 * ns, 0.0);
+      LAUNCH_CHECK("fill_f64");
+      const float4* jb = (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b;
+      const RoundFn fn = kRound[law][pot_on][mode];
+      fn(dim3((unsigned)nb), c.st, jb, ns, (int32_t)nb, (int32_t)nbr, -1, (float)eps2, a64);
+      LAUNCH_CHECK("force_sym_round_kernel (diagonal tiles)");
+      for (int64_t r = 0; r + 1 < nbr; r += K) {
+        const unsigned ky = (unsigned)std::min<int64_t>(K, nbr - 1 - r);
+        fn(dim3((unsigned)(nbr / 2), ky), c.st, jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, (float)eps2, a64);
+        LAUNCH_CHECK("force_sym_round_kernel");
+      }
+      hipLaunchKernelGGL(reduce_rounds, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n, (const double*)a64, (int32_t)K,
+                         c.ls_at(b),
+                         acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, next_step_at(c, nx, b), ef);
+      LAUNCH_CHECK("reduce_rounds");
+      return fused_tail();
+    }
     if (t.sym >= 0 && c.adapt) return adapt_sym_pass(c, t, acc, pot, vel, hh, nx, fused_tail);
     if (t.sym >= 0) {
       const SymVariant& sv = kSym32[t.sym];
@@ -1587,16 +1667,26 @@ __attribute__((visibility("default"))) int nbody_step_noalloc(const nbody_config
                                        "workspace_bytes 0");
   if (cfg->n_systems != 1 || cfg->offsets)
     return fail(NBODY_ERR_UNSUPPORTED, "nbody_step_noalloc serves a single system (n_systems == 1, offsets NULL)");
-  // Tiles whose partial-sum slots leave the scratch room for the rest of the step's workspace
-  // (under 512 bytes per particle): lookup_tile takes the largest-block or the one-sided tile
-  // where the tuned one does not fit. The cap holds for this thread until the call returns.
+  // The first plan of the order tuned tile, largest-block tile, round schedule, one-sided pass
+  // whose whole workspace fits the scratch (for the last, j-range partials that leave room for
+  // the rest of the workspace, at most 128 bytes per particle). Cap and level hold for this
+  // thread until the call returns.
   struct CapGuard {
-    double saved = g_sym_cap;
-    ~CapGuard() { g_sym_cap = saved; }
+    double cap = g_sym_cap;
+    int level = g_sym_level;
+    ~CapGuard() {
+      g_sym_cap = cap;
+      g_sym_level = level;
+    }
   } cap_guard;
-  g_sym_cap = std::max(0.0, (double)NBODY_NOALLOC_SCRATCH_BYTES - 512.0 * (double)n);
+  const double total = (double)NBODY_NOALLOC_SCRATCH_BYTES;
   size_t need = 0;
-  TRY(nbody_workspace_size(cfg, n, 1, 0, &need));
+  for (int level = 0; level < 4; ++level) {
+    g_sym_level = level;
+    g_sym_cap = level < 3 ? total : std::max(0.0, total - 128.0 * (double)n);
+    TRY(nbody_workspace_size(cfg, n, 1, 0, &need));
+    if (need <= (size_t)NBODY_NOALLOC_SCRATCH_BYTES) break;
+  }
   if (need > (size_t)NBODY_NOALLOC_SCRATCH_BYTES)
     return fail(NBODY_ERR_WORKSPACE, "n = %lld needs %zu bytes of scratch; the static scratch of "
                                      "nbody_step_noalloc holds %zu (use nbody_step with a workspace)",

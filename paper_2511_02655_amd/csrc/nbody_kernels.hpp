@@ -747,10 +747,15 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 // potential variant). The double-float loops take part of a lane's i-particles at a time
 // (the j-particles come home after 64 steps), so they need no more registers than the float
 // loop.
-template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE = 0>
+//
+// OUT 1 (the round schedule): instead of writing slots, the tile adds its i-side and j-side sums
+// to per-particle double accumulators acc64 [4][n]; the caller runs only tiles whose blocks no
+// other running tile touches.
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE = 0, int OUT = 0>
 __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_t n, int32_t A, int32_t B,
                                          float eps2_arg, float* __restrict__ part,
-                                         float (&red)[2][W][POT ? 4 : 3][64], AdaptIn ad = AdaptIn{}) {
+                                         float (&red)[2][W][POT ? 4 : 3][64], AdaptIn ad = AdaptIn{},
+                                         double* __restrict__ acc64 = nullptr) {
   constexpr bool COMP = MODE != MODE_PLAIN;
   constexpr bool DS = MODE == MODE_DS;
   constexpr bool ADAPT_OFF = MODE == MODE_ADAPT;        // adaptive, off-diagonal tiles only
@@ -1145,7 +1150,11 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
 #pragma unroll
         for (int ww = 0; ww < W; ++ww) sum += red[sb & 1][ww][c][l];
         const int64_t j = Bbase + (int64_t)sb * 64 + l;
-        if (j < n) part[((int64_t)A * 4 + c) * n + j] = sum;
+        if constexpr (OUT == 0) {
+          if (j < n) part[((int64_t)A * 4 + c) * n + j] = sum;
+        } else {
+          if (j < n) acc64[(int64_t)c * n + j] += (double)sum;
+        }
       }
     }
     if (COMP) {
@@ -1168,9 +1177,14 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
     const int64_t i = Abase + (int64_t)w * 64 * I + u * 64 + lane;
     if (i < n)
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        part[((int64_t)B * 4 + c) * n + i] =
-            COMP ? hi[c][u] + (LO_LDS ? lo_w[(c * I + u) * 64] : lo[c][u]) : ai[c][u];
+      for (int c = 0; c < NC; ++c) {
+        if constexpr (OUT == 0)
+          part[((int64_t)B * 4 + c) * n + i] =
+              COMP ? hi[c][u] + (LO_LDS ? lo_w[(c * I + u) * 64] : lo[c][u]) : ai[c][u];
+        else
+          acc64[(int64_t)c * n + i] +=
+              COMP ? (double)hi[c][u] + (double)(LO_LDS ? lo_w[(c * I + u) * 64] : lo[c][u]) : (double)ai[c][u];
+      }
   }
 }
 
@@ -1189,6 +1203,70 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
     tile_rc(blockIdx.x, nb, A, B);
   }
   sym_tile<W, I, POT, MODE, ROT, LAW, PIPE>(jarr, n, A, B, eps2_arg, part, red, ad);
+}
+
+// The round schedule of the symmetric pass (workspace linear in n). Round r in [0, nbr - 2] is
+// the circle-method pairing of nbr (even) blocks: tile t pairs (r, nbr - 1) for t = 0 and
+// ((r + t) mod (nbr - 1), (r - t) mod (nbr - 1)) for t > 0, so every unordered pair of blocks
+// meets in exactly one round and the tiles of a round touch disjoint blocks. The sums go to K
+// copies of [4][n] double accumulators (zeroed first): round r adds to copy r mod K, so the K
+// rounds r0 .. r0 + K - 1 run in one launch (grid (nbr / 2, K), blockIdx.y = r - r0) without two
+// tiles touching the same accumulator. r0 < 0 runs every diagonal tile (A, A), one workgroup per
+// block, into copy 0 before any round. Every accumulator takes its tiles in a fixed order, so
+// the result is deterministic for a given K. A pair with the padding block nb (odd nb) is
+// skipped.
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
+__global__ __launch_bounds__(W * 64) void force_sym_round_kernel(const float4* __restrict__ jarr, int64_t n,
+                                                                 int32_t nb, int32_t nbr, int32_t r0,
+                                                                 float eps2_arg, double* __restrict__ acc64) {
+  __shared__ float red[2][W][POT ? 4 : 3][64];
+  int32_t A, B;
+  if (r0 < 0) {
+    A = B = (int32_t)blockIdx.x;
+  } else {
+    const int32_t r = r0 + (int32_t)blockIdx.y;
+    if (r >= nbr - 1) return;  // past the last round (the whole workgroup)
+    acc64 += (int64_t)blockIdx.y * 4 * n;
+    const int32_t m = nbr - 1, t = (int32_t)blockIdx.x;
+    const int32_t a = t == 0 ? r : (r + t) % m;
+    const int32_t b = t == 0 ? m : (r - t + m) % m;
+    A = a < b ? a : b;
+    B = a < b ? b : a;
+  }
+  if (B >= nb) return;  // the padding block of an odd block count (the whole workgroup)
+  sym_tile<W, I, POT, MODE, ROT, LAW, PIPE, 1>(jarr, n, A, B, eps2_arg, nullptr, red, AdaptIn{}, acc64);
+}
+
+// The end of the round schedule: particle i's sums are the K (1, 2 or 4) accumulator copies
+// acc64[k][c][i], added as c0, c0 + c1 or (c0 + c1) + (c2 + c3).
+__global__ __launch_bounds__(kReduceBS) void reduce_rounds(int64_t n, int64_t stride, const double* __restrict__ acc64,
+                                                           int32_t K, LawScale ls, double* __restrict__ acc,
+                                                           double* __restrict__ pot, double* __restrict__ vel,
+                                                           double hh, NextStep nx, EnergyFuse ef) {
+  auto body = [&](int64_t i, double* en) {
+    const PState ps = load_state(i, stride, ls, vel, nx, ef.mass, en != nullptr);
+    double a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      a[c] = 0.0;
+      if (c == 3 && !pot) continue;
+      const double* q = acc64 + (int64_t)c * n + i;
+      const int64_t cs = 4 * n;  // one copy
+      if (K == 4)
+        a[c] = (q[0] + q[cs]) + (q[2 * cs] + q[3 * cs]);
+      else if (K == 2)
+        a[c] = q[0] + q[cs];
+      else
+        a[c] = q[0];
+    }
+    finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, en, ps);
+  };
+  if (ef.part) {  // grid (chunks, 1)
+    energy_chunk(0, n, 0, ef, body);
+    return;
+  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) body(i, nullptr);
 }
 
 // ----------------------------------------------------------------- symmetric pass: per-particle reduction

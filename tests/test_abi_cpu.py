@@ -115,9 +115,9 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails val
     (dict(offsets=[0, 5, 3, 10]), 1, "non-decreasing"),
     (dict(offsets=[1, 5, 10]), 1, "offsets[0]"),
     (dict(offsets=[0, 5, 9]), 1, "must equal n"),
-    (dict(flags=8), 1, "flags"),
     (dict(flags=16), 1, "flags"),
-    (dict(flags=7 | 32), 1, "flags"),
+    (dict(flags=32), 1, "flags"),
+    (dict(flags=15 | 64), 1, "flags"),
     (dict(reserved=1), 1, "reserved"),
     (dict(), 4, "workspace is NULL"),
     (dict(ws=0x1000, ws_bytes=10), 4, "too small"),
@@ -217,7 +217,7 @@ def test_lj_ignores_gravity_constants(nb):
 def test_known_flags_accepted(nb):
     """The per-system loop and the whole-rollout flags pass validation (the call then stops
     at the missing workspace, the first check after the configuration)."""
-    for flags in (nb.FLAG_LOOP_SYSTEMS, nb.FLAG_WHOLE_ROLLOUT, nb.FLAG_PER_PASS, 7):
+    for flags in (nb.FLAG_LOOP_SYSTEMS, nb.FLAG_WHOLE_ROLLOUT, nb.FLAG_PER_PASS, nb.FLAG_SYM_ROUNDS, 15):
         c = _cfg(nb, flags=flags)
         assert nb.lib().nbody_forces(ctypes.byref(c), 10, FAKE, FAKE, FAKE, None) == 4
         assert "workspace is NULL" in nb.lib().nbody_last_error().decode()
@@ -319,8 +319,9 @@ def test_step_noalloc_rejections_before_device_work(nb):
 
 
 def test_workspace_stays_linear_beyond_the_symmetric_cap(nb):
-    """Symmetric tiles keep O(n^2 / block) float slots; past 16 GiB of them a single-system pass
-    runs one-sided, so the workspace of a 4M-particle call is O(n) (and smaller than at 1M)."""
+    """Symmetric tiles keep O(n^2 / block) float slots; past 16 GiB of them a single-system force
+    pass runs on the round schedule (per-particle accumulators) and the adjoint one-sided, so the
+    workspace of a 4M-particle call is O(n) (and smaller than at 1M)."""
     for prec in (1, 2, 4):  # plain, compensated, adaptive FP32
         rc, w1m = _ws_size(nb, _cfg(nb, precision=prec), 1 << 20)
         assert rc == 0 and w1m > (1 << 33)  # ~8.6 GB of tile partials on the tuned 2048-particle tiles
@@ -333,3 +334,17 @@ def test_workspace_stays_linear_beyond_the_symmetric_cap(nb):
     for kernel in (0, 1):
         assert nb.lib().nbody_tile_lookup(kernel, 2, 1 << 22, ctypes.byref(v), ctypes.byref(sp)) == 0
         assert "sym=" not in nb.tile_variants(["force", "adjoint"][kernel], "fp32c")[v.value]
+
+
+def test_round_schedule_flag_workspace(nb):
+    """NBODY_FLAG_SYM_ROUNDS (8) is accepted and puts a single-system FP32 pass on per-particle
+    accumulators: 4 copies of 32 bytes per particle instead of the slot planes (8.6 GB at 1M)."""
+    n = 1 << 20
+    for prec in (1, 2, 3, 4):
+        rc, slots = _ws_size(nb, _cfg(nb, precision=prec), n)
+        rc2, rounds = _ws_size(nb, _cfg(nb, precision=prec, flags=8), n)
+        assert rc == 0 and rc2 == 0
+        assert 128 * n < rounds < 240 * n < slots, (prec, rounds, slots)
+    rc, w64 = _ws_size(nb, _cfg(nb, precision=0, flags=8), n)  # FP64 has no symmetric tiles
+    rc2, w64b = _ws_size(nb, _cfg(nb, precision=0), n)
+    assert rc == 0 and rc2 == 0 and w64 == w64b

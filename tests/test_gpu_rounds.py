@@ -1,0 +1,141 @@
+"""The round schedule of the symmetric force pass: tiles of 1024-particle blocks in rounds of
+disjoint block pairs, each tile adding its sums to per-particle double accumulators (workspace
+linear in n). Forced with NBODY_FLAG_SYM_ROUNDS at small sizes; taken by the library itself
+where the slot schedule's partial sums would exceed its cap (checked at 1.6M particles).
+
+Against the oracle every particle is held to its FP32 rounding bound (oracle/bounds.py, the
+same bound as the slot schedule: the sums are the same float tile sums, added in double);
+potentials within the per-mode relative tolerance of the parity tests."""
+import numpy as np
+import pytest
+
+from paper_2511_02655_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_P = {"fp32c": 1e-6, "fp32": 1e-5, "fp32ds": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2511_02655_amd as m
+    m.lib()
+    return m
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _bound(pos, mass, eps, prec, idx=None):
+    from oracle import bounds
+    return bounds.fp32_force_bound(pos, mass, eps, accumulate_plain=(prec == "fp32"),
+                                   exact_coords=(prec == "fp32ds"), idx=idx)
+
+
+@pytest.mark.parametrize("n", [1, 2, 100, 1023, 1024, 1025, 2048, 2049, 5000])
+def test_rounds_vs_oracle(nb, oracle, n):
+    """Sizes below, at and across one and two blocks (odd and even block counts: the padding
+    block of the circle method), every FP32 mode, with and without the potential."""
+    s = inputs.uniform_cube(n, 1200 + n)
+    a_r, p_r = oracle.forces(s.pos, s.mass, eps=1e-2)
+    for prec in ("fp32c", "fp32", "fp32ds"):
+        B = _bound(s.pos, s.mass, 1e-2, prec) if n > 1 else None
+        for want_pot in (True, False):
+            a, p = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision=prec, want_pot=want_pot,
+                             flags=nb.FLAG_SYM_ROUNDS)
+            a = host(a)
+            if n == 1:
+                assert np.all(a == 0)
+                continue
+            d = np.sqrt(np.sum((a - a_r) ** 2, axis=0))
+            assert np.max(d / B) <= 1.0, (prec, want_pot, float(np.max(d / B)))
+            if want_pot:
+                assert np.max(np.abs(host(p) - p_r) / np.abs(p_r)) <= TOL_P[prec], prec
+
+
+def test_rounds_lennard_jones_vs_oracle(nb, oracle):
+    """The Lennard-Jones law on the round schedule, held to the Lennard-Jones parity checks."""
+    from test_gpu_lj import _gas, check_lj
+    for n in (100, 3000):
+        pos, mass, _, _ = _gas(n, 1201 + n)
+        a_r, p_r = oracle.lj_forces(pos, mass, 1.1, 0.7)
+        for prec in ("fp32c", "fp32", "fp32ds"):
+            a, p = nb.lj_forces(dev(pos), dev(mass), sigma=1.1, epsilon=0.7, precision=prec, want_pot=True,
+                                flags=nb.FLAG_SYM_ROUNDS)
+            check_lj(host(a), host(p), a_r, p_r, pos, mass, prec, sigma=1.1, epsilon=0.7)
+
+
+def test_rounds_deterministic_and_consistent(nb):
+    """Repeated calls are bitwise equal; a step's accelerations and potential are bitwise those of
+    a force pass at the new positions; trajectories do not depend on the energy trace; the
+    adaptive mode runs as the double-float mode on this schedule."""
+    import torch
+    n = 7000
+    s = inputs.plummer(n, 1202)
+    x, m = dev(s.pos), dev(s.mass)
+    F = nb.FLAG_SYM_ROUNDS
+    a1, p1 = nb.forces(x, m, precision="fp32c", want_pot=True, flags=F)
+    a2, p2 = nb.forces(x, m, precision="fp32c", want_pot=True, flags=F)
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+    pos, vel = dev(s.pos), dev(s.vel)
+    acc = a1.clone()
+    pot = torch.empty(n, dtype=torch.float64, device="cuda")
+    nb.step(pos, vel, m, acc, 1e-3, precision="fp32c", out_pot=pot, flags=F)
+    a3, p3 = nb.forces(pos, m, precision="fp32c", want_pot=True, flags=F)
+    assert torch.equal(acc, a3) and torch.equal(pot, p3)
+    outs = []
+    for trace in (False, True):
+        p_, v_ = dev(s.pos), dev(s.vel)
+        nb.rollout(p_, v_, m, a1.clone(), 1e-3, 5, energy_trace=trace, precision="fp32c", flags=F)
+        outs.append((host(p_), host(v_)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    aa, _ = nb.forces(x, m, precision="fp32a", flags=F)
+    ad, _ = nb.forces(x, m, precision="fp32ds", flags=F)
+    assert torch.equal(aa, ad)
+
+
+def test_rounds_match_slots(nb):
+    """At N = 40 000 the round schedule and the slot schedule agree within FP32 rounding of
+    the separate sums (both against the FP64 GPU path)."""
+    import torch
+    s = inputs.plummer(40000, 1203)
+    x, m = dev(s.pos), dev(s.mass)
+    a64, _ = nb.forces(x, m, precision="fp64")
+    mag = torch.sqrt((a64 ** 2).sum(0))
+    floor = 1e-6 * float(torch.sqrt((mag ** 2).mean()))
+    for prec in ("fp32c", "fp32ds"):
+        ar, _ = nb.forces(x, m, precision=prec, flags=nb.FLAG_SYM_ROUNDS)
+        asl, _ = nb.forces(x, m, precision=prec)
+        er = float(torch.max(torch.sqrt(((ar - a64) ** 2).sum(0)) / torch.clamp(mag, min=floor)))
+        es = float(torch.max(torch.sqrt(((asl - a64) ** 2).sum(0)) / torch.clamp(mag, min=floor)))
+        assert er <= 1e-5 and es <= 1e-5, (prec, er, es)
+
+
+def test_rounds_taken_beyond_the_slot_cap(nb, oracle):
+    """N = 1.6M: the tuned tile's partial sums would exceed the library's 16 GiB cap, so the pass
+    runs on the round schedule by itself (bitwise equal to forcing it); sampled particles,
+    including the worst against the FP64 GPU path, against the oracle within their bounds."""
+    import torch
+    n = 1600000
+    s = inputs.plummer(n, 1204)
+    x, m = dev(s.pos), dev(s.mass)
+    a, _ = nb.forces(x, m, eps=1e-2, precision="fp32c")
+    af, _ = nb.forces(x, m, eps=1e-2, precision="fp32c", flags=nb.FLAG_SYM_ROUNDS)
+    assert torch.equal(a, af)
+    a64, _ = nb.forces(x, m, eps=1e-2, precision="fp64")
+    d = host(torch.sqrt(((a - a64) ** 2).sum(0)))
+    g = np.random.Generator(np.random.PCG64(1205))
+    idx = np.unique(np.concatenate([np.argsort(d)[-32:], g.choice(n, 32, replace=False)]))
+    ref, _ = oracle.forces_sample(s.pos, s.mass, idx, eps=1e-2)
+    B = _bound(s.pos, s.mass, 1e-2, "fp32c", idx=idx)
+    dd = np.sqrt(np.sum((host(a)[:, idx] - ref) ** 2, axis=0))
+    assert np.max(dd / B) <= 1.0, float(np.max(dd / B))
