@@ -112,13 +112,15 @@ typedef enum {
                                       baseline of that choice; results are identical) */
 #define NBODY_FLAG_SYM_ROUNDS 8u    /* single-system FP32 force passes on the round schedule:
                                       symmetric tiles of 1024-particle blocks run in rounds
-                                      of disjoint block pairs (circle method), K consecutive
-                                      rounds per launch (K = 4 where the workspace allows,
-                                      else 2 or 1), each tile adding its sums to per-particle
-                                      double accumulators (K copies, one per round of a
-                                      launch), so the workspace is linear in n (32 K bytes
-                                      per particle for the sums) instead of one float slot
-                                      per particle and block. Deterministic for a given K;
+                                      of disjoint block pairs (circle method), each tile
+                                      adding its sums to per-particle double accumulators,
+                                      so the workspace is linear in n (32 K bytes per
+                                      particle for K accumulator copies: K = 8 where the
+                                      workspace allows, else 4, 2 or 1) instead of one float
+                                      slot per particle and block. With K >= 2 the launches
+                                      (K/2 rounds each) alternate between two streams the
+                                      library creates per device and keeps; the call's
+                                      stream waits for both. Deterministic for a given K;
                                       not bitwise the slot schedule's sums (another order).
                                       The library takes this schedule by itself where the
                                       slot schedule's partial sums would exceed its cap

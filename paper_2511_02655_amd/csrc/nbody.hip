@@ -181,14 +181,15 @@ template <int W, int I, int MODE, int ROT, int LAW, int PIPE>
 const void* rollout_ptr() { return (const void*)&rollout_sym_batched_kernel<W, I, MODE, ROT, LAW, PIPE>; }
 // The round schedule (single systems, workspace linear in n) on one fixed tile: 4 waves, 4
 // particles per lane, 1024-particle blocks, LDS-crossbar rotation - at the sizes that need it
-// (beyond ~1.5M particles) a round holds ~750-1000 tiles, and a launch of K rounds K times that.
+// (beyond ~1.5M particles) a round holds ~750-1000 tiles, and a launch of several rounds a
+// multiple of that (four or five workgroups of this tile fit a CU, by mode: 1024-1280 on the chip).
 constexpr int kRoundW = 4, kRoundI = 4, kRoundBlock = kRoundW * 64 * kRoundI;
-// Rounds per launch (accumulator copies, 32 bytes per particle each): 4 where the copies and a
-// margin of 128 bytes per particle for the rest of the workspace fit the partial-sum cap, else 2,
-// else 1.
+// Accumulator copies of the round schedule (32 bytes per particle each; the rounds of a launch
+// take one each, on two streams): 8 where the copies and a margin of 128 bytes per particle for
+// the rest of the workspace fit the partial-sum cap, else 4, else 2, else 1.
 int round_copies(int64_t n, double cap) {
   const double nn = (double)std::max<int64_t>(n, 1);
-  for (int k : {4, 2})
+  for (int k : {8, 4, 2})
     if ((32.0 * k + 128.0) * nn <= cap) return k;
   return 1;
 }
@@ -200,6 +201,77 @@ void launch_round(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t
   hipLaunchKernelGGL((force_sym_round_kernel<kRoundW, kRoundI, POT, MODE, 1, LAW, 0>), g, dim3(kRoundW * 64), 0, st,
                      jarr, n, nb, nbr, r, eps2, acc64);
 }
+// Two streams per device on which the round schedule's launches alternate: launches on one
+// stream run one after the other, so a launch's last tiles would leave most CUs idle until the
+// next launch starts; on two streams the next launch fills them. Created on first use (default
+// priority, non-blocking), held until the process ends; calls from several host threads share
+// them (their launches then interleave, each call still ordered by its own events).
+constexpr int kRoundDevices = 64;
+std::mutex g_round_mu;
+hipStream_t g_round_st[kRoundDevices][2] = {};
+
+int round_streams(hipStream_t (&out)[2]) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kRoundDevices)
+    return fail(NBODY_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kRoundDevices);
+  std::lock_guard<std::mutex> lk(g_round_mu);
+  for (int k = 0; k < 2; ++k)
+    if (!g_round_st[dev][k]) HIP_TRY(hipStreamCreateWithFlags(&g_round_st[dev][k], hipStreamNonBlocking));
+  out[0] = g_round_st[dev][0];
+  out[1] = g_round_st[dev][1];
+  return NBODY_OK;
+}
+
+// The rounds 0 .. nbr - 2 of the round schedule after the diagonal tiles (enqueued on st), into K
+// accumulator copies from a64. K = 1: one round per launch on st. K >= 2: launch L runs the K/2
+// rounds from L K/2 on round stream L mod 2, into copies (L mod 2) K/2 .. (L mod 2) K/2 + K/2 - 1;
+// the round streams start after st's work so far and st waits for both at the end, also when a
+// launch failed (the workspace must not be reused under running tiles).
+int run_rounds(hipStream_t st, RoundFn fn, const float4* jb, int64_t ns, int64_t nb, int64_t nbr, float eps2,
+               double* a64, int K) {
+  if (K == 1) {
+    for (int64_t r = 0; r + 1 < nbr; ++r) {
+      fn(dim3((unsigned)(nbr / 2)), st, jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, eps2, a64);
+      LAUNCH_CHECK("force_sym_round_kernel");
+    }
+    return NBODY_OK;
+  }
+  hipStream_t rs[2];
+  TRY(round_streams(rs));
+  struct Events {
+    hipEvent_t e[3] = {};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);  // released once the waits on it are done
+    }
+  } ev;
+  for (hipEvent_t& x : ev.e) HIP_TRY(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ev.e[0], st));
+  HIP_TRY(hipStreamWaitEvent(rs[0], ev.e[0], 0));
+  HIP_TRY(hipStreamWaitEvent(rs[1], ev.e[0], 0));
+  const int64_t KH = K / 2;
+  hipError_t err = hipSuccess;
+  int64_t L = 0;
+  for (int64_t r = 0; r + 1 < nbr && err == hipSuccess; r += KH, ++L) {
+    const unsigned ky = (unsigned)std::min<int64_t>(KH, nbr - 1 - r);
+    fn(dim3((unsigned)(nbr / 2), ky), rs[L & 1], jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, eps2,
+       a64 + (size_t)(L & 1) * KH * 4 * ns);
+    err = hipGetLastError();
+  }
+  hipError_t j0 = hipEventRecord(ev.e[1], rs[0]);
+  if (j0 == hipSuccess) j0 = hipStreamWaitEvent(st, ev.e[1], 0);
+  hipError_t j1 = hipEventRecord(ev.e[2], rs[1]);
+  if (j1 == hipSuccess) j1 = hipStreamWaitEvent(st, ev.e[2], 0);
+  if (j0 != hipSuccess || j1 != hipSuccess) {  // no ordering on st: wait here instead
+    (void)hipStreamSynchronize(rs[0]);
+    (void)hipStreamSynchronize(rs[1]);
+    return fail(NBODY_ERR_DEVICE, "round streams: %s", hipGetErrorString(j0 != hipSuccess ? j0 : j1));
+  }
+  if (err != hipSuccess) return fail(NBODY_ERR_DEVICE, "launch of force_sym_round_kernel failed: %s", hipGetErrorString(err));
+  return NBODY_OK;
+}
+
 #define RND_POT(POT, LAW) \
   { launch_round<POT, 0, LAW>, launch_round<POT, 1, LAW>, launch_round<POT, 2, LAW> }
 const RoundFn kRound[2][2][3] = {{RND_POT(false, 0), RND_POT(true, 0)}, {RND_POT(false, 1), RND_POT(true, 1)}};
@@ -1285,8 +1357,8 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
     Tile t = single_force_tile(c.cfg, force_kernel_id(law, false), prec, ns);
     if (t.rounds) {
       // round schedule: zero the K accumulator copies, the diagonal tiles, then nbr - 1 rounds
-      // of disjoint block pairs, K per launch, then the per-particle end (copies added, scale,
-      // kick, next step, energy)
+      // of disjoint block pairs (K / 2 per launch on two alternating streams), then the
+      // per-particle end (copies added, scale, kick, next step, energy)
       const int64_t nb = cdiv(ns, (int64_t)kRoundBlock), nbr = nb + (nb & 1);
       if (nbr > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many blocks for the round schedule");
       const int K = round_copies(ns, g_sym_cap);
@@ -1298,11 +1370,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
       const RoundFn fn = kRound[law][pot_on][mode];
       fn(dim3((unsigned)nb), c.st, jb, ns, (int32_t)nb, (int32_t)nbr, -1, (float)eps2, a64);
       LAUNCH_CHECK("force_sym_round_kernel (diagonal tiles)");
-      for (int64_t r = 0; r + 1 < nbr; r += K) {
-        const unsigned ky = (unsigned)std::min<int64_t>(K, nbr - 1 - r);
-        fn(dim3((unsigned)(nbr / 2), ky), c.st, jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, (float)eps2, a64);
-        LAUNCH_CHECK("force_sym_round_kernel");
-      }
+      TRY(run_rounds(c.st, fn, jb, ns, nb, nbr, (float)eps2, a64, K));
       hipLaunchKernelGGL(reduce_rounds, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n, (const double*)a64, (int32_t)K,
                          c.ls_at(b),
                          acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, next_step_at(c, nx, b), ef);

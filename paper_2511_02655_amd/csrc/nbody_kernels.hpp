@@ -1152,8 +1152,10 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
         const int64_t j = Bbase + (int64_t)sb * 64 + l;
         if constexpr (OUT == 0) {
           if (j < n) part[((int64_t)A * 4 + c) * n + j] = sum;
-        } else {
+        } else if constexpr (OUT == 1) {
           if (j < n) acc64[(int64_t)c * n + j] += (double)sum;
+        } else {
+          if (j < n) unsafeAtomicAdd(acc64 + (int64_t)c * n + j, (double)sum);
         }
       }
     }
@@ -1181,9 +1183,12 @@ __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_
         if constexpr (OUT == 0)
           part[((int64_t)B * 4 + c) * n + i] =
               COMP ? hi[c][u] + (LO_LDS ? lo_w[(c * I + u) * 64] : lo[c][u]) : ai[c][u];
-        else
+        else if constexpr (OUT == 1)
           acc64[(int64_t)c * n + i] +=
               COMP ? (double)hi[c][u] + (double)(LO_LDS ? lo_w[(c * I + u) * 64] : lo[c][u]) : (double)ai[c][u];
+        else
+          unsafeAtomicAdd(acc64 + (int64_t)c * n + i, COMP ? (double)hi[c][u] + (double)(LO_LDS ? lo_w[(c * I + u) * 64] : lo[c][u])
+                                                            : (double)ai[c][u]);
       }
   }
 }
@@ -1208,13 +1213,13 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 // The round schedule of the symmetric pass (workspace linear in n). Round r in [0, nbr - 2] is
 // the circle-method pairing of nbr (even) blocks: tile t pairs (r, nbr - 1) for t = 0 and
 // ((r + t) mod (nbr - 1), (r - t) mod (nbr - 1)) for t > 0, so every unordered pair of blocks
-// meets in exactly one round and the tiles of a round touch disjoint blocks. The sums go to K
-// copies of [4][n] double accumulators (zeroed first): round r adds to copy r mod K, so the K
-// rounds r0 .. r0 + K - 1 run in one launch (grid (nbr / 2, K), blockIdx.y = r - r0) without two
-// tiles touching the same accumulator. r0 < 0 runs every diagonal tile (A, A), one workgroup per
-// block, into copy 0 before any round. Every accumulator takes its tiles in a fixed order, so
-// the result is deterministic for a given K. A pair with the padding block nb (odd nb) is
-// skipped.
+// meets in exactly one round and the tiles of a round touch disjoint blocks. A launch runs the
+// rounds r0 .. r0 + gridDim.y - 1 (grid (nbr / 2, rounds), blockIdx.y = r - r0), round r adding
+// into its own copy of [4][n] double accumulators, acc64 + (r - r0) [4][n], so no two tiles of a
+// launch touch the same accumulator; launches that reuse copies run one after the other. r0 < 0
+// runs every diagonal tile (A, A), one workgroup per block, into acc64. Every accumulator takes
+// its tiles in a fixed order, so the result is deterministic. A pair with the padding block nb
+// (odd nb) is skipped.
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 __global__ __launch_bounds__(W * 64) void force_sym_round_kernel(const float4* __restrict__ jarr, int64_t n,
                                                                  int32_t nb, int32_t nbr, int32_t r0,
@@ -1234,11 +1239,18 @@ __global__ __launch_bounds__(W * 64) void force_sym_round_kernel(const float4* _
     B = a < b ? b : a;
   }
   if (B >= nb) return;  // the padding block of an odd block count (the whole workgroup)
-  sym_tile<W, I, POT, MODE, ROT, LAW, PIPE, 1>(jarr, n, A, B, eps2_arg, nullptr, red, AdaptIn{}, acc64);
+  // A diagonal tile adds both sides of its sums to the same accumulators: load, add, store in
+  // program order. An off-diagonal tile's two blocks are disjoint, and no other tile of the launch
+  // touches them, so each accumulator word takes exactly one add per launch: a device atomic add
+  // (the same IEEE double addition) that no wave waits for.
+  if (A == B)
+    sym_tile<W, I, POT, MODE, ROT, LAW, PIPE, 1>(jarr, n, A, B, eps2_arg, nullptr, red, AdaptIn{}, acc64);
+  else
+    sym_tile<W, I, POT, MODE, ROT, LAW, PIPE, 2>(jarr, n, A, B, eps2_arg, nullptr, red, AdaptIn{}, acc64);
 }
 
-// The end of the round schedule: particle i's sums are the K (1, 2 or 4) accumulator copies
-// acc64[k][c][i], added as c0, c0 + c1 or (c0 + c1) + (c2 + c3).
+// The end of the round schedule: particle i's sums are the K accumulator copies acc64[k][c][i],
+// added in copy order.
 __global__ __launch_bounds__(kReduceBS) void reduce_rounds(int64_t n, int64_t stride, const double* __restrict__ acc64,
                                                            int32_t K, LawScale ls, double* __restrict__ acc,
                                                            double* __restrict__ pot, double* __restrict__ vel,
@@ -1252,12 +1264,9 @@ __global__ __launch_bounds__(kReduceBS) void reduce_rounds(int64_t n, int64_t st
       if (c == 3 && !pot) continue;
       const double* q = acc64 + (int64_t)c * n + i;
       const int64_t cs = 4 * n;  // one copy
-      if (K == 4)
-        a[c] = (q[0] + q[cs]) + (q[2 * cs] + q[3 * cs]);
-      else if (K == 2)
-        a[c] = q[0] + q[cs];
-      else
-        a[c] = q[0];
+      double t = q[0];
+      for (int k = 1; k < K; ++k) t += q[k * cs];
+      a[c] = t;
     }
     finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, en, ps);
   };

@@ -139,3 +139,45 @@ def test_rounds_taken_beyond_the_slot_cap(nb, oracle):
     B = _bound(s.pos, s.mass, 1e-2, "fp32c", idx=idx)
     dd = np.sqrt(np.sum((host(a)[:, idx] - ref) ** 2, axis=0))
     assert np.max(dd / B) <= 1.0, float(np.max(dd / B))
+
+
+def test_rounds_from_two_threads_on_two_streams(nb):
+    """Round-schedule passes and steps issued at once from two host threads, each on its own
+    stream (both share the library's two round streams, each call ordered by its own events):
+    every result equals the same calls made alone, bitwise."""
+    import threading
+
+    import torch
+    F = nb.FLAG_SYM_ROUNDS
+    systems = [inputs.plummer(5000, 1206), inputs.plummer(20000, 1207)]
+    data = [(dev(s.pos), dev(s.vel), dev(s.mass)) for s in systems]
+    torch.cuda.synchronize()  # the inputs, made on the default stream, are read from others
+
+    def work(k, stream, out):
+        p0, v0, m = data[k]
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                a, pot = nb.forces(p0, m, precision="fp32c", want_pot=True, flags=F, stream=stream)
+                p, v = p0.clone(), v0.clone()
+                nb.rollout(p, v, m, a.clone(), 1e-3, 3, precision="fp32c", flags=F, stream=stream)
+                out.append((a, pot, p, v))
+            stream.synchronize()
+
+    alone = []
+    for k in range(2):
+        o = []
+        work(k, torch.cuda.Stream(), o)
+        alone.append(o[0])
+    outs = [[], []]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    threads = [threading.Thread(target=work, args=(k, streams[k], outs[k])) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert len(outs[k]) == 3
+        for got in outs[k]:
+            for x, y in zip(got, alone[k]):
+                assert torch.equal(x, y), k
