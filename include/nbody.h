@@ -115,8 +115,8 @@ typedef enum {
                                       of disjoint block pairs (circle method), each tile
                                       adding its sums to per-particle double accumulators,
                                       so the workspace is linear in n (32 K bytes per
-                                      particle for K accumulator copies: K = 8 where the
-                                      workspace allows, else 4, 2 or 1) instead of one float
+                                      particle for K accumulator copies: K = 4 where the
+                                      workspace allows, else 2 or 1) instead of one float
                                       slot per particle and block. With K >= 2 the launches
                                       (K/2 rounds each) alternate between two streams the
                                       library creates per device and keeps; the call's
@@ -125,7 +125,7 @@ typedef enum {
                                       The library takes this schedule by itself where the
                                       slot schedule's partial sums would exceed its cap
                                       (16 GiB, near 1.5 million particles). The adaptive mode
-                                      runs as the double-float mode on it (no sort). */
+                                      sorts and runs its adaptive tiles on it as well. */
 
 typedef struct {
   int32_t abi_version;     /* must equal NBODY_ABI_VERSION */

@@ -185,21 +185,29 @@ const void* rollout_ptr() { return (const void*)&rollout_sym_batched_kernel<W, I
 // multiple of that (four or five workgroups of this tile fit a CU, by mode: 1024-1280 on the chip).
 constexpr int kRoundW = 4, kRoundI = 4, kRoundBlock = kRoundW * 64 * kRoundI;
 // Accumulator copies of the round schedule (32 bytes per particle each; the rounds of a launch
-// take one each, on two streams): 8 where the copies and a margin of 128 bytes per particle for
-// the rest of the workspace fit the partial-sum cap, else 4, else 2, else 1.
+// take one each, on two streams): 4 where the copies and a margin of 128 bytes per particle for
+// the rest of the workspace fit the partial-sum cap, else 2, else 1. (8 copies, four rounds per
+// launch, measured no faster.)
 int round_copies(int64_t n, double cap) {
   const double nn = (double)std::max<int64_t>(n, 1);
-  for (int k : {8, 4, 2})
+  for (int k : {4, 2})
     if ((32.0 * k + 128.0) * nn <= cap) return k;
   return 1;
 }
 using RoundFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, int32_t nb, int32_t nbr, int32_t r,
-                         float eps2, double* acc64);
+                         float eps2, double* acc64, AdaptIn ad);
+using RoundDiagFn = void (*)(dim3, hipStream_t, const float4* jarr, int64_t n, float eps2, double* acc64, AdaptIn ad);
 template <bool POT, int MODE, int LAW>
 void launch_round(dim3 g, hipStream_t st, const float4* jarr, int64_t n, int32_t nb, int32_t nbr, int32_t r, float eps2,
-                  double* acc64) {
+                  double* acc64, AdaptIn ad) {
   hipLaunchKernelGGL((force_sym_round_kernel<kRoundW, kRoundI, POT, MODE, 1, LAW, 0>), g, dim3(kRoundW * 64), 0, st,
-                     jarr, n, nb, nbr, r, eps2, acc64);
+                     jarr, n, nb, nbr, r, eps2, acc64, ad);
+}
+template <bool POT, int MODE, int LAW>
+void launch_round_diag(dim3 g, hipStream_t st, const float4* jarr, int64_t n, float eps2, double* acc64, AdaptIn ad) {
+  constexpr int DM = MODE == MODE_ADAPT ? MODE_ADAPT_DIAG : MODE;
+  hipLaunchKernelGGL((force_sym_round_diag_kernel<kRoundW, kRoundI, POT, DM, 1, LAW, 0>), g, dim3(kRoundW * 64), 0,
+                     st, jarr, n, eps2, acc64, ad);
 }
 // Two streams per device on which the round schedule's launches alternate: launches on one
 // stream run one after the other, so a launch's last tiles would leave most CUs idle until the
@@ -229,10 +237,10 @@ int round_streams(hipStream_t (&out)[2]) {
 // the round streams start after st's work so far and st waits for both at the end, also when a
 // launch failed (the workspace must not be reused under running tiles).
 int run_rounds(hipStream_t st, RoundFn fn, const float4* jb, int64_t ns, int64_t nb, int64_t nbr, float eps2,
-               double* a64, int K) {
+               double* a64, int K, const AdaptIn& ad) {
   if (K == 1) {
     for (int64_t r = 0; r + 1 < nbr; ++r) {
-      fn(dim3((unsigned)(nbr / 2)), st, jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, eps2, a64);
+      fn(dim3((unsigned)(nbr / 2)), st, jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, eps2, a64, ad);
       LAUNCH_CHECK("force_sym_round_kernel");
     }
     return NBODY_OK;
@@ -256,7 +264,7 @@ int run_rounds(hipStream_t st, RoundFn fn, const float4* jb, int64_t ns, int64_t
   for (int64_t r = 0; r + 1 < nbr && err == hipSuccess; r += KH, ++L) {
     const unsigned ky = (unsigned)std::min<int64_t>(KH, nbr - 1 - r);
     fn(dim3((unsigned)(nbr / 2), ky), rs[L & 1], jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, eps2,
-       a64 + (size_t)(L & 1) * KH * 4 * ns);
+       a64 + (size_t)(L & 1) * KH * 4 * ns, ad);
     err = hipGetLastError();
   }
   hipError_t j0 = hipEventRecord(ev.e[1], rs[0]);
@@ -272,9 +280,17 @@ int run_rounds(hipStream_t st, RoundFn fn, const float4* jb, int64_t ns, int64_t
   return NBODY_OK;
 }
 
+// [law][pot][mode]: modes 0-2 as force_mode, 3 the adaptive mode (sorted particles)
 #define RND_POT(POT, LAW) \
-  { launch_round<POT, 0, LAW>, launch_round<POT, 1, LAW>, launch_round<POT, 2, LAW> }
-const RoundFn kRound[2][2][3] = {{RND_POT(false, 0), RND_POT(true, 0)}, {RND_POT(false, 1), RND_POT(true, 1)}};
+  { launch_round<POT, 0, LAW>, launch_round<POT, 1, LAW>, launch_round<POT, 2, LAW>, launch_round<POT, 3, LAW> }
+const RoundFn kRound[2][2][4] = {{RND_POT(false, 0), RND_POT(true, 0)}, {RND_POT(false, 1), RND_POT(true, 1)}};
+#define RND_DIAG_POT(POT, LAW)                                                                      \
+  {                                                                                                 \
+    launch_round_diag<POT, 0, LAW>, launch_round_diag<POT, 1, LAW>, launch_round_diag<POT, 2, LAW>, \
+        launch_round_diag<POT, 3, LAW>                                                              \
+  }
+const RoundDiagFn kRoundDiag[2][2][4] = {{RND_DIAG_POT(false, 0), RND_DIAG_POT(true, 0)},
+                                         {RND_DIAG_POT(false, 1), RND_DIAG_POT(true, 1)}};
 struct SymVariant {
   int w, i, rot;      // rot: 0 = DPP lane rotation, 1 = LDS-crossbar (ds_bpermute) rotation
   int pipe;           // coordinate rotation issued after phase 1 (0) or a step ahead (1)
@@ -869,10 +885,12 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
   p.off_jbuf = take(p.sz_jbuf);
   p.sz_part = std::max(force_part, adj_part);
   p.off_part = take(p.sz_part);
-  // the adaptive mode sorts a single system whose force pass runs on symmetric tiles
+  // the adaptive mode sorts a single system whose force pass runs on symmetric tiles (the slot
+  // or the round schedule)
+  auto symmetric = [](const Tile& t) { return t.sym >= 0 || t.rounds; };
   p.adapt = is_adapt(prec) && !bat && n > 0 &&
-            (single_force_tile(cfg, NBODY_KERNEL_FORCE, prec, n).sym >= 0 ||
-             single_force_tile(cfg, NBODY_KERNEL_LJ_FORCE, prec, n).sym >= 0);
+            (symmetric(single_force_tile(cfg, NBODY_KERNEL_FORCE, prec, n)) ||
+             symmetric(single_force_tile(cfg, NBODY_KERNEL_LJ_FORCE, prec, n)));
   if (p.adapt) {
     int64_t P = kBitonicLocal;
     while (P < n) P <<= 1;
@@ -992,7 +1010,10 @@ int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsi
   c.bat = c.sys.S > 1;
   c.loop = c.bat && (cfg->flags & NBODY_FLAG_LOOP_SYSTEMS);
   TRY(make_plan(cfg, c.sys, n, ckpt_every, need, c.plan, &c.uf, &c.ua, c.law));
-  c.adapt = c.plan.adapt && single_force_tile(cfg, force_kernel_id(c.law, false), cfg->precision, n).sym >= 0;
+  {
+    const Tile t = single_force_tile(cfg, force_kernel_id(c.law, false), cfg->precision, n);
+    c.adapt = c.plan.adapt && (t.sym >= 0 || t.rounds);
+  }
   if (n == 0) return NBODY_OK;
   if (!cfg->workspace) return fail(NBODY_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", c.plan.total);
   if (((uintptr_t)cfg->workspace) % kAlign)
@@ -1245,17 +1266,34 @@ int flush_energy(Ctx& c, int32_t count, double* out) {
 // last staging call named: bounding box and threshold, Morton keys, bitonic sort, sorted
 // staging with sub-block boxes, the tile kernel, and the per-particle reduction in sorted
 // order that writes every output at the particle's own index.
+// The tiles of the round schedule over a system of ns particles whose j-array is jb: zero the K
+// accumulator copies (K out), the diagonal tiles, then nbr - 1 rounds of disjoint block pairs
+// (K / 2 per launch on two alternating streams). The caller adds the copies per particle.
+// mode: force_mode's, or 3 for the adaptive mode (sorted particles, ad).
+int round_tiles(Ctx& c, int64_t ns, const float4* jb, int law, int pot_on, int mode, const AdaptIn& ad, int& K) {
+  const int64_t nb = cdiv(ns, (int64_t)kRoundBlock), nbr = nb + (nb & 1);
+  if (nbr > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many blocks for the round schedule");
+  K = round_copies(ns, g_sym_cap);
+  TRY(check_part(c, (size_t)K * 4 * ns * sizeof(double), "force_sym_round_kernel"));
+  double* a64 = (double*)(c.ws + c.plan.off_part);
+  hipLaunchKernelGGL(fill_f64, grid1d(K * 4 * ns), dim3(256), 0, c.st, a64, K * 4 * ns, 0.0);
+  LAUNCH_CHECK("fill_f64");
+  kRoundDiag[law][pot_on][mode](dim3((unsigned)nb), c.st, jb, ns, (float)c.eps2, a64, ad);
+  LAUNCH_CHECK("force_sym_round_diag_kernel");
+  return run_rounds(c.st, kRound[law][pot_on][mode], jb, ns, nb, nbr, (float)c.eps2, a64, K, ad);
+}
+
 template <typename Tail>
 int adapt_sym_pass(Ctx& c, const Tile& t, double* acc, double* pot, double* vel, double hh, const NextStep* nx,
                    Tail&& tail) {
   const int64_t n = c.n;
   if (!c.src_pos || !c.src_mass) return fail(NBODY_ERR_DEVICE, "internal: adaptive pass without staged positions");
   if (n > 0xffffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "the adaptive mode sorts at most 2^32 particles");
-  const SymVariant& sv = kSym32[t.sym];
-  const int64_t nb = cdiv(n, (int64_t)t.tj);
-  const int64_t off_tiles = nb * (nb - 1) / 2;  // off-diagonal tiles (the diagonal ones launch apart)
+  // slot schedule: off-diagonal tiles (the diagonal ones launch apart)
+  const int64_t nb = t.rounds ? 0 : cdiv(n, (int64_t)t.tj);
+  const int64_t off_tiles = nb * (nb - 1) / 2;
   if (off_tiles > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many symmetric tiles");
-  TRY(check_part(c, (size_t)nb * 4 * n * sizeof(float), "force_sym_kernel (adaptive)"));
+  if (!t.rounds) TRY(check_part(c, (size_t)nb * 4 * n * sizeof(float), "force_sym_kernel (adaptive)"));
   TRY(check_jbuf(c, 2 * sizeof(float4), "adapt_stage"));
   const Plan& pl = c.plan;
   if (!pl.adapt) return fail(NBODY_ERR_DEVICE, "internal: adaptive pass without its workspace");
@@ -1289,11 +1327,21 @@ int adapt_sym_pass(Ctx& c, const Tile& t, double* acc, double* pot, double* vel,
   hipLaunchKernelGGL(adapt_stage, grid1d(cdiv(n, kSub) * kSub, kAdaptBS), dim3(kAdaptBS), 0, c.st, n,
                      (const uint64_t*)keys, c.src_pos, c.src_mass, c.xs, perm, jhi, jlo, box);
   LAUNCH_CHECK("adapt_stage");
-  float* pf = (float*)(c.ws + pl.off_part);
   AdaptIn ad;
   ad.jlo = jlo;
   ad.box = box;
   ad.thr = bbox + 6;
+  if (t.rounds) {
+    int K = 1;
+    TRY(round_tiles(c, n, jhi, c.law, pot != nullptr, 3, ad, K));
+    hipLaunchKernelGGL(reduce_rounds, grid1d(n), dim3(kReduceBS), 0, c.st, n, n,
+                       (const double*)(c.ws + pl.off_part), (int32_t)K, c.ls, acc, pot, vel, hh,
+                       nx ? *nx : NextStep{}, EnergyFuse{}, (const uint32_t*)perm);
+    LAUNCH_CHECK("reduce_rounds");
+    return tail();
+  }
+  const SymVariant& sv = kSym32[t.sym];
+  float* pf = (float*)(c.ws + pl.off_part);
   sv.dfn[c.law][pot != nullptr](dim3((unsigned)nb), c.st, jhi, n, (int32_t)nb, (float)c.eps2, pf, ad);
   LAUNCH_CHECK("force_sym_kernel (adaptive, diagonal tiles)");
   if (off_tiles > 0) {
@@ -1355,29 +1403,18 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
     const int64_t ns = e - b;
     if (ns == 0) return NBODY_OK;
     Tile t = single_force_tile(c.cfg, force_kernel_id(law, false), prec, ns);
+    if ((t.sym >= 0 || t.rounds) && c.adapt) return adapt_sym_pass(c, t, acc, pot, vel, hh, nx, fused_tail);
     if (t.rounds) {
-      // round schedule: zero the K accumulator copies, the diagonal tiles, then nbr - 1 rounds
-      // of disjoint block pairs (K / 2 per launch on two alternating streams), then the
-      // per-particle end (copies added, scale, kick, next step, energy)
-      const int64_t nb = cdiv(ns, (int64_t)kRoundBlock), nbr = nb + (nb & 1);
-      if (nbr > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many blocks for the round schedule");
-      const int K = round_copies(ns, g_sym_cap);
-      TRY(check_part(c, (size_t)K * 4 * ns * sizeof(double), "force_sym_round_kernel"));
-      double* a64 = (double*)(c.ws + c.plan.off_part);
-      hipLaunchKernelGGL(fill_f64, grid1d(K * 4 * ns), dim3(256), 0, c.st, a64, K * 4 * ns, 0.0);
-      LAUNCH_CHECK("fill_f64");
-      const float4* jb = (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b;
-      const RoundFn fn = kRound[law][pot_on][mode];
-      fn(dim3((unsigned)nb), c.st, jb, ns, (int32_t)nb, (int32_t)nbr, -1, (float)eps2, a64);
-      LAUNCH_CHECK("force_sym_round_kernel (diagonal tiles)");
-      TRY(run_rounds(c.st, fn, jb, ns, nb, nbr, (float)eps2, a64, K));
-      hipLaunchKernelGGL(reduce_rounds, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n, (const double*)a64, (int32_t)K,
-                         c.ls_at(b),
-                         acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, next_step_at(c, nx, b), ef);
+      // round schedule, then the per-particle end (copies added, scale, kick, next step, energy)
+      int K = 1;
+      TRY(round_tiles(c, ns, (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b, law, pot_on, mode, AdaptIn{}, K));
+      hipLaunchKernelGGL(reduce_rounds, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n,
+                         (const double*)(c.ws + c.plan.off_part), (int32_t)K, c.ls_at(b), acc + b,
+                         pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, next_step_at(c, nx, b), ef,
+                         (const uint32_t*)nullptr);
       LAUNCH_CHECK("reduce_rounds");
       return fused_tail();
     }
-    if (t.sym >= 0 && c.adapt) return adapt_sym_pass(c, t, acc, pot, vel, hh, nx, fused_tail);
     if (t.sym >= 0) {
       const SymVariant& sv = kSym32[t.sym];
       const int64_t nb = cdiv(ns, (int64_t)t.tj);

@@ -748,9 +748,9 @@ __device__ __forceinline__ void tile_rc(int64_t t, int32_t nb, int32_t& A, int32
 // (the j-particles come home after 64 steps), so they need no more registers than the float
 // loop.
 //
-// OUT 1 (the round schedule): instead of writing slots, the tile adds its i-side and j-side sums
-// to per-particle double accumulators acc64 [4][n]; the caller runs only tiles whose blocks no
-// other running tile touches.
+// OUT 1 and 2 (the round schedule): instead of writing slots, the tile adds its i-side and j-side
+// sums to per-particle double accumulators acc64 [4][n], with a load, add and store (1) or a
+// device atomic add (2); the caller runs only tiles whose blocks no other running tile touches.
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE = 0, int OUT = 0>
 __device__ __forceinline__ void sym_tile(const float4* __restrict__ jarr, int64_t n, int32_t A, int32_t B,
                                          float eps2_arg, float* __restrict__ part,
@@ -1212,57 +1212,61 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(const float4* __restr
 
 // The round schedule of the symmetric pass (workspace linear in n). Round r in [0, nbr - 2] is
 // the circle-method pairing of nbr (even) blocks: tile t pairs (r, nbr - 1) for t = 0 and
-// ((r + t) mod (nbr - 1), (r - t) mod (nbr - 1)) for t > 0, so every unordered pair of blocks
-// meets in exactly one round and the tiles of a round touch disjoint blocks. A launch runs the
-// rounds r0 .. r0 + gridDim.y - 1 (grid (nbr / 2, rounds), blockIdx.y = r - r0), round r adding
-// into its own copy of [4][n] double accumulators, acc64 + (r - r0) [4][n], so no two tiles of a
-// launch touch the same accumulator; launches that reuse copies run one after the other. r0 < 0
-// runs every diagonal tile (A, A), one workgroup per block, into acc64. Every accumulator takes
-// its tiles in a fixed order, so the result is deterministic. A pair with the padding block nb
-// (odd nb) is skipped.
+// ((r + t) mod (nbr - 1), (r - t) mod (nbr - 1)) for t > 0, so every unordered pair of distinct
+// blocks meets in exactly one round and the tiles of a round touch disjoint blocks. A launch
+// runs the rounds r0 .. r0 + gridDim.y - 1 (grid (nbr / 2, rounds), blockIdx.y = r - r0), round
+// r adding into its own copy of [4][n] double accumulators, acc64 + (r - r0) [4][n], so no two
+// tiles of a launch touch the same accumulator word and each word takes exactly one add per
+// launch: a device atomic add (the same IEEE double addition) that no wave waits for. Launches
+// that reuse copies run one after the other, so every accumulator takes its tiles in a fixed
+// order and the result is deterministic. A pair with the padding block nb (odd nb) is skipped.
+// MODE_ADAPT: particles in Morton order, ad as in the slot schedule.
 template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
 __global__ __launch_bounds__(W * 64) void force_sym_round_kernel(const float4* __restrict__ jarr, int64_t n,
                                                                  int32_t nb, int32_t nbr, int32_t r0,
-                                                                 float eps2_arg, double* __restrict__ acc64) {
+                                                                 float eps2_arg, double* __restrict__ acc64,
+                                                                 AdaptIn ad) {
   __shared__ float red[2][W][POT ? 4 : 3][64];
-  int32_t A, B;
-  if (r0 < 0) {
-    A = B = (int32_t)blockIdx.x;
-  } else {
-    const int32_t r = r0 + (int32_t)blockIdx.y;
-    if (r >= nbr - 1) return;  // past the last round (the whole workgroup)
-    acc64 += (int64_t)blockIdx.y * 4 * n;
-    const int32_t m = nbr - 1, t = (int32_t)blockIdx.x;
-    const int32_t a = t == 0 ? r : (r + t) % m;
-    const int32_t b = t == 0 ? m : (r - t + m) % m;
-    A = a < b ? a : b;
-    B = a < b ? b : a;
-  }
+  const int32_t r = r0 + (int32_t)blockIdx.y;
+  if (r >= nbr - 1) return;  // past the last round (the whole workgroup)
+  acc64 += (int64_t)blockIdx.y * 4 * n;
+  const int32_t m = nbr - 1, t = (int32_t)blockIdx.x;
+  const int32_t a = t == 0 ? r : (r + t) % m;
+  const int32_t b = t == 0 ? m : (r - t + m) % m;
+  const int32_t A = a < b ? a : b, B = a < b ? b : a;
   if (B >= nb) return;  // the padding block of an odd block count (the whole workgroup)
-  // A diagonal tile adds both sides of its sums to the same accumulators: load, add, store in
-  // program order. An off-diagonal tile's two blocks are disjoint, and no other tile of the launch
-  // touches them, so each accumulator word takes exactly one add per launch: a device atomic add
-  // (the same IEEE double addition) that no wave waits for.
-  if (A == B)
-    sym_tile<W, I, POT, MODE, ROT, LAW, PIPE, 1>(jarr, n, A, B, eps2_arg, nullptr, red, AdaptIn{}, acc64);
-  else
-    sym_tile<W, I, POT, MODE, ROT, LAW, PIPE, 2>(jarr, n, A, B, eps2_arg, nullptr, red, AdaptIn{}, acc64);
+  sym_tile<W, I, POT, MODE, ROT, LAW, PIPE, 2>(jarr, n, A, B, eps2_arg, nullptr, red, ad, acc64);
 }
 
-// The end of the round schedule: particle i's sums are the K accumulator copies acc64[k][c][i],
-// added in copy order.
+// The diagonal tiles (A, A) of the round schedule, one workgroup per block, before any round: a
+// diagonal tile adds both sides of its sums to the same accumulators, with loads, adds and stores
+// in program order. The adaptive mode launches its MODE_ADAPT_DIAG form.
+template <int W, int I, bool POT, int MODE, int ROT, int LAW, int PIPE>
+__global__ __launch_bounds__(W * 64) void force_sym_round_diag_kernel(const float4* __restrict__ jarr, int64_t n,
+                                                                      float eps2_arg, double* __restrict__ acc64,
+                                                                      AdaptIn ad) {
+  __shared__ float red[2][W][POT ? 4 : 3][64];
+  const int32_t A = (int32_t)blockIdx.x;
+  sym_tile<W, I, POT, MODE, ROT, LAW, PIPE, 1>(jarr, n, A, A, eps2_arg, nullptr, red, ad, acc64);
+}
+
+// The end of the round schedule: the sums at position p are the K accumulator copies
+// acc64[k][c][p], added in copy order. perm (nullable): positions are in sorted order (the
+// adaptive mode) and position p holds particle perm[p], whose outputs are written at its own index.
 __global__ __launch_bounds__(kReduceBS) void reduce_rounds(int64_t n, int64_t stride, const double* __restrict__ acc64,
                                                            int32_t K, LawScale ls, double* __restrict__ acc,
                                                            double* __restrict__ pot, double* __restrict__ vel,
-                                                           double hh, NextStep nx, EnergyFuse ef) {
-  auto body = [&](int64_t i, double* en) {
+                                                           double hh, NextStep nx, EnergyFuse ef,
+                                                           const uint32_t* __restrict__ perm) {
+  auto body = [&](int64_t p, double* en) {
+    const int64_t i = perm ? (int64_t)perm[p] : p;
     const PState ps = load_state(i, stride, ls, vel, nx, ef.mass, en != nullptr);
     double a[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       a[c] = 0.0;
       if (c == 3 && !pot) continue;
-      const double* q = acc64 + (int64_t)c * n + i;
+      const double* q = acc64 + (int64_t)c * n + p;
       const int64_t cs = 4 * n;  // one copy
       double t = q[0];
       for (int k = 1; k < K; ++k) t += q[k * cs];

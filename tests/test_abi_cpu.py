@@ -326,7 +326,7 @@ def test_workspace_stays_linear_beyond_the_symmetric_cap(nb):
         rc, w1m = _ws_size(nb, _cfg(nb, precision=prec), 1 << 20)
         assert rc == 0 and w1m > (1 << 33)  # ~8.6 GB of tile partials on the tuned 2048-particle tiles
         rc, w4m = _ws_size(nb, _cfg(nb, precision=prec), 1 << 22)
-        assert rc == 0 and w4m < 400 * (1 << 22) and w4m < w1m  # 8 accumulator copies: 256 B per particle
+        assert rc == 0 and w4m < 240 * (1 << 22) and w4m < w1m  # 4 accumulator copies: 128 B per particle
         rc, wb = _ws_size(nb, _cfg(nb, precision=prec), 1 << 22, 10, 5)  # with a backward pass
         assert rc == 0 and wb < 1000 * (1 << 22)
     v = ctypes.c_int32()
@@ -338,13 +338,13 @@ def test_workspace_stays_linear_beyond_the_symmetric_cap(nb):
 
 def test_round_schedule_flag_workspace(nb):
     """NBODY_FLAG_SYM_ROUNDS (8) is accepted and puts a single-system FP32 pass on per-particle
-    accumulators: 8 copies of 32 bytes per particle instead of the slot planes (8.6 GB at 1M)."""
+    accumulators: 4 copies of 32 bytes per particle instead of the slot planes (8.6 GB at 1M)."""
     n = 1 << 20
     for prec in (1, 2, 3, 4):
         rc, slots = _ws_size(nb, _cfg(nb, precision=prec), n)
         rc2, rounds = _ws_size(nb, _cfg(nb, precision=prec, flags=8), n)
         assert rc == 0 and rc2 == 0
-        assert 256 * n < rounds < 400 * n < slots, (prec, rounds, slots)
+        assert 128 * n < rounds < 240 * n < slots, (prec, rounds, slots)
     rc, w64 = _ws_size(nb, _cfg(nb, precision=0, flags=8), n)  # FP64 has no symmetric tiles
     rc2, w64b = _ws_size(nb, _cfg(nb, precision=0), n)
     assert rc == 0 and rc2 == 0 and w64 == w64b

@@ -13,7 +13,7 @@ from paper_2511_02655_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TOL_P = {"fp32c": 1e-6, "fp32": 1e-5, "fp32ds": 1e-6}
+TOL_P = {"fp32c": 1e-6, "fp32": 1e-5, "fp32ds": 1e-6, "fp32a": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -37,6 +37,8 @@ def host(t):
 
 def _bound(pos, mass, eps, prec, idx=None):
     from oracle import bounds
+    if prec == "fp32a":
+        return bounds.fp32_force_bound(pos, mass, eps, adaptive=True, idx=idx)
     return bounds.fp32_force_bound(pos, mass, eps, accumulate_plain=(prec == "fp32"),
                                    exact_coords=(prec == "fp32ds"), idx=idx)
 
@@ -44,10 +46,11 @@ def _bound(pos, mass, eps, prec, idx=None):
 @pytest.mark.parametrize("n", [1, 2, 100, 1023, 1024, 1025, 2048, 2049, 5000])
 def test_rounds_vs_oracle(nb, oracle, n):
     """Sizes below, at and across one and two blocks (odd and even block counts: the padding
-    block of the circle method), every FP32 mode, with and without the potential."""
+    block of the circle method), every FP32 mode (the adaptive one sorted, on its adaptive
+    tiles), with and without the potential."""
     s = inputs.uniform_cube(n, 1200 + n)
     a_r, p_r = oracle.forces(s.pos, s.mass, eps=1e-2)
-    for prec in ("fp32c", "fp32", "fp32ds"):
+    for prec in ("fp32c", "fp32", "fp32ds", "fp32a"):
         B = _bound(s.pos, s.mass, 1e-2, prec) if n > 1 else None
         for want_pot in (True, False):
             a, p = nb.forces(dev(s.pos), dev(s.mass), eps=1e-2, precision=prec, want_pot=want_pot,
@@ -68,16 +71,19 @@ def test_rounds_lennard_jones_vs_oracle(nb, oracle):
     for n in (100, 3000):
         pos, mass, _, _ = _gas(n, 1201 + n)
         a_r, p_r = oracle.lj_forces(pos, mass, 1.1, 0.7)
-        for prec in ("fp32c", "fp32", "fp32ds"):
+        for prec in ("fp32c", "fp32", "fp32ds", "fp32a"):
             a, p = nb.lj_forces(dev(pos), dev(mass), sigma=1.1, epsilon=0.7, precision=prec, want_pot=True,
                                 flags=nb.FLAG_SYM_ROUNDS)
-            check_lj(host(a), host(p), a_r, p_r, pos, mass, prec, sigma=1.1, epsilon=0.7)
+            # the adaptive mode's separations are never worse than the compensated mode's float
+            # ones (exact on near sub-block pairs), so the compensated bound holds for it
+            check_lj(host(a), host(p), a_r, p_r, pos, mass, "fp32c" if prec == "fp32a" else prec, sigma=1.1,
+                     epsilon=0.7)
 
 
 def test_rounds_deterministic_and_consistent(nb):
     """Repeated calls are bitwise equal; a step's accelerations and potential are bitwise those of
-    a force pass at the new positions; trajectories do not depend on the energy trace; the
-    adaptive mode runs as the double-float mode on this schedule."""
+    a force pass at the new positions; trajectories do not depend on the energy trace; in the
+    adaptive mode five single steps equal a five-step rollout, with and without the trace."""
     import torch
     n = 7000
     s = inputs.plummer(n, 1202)
@@ -98,9 +104,17 @@ def test_rounds_deterministic_and_consistent(nb):
         nb.rollout(p_, v_, m, a1.clone(), 1e-3, 5, energy_trace=trace, precision="fp32c", flags=F)
         outs.append((host(p_), host(v_)))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
-    aa, _ = nb.forces(x, m, precision="fp32a", flags=F)
-    ad, _ = nb.forces(x, m, precision="fp32ds", flags=F)
-    assert torch.equal(aa, ad)
+    b1, q1 = nb.forces(x, m, precision="fp32a", want_pot=True, flags=F)
+    b2, q2 = nb.forces(x, m, precision="fp32a", want_pot=True, flags=F)
+    assert torch.equal(b1, b2) and torch.equal(q1, q2)
+    p1, v1 = dev(s.pos), dev(s.vel)
+    a_s = b1.clone()
+    for _ in range(5):
+        nb.step(p1, v1, m, a_s, 1e-3, precision="fp32a", flags=F)
+    for trace in (False, True):
+        p_, v_ = dev(s.pos), dev(s.vel)
+        nb.rollout(p_, v_, m, b1.clone(), 1e-3, 5, energy_trace=trace, precision="fp32a", flags=F)
+        assert torch.equal(p_, p1) and torch.equal(v_, v1), trace
 
 
 def test_rounds_match_slots(nb):
@@ -112,7 +126,7 @@ def test_rounds_match_slots(nb):
     a64, _ = nb.forces(x, m, precision="fp64")
     mag = torch.sqrt((a64 ** 2).sum(0))
     floor = 1e-6 * float(torch.sqrt((mag ** 2).mean()))
-    for prec in ("fp32c", "fp32ds"):
+    for prec in ("fp32c", "fp32ds", "fp32a"):
         ar, _ = nb.forces(x, m, precision=prec, flags=nb.FLAG_SYM_ROUNDS)
         asl, _ = nb.forces(x, m, precision=prec)
         er = float(torch.max(torch.sqrt(((ar - a64) ** 2).sum(0)) / torch.clamp(mag, min=floor)))
@@ -137,6 +151,31 @@ def test_rounds_taken_beyond_the_slot_cap(nb, oracle):
     idx = np.unique(np.concatenate([np.argsort(d)[-32:], g.choice(n, 32, replace=False)]))
     ref, _ = oracle.forces_sample(s.pos, s.mass, idx, eps=1e-2)
     B = _bound(s.pos, s.mass, 1e-2, "fp32c", idx=idx)
+    dd = np.sqrt(np.sum((host(a)[:, idx] - ref) ** 2, axis=0))
+    assert np.max(dd / B) <= 1.0, float(np.max(dd / B))
+
+
+def test_adaptive_rounds_beyond_the_slot_cap(nb, oracle):
+    """N = 1.6M at eps = 1e-3 in the adaptive mode, which the library runs on the round schedule
+    (sorted, adaptive tiles): every particle within 1e-5 of the FP64 GPU path, and sampled
+    particles, including the worst, against the oracle within the adaptive mode's bound."""
+    import torch
+    n, eps = 1600000, 1e-3
+    s = inputs.plummer(n, 1208)
+    x, m = dev(s.pos), dev(s.mass)
+    a, _ = nb.forces(x, m, eps=eps, precision="fp32a")
+    af, _ = nb.forces(x, m, eps=eps, precision="fp32a", flags=nb.FLAG_SYM_ROUNDS)
+    assert torch.equal(a, af)
+    a64, _ = nb.forces(x, m, eps=eps, precision="fp64")
+    mag = torch.sqrt((a64 ** 2).sum(0))
+    floor = 1e-6 * float(torch.sqrt((mag ** 2).mean()))
+    e = host(torch.sqrt(((a - a64) ** 2).sum(0)) / torch.clamp(mag, min=floor))
+    print("adaptive rounds 1.6M eps 1e-3: max e %.3e" % e.max())
+    assert e.max() <= 1e-5
+    g = np.random.Generator(np.random.PCG64(1209))
+    idx = np.unique(np.concatenate([np.argsort(e)[-32:], g.choice(n, 32, replace=False)]))
+    ref, _ = oracle.forces_sample(s.pos, s.mass, idx, eps=eps)
+    B = _bound(s.pos, s.mass, eps, "fp32a", idx=idx)
     dd = np.sqrt(np.sum((host(a)[:, idx] - ref) ** 2, axis=0))
     assert np.max(dd / B) <= 1.0, float(np.max(dd / B))
 
