@@ -188,9 +188,9 @@ int nbody_step(const nbody_config *cfg, int64_t n, double dt, double *pos, doubl
  *   cfg->workspace must be NULL and cfg->workspace_bytes 0 (else NBODY_ERR_INVALID_ARG);
  *   a single system only (n_systems == 1, offsets NULL; else NBODY_ERR_UNSUPPORTED);
  *   n whose step needs more than NBODY_NOALLOC_SCRATCH_BYTES of workspace even one-sided
- *   with one j-range (beyond about 1.9 million particles in FP64 and in the double-float and
- *   adaptive modes, 2.5 million in the other FP32 modes; the round schedule serves up to about
- *   1.33 and 1.58 million) returns NBODY_ERR_WORKSPACE before any device work.
+ *   with one j-range (beyond about 1.95 million particles in FP64 and in the double-float and
+ *   adaptive modes, 2.6 million in the other FP32 modes; the round schedule serves up to about
+ *   1.2-1.6 million, by mode) returns NBODY_ERR_WORKSPACE before any device work.
  * Every call on one GPU shares that GPU's array (nothing in it needs to start at zero): calls
  * that overlap on one GPU (other host threads, other streams without ordering) race. */
 #define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
