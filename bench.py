@@ -17,7 +17,9 @@ sample of the same workload.
 
 Also reported (not part of the timed step): the paper's own workload, a Lennard-Jones
 gas of 10 000 particles in a box with reflective walls run for 2500 KDK steps, with and
-without the per-step energy reduction, in FP64 and FP32 (the "lj10k" leg).
+without the per-step energy reduction, in FP64 and FP32 (the "lj10k" leg); and the same
+force pass on the round schedule, whose workspace is linear in N, beside the default slot
+schedule (the "round_schedule" leg: time, workspace, max error on every particle).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
        python bench.py --lj-only     (only the Lennard-Jones leg, printed as one JSON line)
@@ -222,6 +224,8 @@ def main():
     out["force_pass_reps"] = force_pass_reps(nb, torch, np, pos0, mass, eps, prec, n)
     if not args.no_extras:
         out["error"] = force_errors(nb, torch, np, pos0, mass, s, eps, prec)
+        if prec != "fp64":
+            out["round_schedule"] = round_schedule_leg(nb, torch, np, pos0, mass, eps, prec, n)
         out["cube1k"] = cube1k_leg(nb, torch, np, inputs, dev)
         out["plummer64k"] = plummer64k_leg(nb, torch, np, inputs, dev)
         out["adjoint"] = adjoint_leg(nb, torch, np, inputs, dev)
@@ -286,6 +290,46 @@ def force_pass_reps(nb, torch, np, pos0, mass, eps, prec, n, warm=2, reps=10):
         peak_at_clk = 256 * 256 * float(np.median(sclk)) * 1e6
         out["pct_fp32_peak_at_sampled_sclk"] = 100.0 * flops / peak_at_clk
     return out
+
+
+def round_schedule_leg(nb, torch, np, pos0, mass, eps, prec, n, warm=1, reps=5):
+    """The headline force pass on the round schedule (NBODY_FLAG_SYM_ROUNDS: per-particle double
+    accumulators, workspace linear in N) beside the default slot schedule: one step's workspace
+    under each, the pass timed as in force_pass_reps, and its max relative error on every
+    particle against the FP64 GPU path."""
+    import ctypes
+    log("round schedule: %d warm-up + %d timed launches" % (warm, reps))
+    lib = nb.lib()
+
+    def ws(flags):
+        c = nb._Cfg(prec, 1.0, eps, None, flags, None)
+        b = ctypes.c_size_t()
+        rc = lib.nbody_workspace_size(ctypes.byref(c.cfg), n, 1, 0, ctypes.byref(b))
+        return int(b.value) if rc == 0 else None
+
+    F = nb.FLAG_SYM_ROUNDS
+    acc = torch.empty((3, n), dtype=torch.float64, device=pos0.device)
+    for _ in range(warm):
+        nb.forces(pos0, mass, eps=eps, precision=prec, out_acc=acc, flags=F)
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nb.forces(pos0, mass, eps=eps, precision=prec, out_acc=acc, flags=F)
+        e1.record()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in evs])
+    med = float(np.median(ms))
+    a64, _ = nb.forces(pos0, mass, eps=eps, precision="fp64")
+    mag = torch.sqrt((a64 ** 2).sum(0))
+    floor = 1e-6 * float(torch.sqrt((mag ** 2).mean()))
+    e = torch.sqrt(((acc - a64) ** 2).sum(0)) / torch.clamp(mag, min=floor)
+    return {"median_ms": med, "min_ms": float(ms.min()), "max_ms": float(ms.max()), "reps": reps,
+            "pct_fp32_peak": 100.0 * FLOP_PER_INTERACTION * float(n) * float(n) / (med * 1e-3) / PEAK_FP32,
+            "max_e_all_particles": float(e.max()), "workspace_bytes_step": ws(F),
+            "workspace_bytes_step_slot_schedule": ws(0)}
 
 
 def adjoint_1m_leg(nb, torch, np, pos0, mass, s, eps, prec):
