@@ -24,6 +24,7 @@ schedule (the "round_schedule" leg: time, workspace, max error on every particle
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
        python bench.py --lj-only     (only the Lennard-Jones leg, printed as one JSON line)
        python bench.py --adjoint-1m-only  (only the adjoint pass at the headline size)
+       python bench.py --round-schedule-only  (only the headline pass on the round schedule)
 """
 import argparse
 import hashlib
@@ -90,6 +91,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--lj-only", action="store_true")
     ap.add_argument("--adjoint-1m-only", action="store_true")
+    ap.add_argument("--round-schedule-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole system on a single MI355X "
@@ -120,6 +122,10 @@ def main():
     pos0 = torch.from_numpy(s.pos).to(dev)
     vel0 = torch.from_numpy(s.vel).to(dev)
     mass = torch.from_numpy(s.mass).to(dev)
+    if args.round_schedule_only:
+        leg = round_schedule_leg(nb, torch, np, pos0, mass, eps, prec, n, warm=1, reps=3)
+        print(json.dumps({"round_schedule": leg}), flush=True)
+        return
     if args.adjoint_1m_only:
         print(json.dumps({"adjoint_1m": adjoint_1m_leg(nb, torch, np, pos0, mass, s, eps, prec)}), flush=True)
         return
