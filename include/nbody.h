@@ -110,21 +110,22 @@ typedef enum {
 #define NBODY_FLAG_PER_PASS 4u      /* batched rollouts: one launch per pass even where
                                       every step in one launch would be chosen (the
                                       baseline of that choice; results are identical) */
-#define NBODY_FLAG_SYM_ROUNDS 8u    /* single-system FP32 force passes on the round schedule:
-                                      symmetric tiles of 1024-particle blocks run in rounds
-                                      of disjoint block pairs (circle method), each tile
-                                      adding its sums to per-particle double accumulators,
-                                      so the workspace is linear in n (32 K bytes per
-                                      particle for K accumulator copies: K = 4 where the
-                                      workspace allows, else 2 or 1) instead of one float
-                                      slot per particle and block. With K >= 2 the launches
-                                      (K/2 rounds each) alternate between two streams the
-                                      library creates per device and keeps; the call's
-                                      stream waits for both. Deterministic for a given K;
-                                      not bitwise the slot schedule's sums (another order).
-                                      The library takes this schedule by itself where the
-                                      slot schedule's partial sums would exceed its cap
-                                      (16 GiB, near 1.5 million particles). The adaptive mode
+#define NBODY_FLAG_SYM_ROUNDS 8u    /* single-system FP32 force and adjoint passes on the
+                                      round schedule: symmetric tiles of 1024-particle
+                                      blocks run in rounds of disjoint block pairs (circle
+                                      method), each tile adding its sums to per-particle
+                                      double accumulators, so the workspace is linear in n
+                                      (32 K bytes per particle for K accumulator copies:
+                                      K = 4 where the workspace allows, else 2 or 1) instead
+                                      of one float slot per particle and block. With K >= 2
+                                      the launches (K/2 rounds each) alternate between two
+                                      streams the library creates per device and keeps; the
+                                      call's stream waits for both. Deterministic for a
+                                      given K; not bitwise the slot schedule's sums (another
+                                      order). The library takes this schedule by itself
+                                      where the slot schedule's partial sums would exceed
+                                      its cap (16 GiB: forces near 1.5 million particles,
+                                      the adjoint just above 1 million). The adaptive mode
                                       sorts and runs its adaptive tiles on it as well. */
 
 typedef struct {

@@ -232,16 +232,18 @@ int round_streams(hipStream_t (&out)[2]) {
 }
 
 // The rounds 0 .. nbr - 2 of the round schedule after the diagonal tiles (enqueued on st), into K
-// accumulator copies from a64. K = 1: one round per launch on st. K >= 2: launch L runs the K/2
-// rounds from L K/2 on round stream L mod 2, into copies (L mod 2) K/2 .. (L mod 2) K/2 + K/2 - 1;
-// the round streams start after st's work so far and st waits for both at the end, also when a
-// launch failed (the workspace must not be reused under running tiles).
-int run_rounds(hipStream_t st, RoundFn fn, const float4* jb, int64_t ns, int64_t nb, int64_t nbr, float eps2,
-               double* a64, int K, const AdaptIn& ad) {
+// accumulator copies of 4 ns doubles from a64; launch(grid, stream, r0, copies) enqueues the
+// rounds r0 .. r0 + grid.y - 1 into the copies from `copies`. K = 1: one round per launch on st.
+// K >= 2: launch L runs the K/2 rounds from L K/2 on round stream L mod 2, into copies
+// (L mod 2) K/2 .. (L mod 2) K/2 + K/2 - 1; the round streams start after st's work so far and
+// st waits for both at the end, also when a launch failed (the workspace must not be reused
+// under running tiles).
+template <typename Launch>
+int run_rounds(hipStream_t st, int64_t ns, int64_t nbr, double* a64, int K, const char* what, Launch&& launch) {
   if (K == 1) {
     for (int64_t r = 0; r + 1 < nbr; ++r) {
-      fn(dim3((unsigned)(nbr / 2)), st, jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, eps2, a64, ad);
-      LAUNCH_CHECK("force_sym_round_kernel");
+      launch(dim3((unsigned)(nbr / 2)), st, (int32_t)r, a64);
+      LAUNCH_CHECK(what);
     }
     return NBODY_OK;
   }
@@ -263,8 +265,7 @@ int run_rounds(hipStream_t st, RoundFn fn, const float4* jb, int64_t ns, int64_t
   int64_t L = 0;
   for (int64_t r = 0; r + 1 < nbr && err == hipSuccess; r += KH, ++L) {
     const unsigned ky = (unsigned)std::min<int64_t>(KH, nbr - 1 - r);
-    fn(dim3((unsigned)(nbr / 2), ky), rs[L & 1], jb, ns, (int32_t)nb, (int32_t)nbr, (int32_t)r, eps2,
-       a64 + (size_t)(L & 1) * KH * 4 * ns, ad);
+    launch(dim3((unsigned)(nbr / 2), ky), rs[L & 1], (int32_t)r, a64 + (size_t)(L & 1) * KH * 4 * ns);
     err = hipGetLastError();
   }
   hipError_t j0 = hipEventRecord(ev.e[1], rs[0]);
@@ -276,9 +277,27 @@ int run_rounds(hipStream_t st, RoundFn fn, const float4* jb, int64_t ns, int64_t
     (void)hipStreamSynchronize(rs[1]);
     return fail(NBODY_ERR_DEVICE, "round streams: %s", hipGetErrorString(j0 != hipSuccess ? j0 : j1));
   }
-  if (err != hipSuccess) return fail(NBODY_ERR_DEVICE, "launch of force_sym_round_kernel failed: %s", hipGetErrorString(err));
+  if (err != hipSuccess) return fail(NBODY_ERR_DEVICE, "launch of %s failed: %s", what, hipGetErrorString(err));
   return NBODY_OK;
 }
+
+// The adjoint pass on the round schedule: the same tile shape, [comp].
+using AdjRoundFn = void (*)(dim3, hipStream_t, const float4* jadj, int64_t n, int32_t nb, int32_t nbr, int32_t r,
+                            float eps2, double* acc64);
+using AdjRoundDiagFn = void (*)(dim3, hipStream_t, const float4* jadj, int64_t n, float eps2, double* acc64);
+template <bool COMP>
+void launch_adj_round(dim3 g, hipStream_t st, const float4* jadj, int64_t n, int32_t nb, int32_t nbr, int32_t r,
+                      float eps2, double* acc64) {
+  hipLaunchKernelGGL((adjoint_sym_round_kernel<kRoundW, kRoundI, COMP, 1>), g, dim3(kRoundW * 64), 0, st, jadj, n, nb,
+                     nbr, r, eps2, acc64);
+}
+template <bool COMP>
+void launch_adj_round_diag(dim3 g, hipStream_t st, const float4* jadj, int64_t n, float eps2, double* acc64) {
+  hipLaunchKernelGGL((adjoint_sym_round_diag_kernel<kRoundW, kRoundI, COMP, 1>), g, dim3(kRoundW * 64), 0, st, jadj,
+                     n, eps2, acc64);
+}
+const AdjRoundFn kAdjRound[2] = {launch_adj_round<false>, launch_adj_round<true>};
+const AdjRoundDiagFn kAdjRoundDiag[2] = {launch_adj_round_diag<false>, launch_adj_round_diag<true>};
 
 // [law][pot][mode]: modes 0-2 as force_mode, 3 the adaptive mode (sorted particles)
 #define RND_POT(POT, LAW) \
@@ -499,7 +518,7 @@ bool find_entry(int kernel, int prec, int64_t n, Tile& out);
 // A single-system force pass whose slots would exceed the cap runs on the table's tile for the
 // largest systems (the largest block, so the fewest slots) when that fits, else on the round
 // schedule (4 doubles per particle) when that fits, else one-sided (no partial sums with one
-// j-range); an adjoint pass runs one-sided. The default cap is reached near 1.5M particles by the
+// j-range); an adjoint pass on the round schedule when that fits, else one-sided. The default cap is reached near 1.5M particles by the
 // tuned table's symmetric entries. The allocation-free step (on its own thread, for its own call)
 // sets the cap to its static scratch and a level that skips the first choices of that order:
 // 1 starts at the largest block, 2 at the round schedule, 3 at the one-sided pass.
@@ -530,9 +549,9 @@ Tile lookup_tile(int kernel, int prec, int64_t n) {
     if (bk == NBODY_KERNEL_FORCE) {
       const Tile big = lookup_tile_raw(kernel, prec, (int64_t)1 << 40);
       if (g_sym_level <= 1 && big.sym >= 0 && slot_bytes(big) <= g_sym_cap) return big;
-      // the round schedule's accumulators: 4 doubles per particle
-      if (g_sym_level <= 2 && 32.0 * (double)std::max<int64_t>(n, 1) <= g_sym_cap) return rounds_tile(kernel, prec);
     }
+    // the round schedule's accumulators: 4 doubles per particle
+    if (g_sym_level <= 2 && 32.0 * (double)std::max<int64_t>(n, 1) <= g_sym_cap) return rounds_tile(kernel, prec);
     // the one-sided variant of the built-in defaults, one j-range per block column
     Tile o{};
     o.variant = 0;
@@ -548,11 +567,14 @@ Tile lookup_tile(int kernel, int prec, int64_t n) {
   return t;
 }
 
-// The tile of a single-system force pass under cfg: NBODY_FLAG_SYM_ROUNDS puts every FP32 pass on
-// the round schedule.
+// The tile of a single-system force or adjoint pass under cfg: NBODY_FLAG_SYM_ROUNDS puts every
+// FP32 pass on the round schedule.
 Tile single_force_tile(const nbody_config* cfg, int kernel, int prec, int64_t n) {
   if ((cfg->flags & NBODY_FLAG_SYM_ROUNDS) && !is_fp64(prec)) return rounds_tile(kernel, prec);
   return lookup_tile(kernel, prec, n);
+}
+Tile single_adj_tile(const nbody_config* cfg, int prec, int64_t n) {
+  return single_force_tile(cfg, NBODY_KERNEL_ADJOINT, prec, n);
 }
 
 Tile lookup_tile_raw(int kernel, int prec, int64_t n) {
@@ -813,6 +835,8 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     return S > 1 ? (size_t)S * 4 * nd : 0;
   };
   auto single_adj_part = [&](const Tile& t, int64_t ns) -> size_t {
+    if (t.rounds)  // the round schedule's accumulator copies
+      return (size_t)round_copies(ns, g_sym_cap) * 4 * (size_t)ns * sizeof(double);
     if (t.sym >= 0) {
       const int64_t nb = cdiv(ns, (int64_t)t.tj);
       return (size_t)nb * 4 * (size_t)ns * sizeof(float);
@@ -873,13 +897,13 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
         force_part =
             std::max(force_part, single_force_part(single_force_tile(cfg, force_kernel_id(lw, false), prec, ns), ns));
       if (need & NEED_BACKWARD)
-        adj_part = std::max(adj_part, single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns), ns));
+        adj_part = std::max(adj_part, single_adj_part(single_adj_tile(cfg, prec, ns), ns));
     }
   } else {
     for (int lw : {LAW_GRAV, LAW_LJ})
       force_part =
           std::max(force_part, single_force_part(single_force_tile(cfg, force_kernel_id(lw, false), prec, n), n));
-    if (need & NEED_BACKWARD) adj_part = single_adj_part(lookup_tile(NBODY_KERNEL_ADJOINT, prec, n), n);
+    if (need & NEED_BACKWARD) adj_part = single_adj_part(single_adj_tile(cfg, prec, n), n);
   }
   p.sz_jbuf = (size_t)n * std::max(jvec_bytes(prec), (need & NEED_BACKWARD) ? jadj_bytes(prec) : (size_t)0);
   p.off_jbuf = take(p.sz_jbuf);
@@ -1280,7 +1304,12 @@ int round_tiles(Ctx& c, int64_t ns, const float4* jb, int law, int pot_on, int m
   LAUNCH_CHECK("fill_f64");
   kRoundDiag[law][pot_on][mode](dim3((unsigned)nb), c.st, jb, ns, (float)c.eps2, a64, ad);
   LAUNCH_CHECK("force_sym_round_diag_kernel");
-  return run_rounds(c.st, kRound[law][pot_on][mode], jb, ns, nb, nbr, (float)c.eps2, a64, K, ad);
+  const RoundFn fn = kRound[law][pot_on][mode];
+  const float eps2 = (float)c.eps2;
+  return run_rounds(c.st, ns, nbr, a64, K, "force_sym_round_kernel",
+                    [&](dim3 g, hipStream_t s, int32_t r0, double* acc) {
+                      fn(g, s, jb, ns, (int32_t)nb, (int32_t)nbr, r0, eps2, acc, ad);
+                    });
 }
 
 template <typename Tail>
@@ -1568,7 +1597,31 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
   auto single = [&](int64_t b, int64_t e) -> int {
     const int64_t ns = e - b;
     if (ns == 0) return NBODY_OK;
-    Tile t = lookup_tile(NBODY_KERNEL_ADJOINT, prec, ns);
+    Tile t = single_adj_tile(c.cfg, prec, ns);
+    if (t.rounds) {
+      // round schedule: zero the K accumulator copies, the diagonal tiles, the rounds, then the
+      // per-particle update of the gradients
+      const int64_t nb = cdiv(ns, (int64_t)kRoundBlock), nbr = nb + (nb & 1);
+      if (nbr > 0x7fffffffLL) return fail(NBODY_ERR_UNSUPPORTED, "too many blocks for the round schedule");
+      const int K = round_copies(ns, g_sym_cap);
+      TRY(check_part(c, (size_t)K * 4 * ns * sizeof(double), "adjoint_sym_round_kernel"));
+      double* a64 = (double*)(c.ws + c.plan.off_part);
+      hipLaunchKernelGGL(fill_f64, grid1d(K * 4 * ns), dim3(256), 0, c.st, a64, K * 4 * ns, 0.0);
+      LAUNCH_CHECK("fill_f64");
+      const float4* ja = (const float4*)jadj + 2 * b;
+      const float e2 = (float)eps2;
+      kAdjRoundDiag[comp](dim3((unsigned)nb), c.st, ja, ns, e2, a64);
+      LAUNCH_CHECK("adjoint_sym_round_diag_kernel");
+      const AdjRoundFn fn = kAdjRound[comp];
+      TRY(run_rounds(c.st, ns, nbr, a64, K, "adjoint_sym_round_kernel",
+                     [&](dim3 g, hipStream_t s, int32_t r0, double* acc) {
+                       fn(g, s, ja, ns, (int32_t)nb, (int32_t)nbr, r0, e2, acc);
+                     }));
+      hipLaunchKernelGGL(adjoint_reduce_rounds, grid1d(ns), dim3(256), 0, c.st, ns, n, (int32_t)K,
+                         (const double*)a64, c.cfg->G, gpos + b, gmass + b);
+      LAUNCH_CHECK("adjoint_reduce_rounds");
+      return NBODY_OK;
+    }
     if (t.sym >= 0) {
       const AdjSymVariant& sv = kAdjSym32[t.sym];
       const int64_t nb = cdiv(ns, (int64_t)t.tj);

@@ -1987,11 +1987,12 @@ __global__ __launch_bounds__(256) void adjoint_reduce(int64_t count, int64_t str
 // taken directly, so every particle carries 4 accumulators instead of 8 - half the
 // registers and lane rotations. Tiles, lane rotation and slots as in sym_tile:
 // part[(slot*4 + c)*n + p], c = gx, gy, gz, M. Diagonal tiles run one-sided with the
-// self pair masked (r3 = 0 removes every term).
-template <int W, int I, bool COMP, int ROT>
+// self pair masked (r3 = 0 removes every term). OUT 1 and 2 (the round schedule) add the sums
+// to double accumulators acc64 [4][n] instead, as sym_tile does.
+template <int W, int I, bool COMP, int ROT, int OUT = 0>
 __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, int64_t n, int32_t A, int32_t B,
                                              float eps2_arg, float* __restrict__ part,
-                                             float (&red)[2][W][4][64]) {
+                                             float (&red)[2][W][4][64], double* __restrict__ acc64 = nullptr) {
   constexpr int BI = W * 64 * I;
   constexpr int NSUB = BI / 64;
   const bool diag = (A == B);
@@ -2146,7 +2147,13 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
 #pragma unroll
         for (int ww = 0; ww < W; ++ww) sum += red[sb & 1][ww][c][l];
         const int64_t j = Bbase + (int64_t)sb * 64 + l;
-        if (j < n) part[((int64_t)A * 4 + c) * n + j] = sum;
+        if constexpr (OUT == 0) {
+          if (j < n) part[((int64_t)A * 4 + c) * n + j] = sum;
+        } else if constexpr (OUT == 1) {
+          if (j < n) acc64[(int64_t)c * n + j] += (double)sum;
+        } else {
+          if (j < n) unsafeAtomicAdd(acc64 + (int64_t)c * n + j, (double)sum);
+        }
       }
     }
     if (COMP) {
@@ -2176,12 +2183,46 @@ __device__ __forceinline__ void adj_sym_tile(const float4* __restrict__ jadj, in
     if (i < n)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        float v = ai[c][u];
-        if constexpr (HL_LDS) v = hl_w[(c * I + u) * 64] + hl_w[((4 + c) * I + u) * 64];
-        else if constexpr (COMP) v = hi[c][u] + lo[c][u];
-        part[((int64_t)B * 4 + c) * n + i] = v;
+        if constexpr (OUT == 0) {
+          float v = ai[c][u];
+          if constexpr (HL_LDS) v = hl_w[(c * I + u) * 64] + hl_w[((4 + c) * I + u) * 64];
+          else if constexpr (COMP) v = hi[c][u] + lo[c][u];
+          part[((int64_t)B * 4 + c) * n + i] = v;
+        } else {
+          double v = (double)ai[c][u];
+          if constexpr (HL_LDS) v = (double)hl_w[(c * I + u) * 64] + (double)hl_w[((4 + c) * I + u) * 64];
+          else if constexpr (COMP) v = (double)hi[c][u] + (double)lo[c][u];
+          if constexpr (OUT == 1) acc64[(int64_t)c * n + i] += v;
+          else unsafeAtomicAdd(acc64 + (int64_t)c * n + i, v);
+        }
       }
   }
+}
+
+// The adjoint pass on the round schedule (the pairing, copies and atomic adds of
+// force_sym_round_kernel; its diagonal tiles in adjoint_sym_round_diag_kernel).
+template <int W, int I, bool COMP, int ROT>
+__global__ __launch_bounds__(W * 64) void adjoint_sym_round_kernel(const float4* __restrict__ jadj, int64_t n,
+                                                                   int32_t nb, int32_t nbr, int32_t r0, float eps2,
+                                                                   double* __restrict__ acc64) {
+  __shared__ float red[2][W][4][64];
+  const int32_t r = r0 + (int32_t)blockIdx.y;
+  if (r >= nbr - 1) return;  // past the last round (the whole workgroup)
+  acc64 += (int64_t)blockIdx.y * 4 * n;
+  const int32_t m = nbr - 1, t = (int32_t)blockIdx.x;
+  const int32_t a = t == 0 ? r : (r + t) % m;
+  const int32_t b = t == 0 ? m : (r - t + m) % m;
+  const int32_t A = a < b ? a : b, B = a < b ? b : a;
+  if (B >= nb) return;  // the padding block of an odd block count (the whole workgroup)
+  adj_sym_tile<W, I, COMP, ROT, 2>(jadj, n, A, B, eps2, nullptr, red, acc64);
+}
+
+template <int W, int I, bool COMP, int ROT>
+__global__ __launch_bounds__(W * 64) void adjoint_sym_round_diag_kernel(const float4* __restrict__ jadj, int64_t n,
+                                                                        float eps2, double* __restrict__ acc64) {
+  __shared__ float red[2][W][4][64];
+  const int32_t A = (int32_t)blockIdx.x;
+  adj_sym_tile<W, I, COMP, ROT, 1>(jadj, n, A, A, eps2, nullptr, red, acc64);
 }
 
 template <int W, int I, bool COMP, int ROT>
@@ -2236,6 +2277,30 @@ __global__ __launch_bounds__(256) void adjoint_reduce_sym(int64_t n, int64_t str
   g0[3] = gmass[i];
   double r[4] = {0, 0, 0, 0};
   sum_slots<4>(ps, ns, li, nbs, r);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) gpos[c * stride + i] = g0[c] + G * r[c];
+  gmass[i] = g0[3] + -G * r[3];
+}
+
+// The end of the adjoint round schedule: the K accumulator copies added in copy order,
+// gpos += G gx, gmass += -G M.
+__global__ __launch_bounds__(256) void adjoint_reduce_rounds(int64_t n, int64_t stride, int32_t K,
+                                                            const double* __restrict__ acc64, double G,
+                                                            double* __restrict__ gpos, double* __restrict__ gmass) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double g0[4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g0[c] = gpos[c * stride + i];
+  g0[3] = gmass[i];
+  double r[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double* q = acc64 + (int64_t)c * n + i;
+    double t = q[0];
+    for (int k = 1; k < K; ++k) t += q[(int64_t)k * 4 * n];
+    r[c] = t;
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) gpos[c * stride + i] = g0[c] + G * r[c];
   gmass[i] = g0[3] + -G * r[3];

@@ -220,3 +220,65 @@ def test_rounds_from_two_threads_on_two_streams(nb):
         for got in outs[k]:
             for x, y in zip(got, alone[k]):
                 assert torch.equal(x, y), k
+
+
+@pytest.mark.parametrize("n", [100, 1025, 3000])
+def test_rounds_adjoint_vs_oracle(nb, oracle, n):
+    """The adjoint pass on the round schedule (NBODY_FLAG_SYM_ROUNDS on the backward): a
+    one-step backward (two adjoint passes) in every FP32 mode against the oracle's discrete
+    adjoint, rel-L2 and per particle as the symmetric adjoint's parity test; bitwise repeatable;
+    the checkpoint interval leaves a 6-step backward bitwise unchanged."""
+    from test_gpu_parity import _grad_ok
+    s = inputs.plummer(n, 1210 + n)
+    g = np.random.Generator(np.random.PCG64(1211))
+    gxK, gvK = g.normal(size=(3, n)), g.normal(size=(3, n))
+    ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, 1e-3, 1, gxK, gvK, eps=1e-2)
+    tol = {"fp32c": 1e-4, "fp32": 1e-3, "fp32ds": 1e-4}
+    F = nb.FLAG_SYM_ROUNDS
+    for prec in ("fp32c", "fp32", "fp32ds"):
+        pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+        acc, _ = nb.forces(pos, mass, precision=prec, flags=F)
+        ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 1, ckpt_every=1, precision=prec, flags=F)
+        out = [host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 1, 1, precision=prec,
+                                                     flags=F)]
+        for a, b in zip(out, ref):
+            _grad_ok(a, b, tol[prec], "rounds %s n=%d" % (prec, n))
+        out2 = [host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 1, 1, precision=prec,
+                                                      flags=F)]
+        for a, b in zip(out, out2):
+            assert np.array_equal(a, b)
+    res = []
+    for ck in (1, 3, 6):
+        pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+        acc, _ = nb.forces(pos, mass, precision="fp32c", flags=F)
+        ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 6, ckpt_every=ck, precision="fp32c", flags=F)
+        res.append([host(t) for t in nb.rollout_backward(mass, ckpt, dev(gxK), dev(gvK), 1e-3, 6, ck,
+                                                         precision="fp32c", flags=F)])
+    for r in res[1:]:
+        for a, b in zip(r, res[0]):
+            assert np.array_equal(a, b)
+
+
+def test_adjoint_rounds_beyond_the_slot_cap(nb):
+    """N = 1.1M: the tuned symmetric adjoint tile's slots would exceed the 16 GiB cap, so the
+    adjoint pass runs on the round schedule by itself (bitwise equal to forcing it) and agrees
+    with the FP64 backward within the FP32 gradient tolerance."""
+    import torch
+    n = 1100000
+    s = inputs.plummer(n, 1212)
+    g = np.random.Generator(np.random.PCG64(1213))
+    gxK = dev(g.normal(size=(3, n)))
+    gvK = torch.zeros_like(gxK)
+    outs = {}
+    for prec, fl in (("fp32c", 0), ("fp32c", nb.FLAG_SYM_ROUNDS), ("fp64", 0)):
+        pos, vel, mass = dev(s.pos), dev(s.vel), dev(s.mass)
+        acc, _ = nb.forces(pos, mass, precision=prec, flags=fl)
+        ckpt, _ = nb.rollout(pos, vel, mass, acc, 1e-3, 1, ckpt_every=1, precision=prec, flags=fl)
+        outs[(prec, fl)] = nb.rollout_backward(mass, ckpt, gxK, gvK, 1e-3, 1, 1, precision=prec, flags=fl)
+        del ckpt
+        torch.cuda.empty_cache()
+    for a, b in zip(outs[("fp32c", 0)], outs[("fp32c", nb.FLAG_SYM_ROUNDS)]):
+        assert torch.equal(a, b)
+    for a, b in zip(outs[("fp32c", 0)], outs[("fp64", 0)]):
+        rel = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        assert rel <= 1e-4, rel
