@@ -233,16 +233,23 @@ int round_streams(hipStream_t (&out)[2]) {
 
 // The rounds 0 .. nbr - 2 of the round schedule after the diagonal tiles (enqueued on st), into K
 // accumulator copies of 4 ns doubles from a64; launch(grid, stream, r0, copies) enqueues the
-// rounds r0 .. r0 + grid.y - 1 into the copies from `copies`. K = 1: one round per launch on st.
-// K >= 2: launch L runs the K/2 rounds from L K/2 on round stream L mod 2, into copies
-// (L mod 2) K/2 .. (L mod 2) K/2 + K/2 - 1; the round streams start after st's work so far and
-// st waits for both at the end, also when a launch failed (the workspace must not be reused
-// under running tiles).
+// rounds r0 .. r0 + grid.y - 1 into the copies from `copies`. K = 1: one round per launch. K >= 2:
+// launch L runs the K/2 rounds from L K/2 into copies (L mod 2) K/2 .. (L mod 2) K/2 + K/2 - 1,
+// on round stream L mod 2; the round streams start after st's work so far and st waits for both
+// at the end, also when a launch failed (the workspace must not be reused under running tiles).
+// Under stream capture the same launches go in order on st (the same sums in the same order, so
+// the same results), with no other stream or event involved.
 template <typename Launch>
 int run_rounds(hipStream_t st, int64_t ns, int64_t nbr, double* a64, int K, const char* what, Launch&& launch) {
-  if (K == 1) {
-    for (int64_t r = 0; r + 1 < nbr; ++r) {
-      launch(dim3((unsigned)(nbr / 2)), st, (int32_t)r, a64);
+  const int64_t KH = K >= 2 ? K / 2 : 1;
+  const int sets = K >= 2 ? 2 : 1;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(st, &cap));
+  if (sets == 1 || cap != hipStreamCaptureStatusNone) {
+    int64_t L = 0;
+    for (int64_t r = 0; r + 1 < nbr; r += KH, ++L) {
+      const unsigned ky = (unsigned)std::min<int64_t>(KH, nbr - 1 - r);
+      launch(dim3((unsigned)(nbr / 2), ky), st, (int32_t)r, a64 + (size_t)(L % sets) * KH * 4 * ns);
       LAUNCH_CHECK(what);
     }
     return NBODY_OK;
@@ -260,7 +267,6 @@ int run_rounds(hipStream_t st, int64_t ns, int64_t nbr, double* a64, int K, cons
   HIP_TRY(hipEventRecord(ev.e[0], st));
   HIP_TRY(hipStreamWaitEvent(rs[0], ev.e[0], 0));
   HIP_TRY(hipStreamWaitEvent(rs[1], ev.e[0], 0));
-  const int64_t KH = K / 2;
   hipError_t err = hipSuccess;
   int64_t L = 0;
   for (int64_t r = 0; r + 1 < nbr && err == hipSuccess; r += KH, ++L) {

@@ -6,7 +6,7 @@ The allocation-free step takes the first of: the tile nbody_step takes, the tile
 the largest systems, the round schedule, whose whole workspace fits the scratch; nbody_step is run
 on that same tile (the tile table set to it) or schedule (NBODY_FLAG_SYM_ROUNDS). Each case checks
 first, from nbody_workspace_size, that the choice it expects is the one the rule makes for its
-size."""
+size. The step is also captured into a HIP graph and replayed against eager steps."""
 import ctypes
 
 import numpy as np
@@ -94,3 +94,36 @@ def test_step_noalloc_matches_step(nb):
         import torch
         for r, o, name in zip(ref, out, ("pos", "vel", "acc", "pot")):
             assert torch.equal(r, o), (n, prec, name)
+
+
+@pytest.mark.parametrize("n,prec", [(3000, "fp32c"), (40000, "fp32a"), (300000, "fp32c")])
+def test_step_noalloc_graph_replays(nb, n, prec):
+    """The step captured into a HIP graph (torch.cuda.graph on a side stream) and replayed: every
+    replay equals the same step run eagerly, bitwise, with eager steps and synchronizations
+    between the replays. Cases: the tuned one-sided tile, the adaptive mode's sort and symmetric
+    tiles, the round schedule (whose launches go in order on the captured stream)."""
+    import torch
+    print("graph capture of step_noalloc n=%d %s" % (n, prec), flush=True)
+    s = inputs.plummer(n, 970 + n)
+    m = dev(s.mass)
+    a0, _ = nb.forces(dev(s.pos), m, precision=prec)
+    st = torch.cuda.Stream()
+    p, v, a = dev(s.pos), dev(s.vel), a0.clone()
+    pot = torch.empty(n, dtype=torch.float64, device="cuda")
+    pe, ve, ae = p.clone(), v.clone(), a.clone()
+    pote = torch.empty_like(pot)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):  # a first call on the device outside the capture
+        nb.step_noalloc(p.clone(), v.clone(), m, a.clone(), 1e-3, precision=prec, out_pot=pot, stream=st)
+    st.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        nb.step_noalloc(p, v, m, a, 1e-3, precision=prec, out_pot=pot, stream=st)
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        nb.step_noalloc(pe, ve, m, ae, 1e-3, precision=prec, out_pot=pote)
+        torch.cuda.synchronize()
+        for x, y, name in ((p, pe, "pos"), (v, ve, "vel"), (a, ae, "acc"), (pot, pote, "pot")):
+            assert torch.equal(x, y), (n, prec, k, name)
