@@ -19,7 +19,9 @@ Also reported (not part of the timed step): the paper's own workload, a Lennard-
 gas of 10 000 particles in a box with reflective walls run for 2500 KDK steps, with and
 without the per-step energy reduction, in FP64 and FP32 (the "lj10k" leg); and the same
 force pass on the round schedule, whose workspace is linear in N, beside the default slot
-schedule (the "round_schedule" leg: time, workspace, max error on every particle).
+schedule (the "round_schedule" leg: time, workspace, max error on every particle); and one
+GPU's share of the paper's ring decomposition at its real shape, 1/8 of the particles against
+all (the "ring_share" leg).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
        python bench.py --lj-only     (only the Lennard-Jones leg, printed as one JSON line)
@@ -232,6 +234,7 @@ def main():
         out["error"] = force_errors(nb, torch, np, pos0, mass, s, eps, prec)
         if prec != "fp64":
             out["round_schedule"] = round_schedule_leg(nb, torch, np, pos0, mass, eps, prec, n)
+        out["ring_share"] = ring_share_leg(nb, torch, np, pos0, mass, eps, n)
         out["cube1k"] = cube1k_leg(nb, torch, np, inputs, dev)
         out["plummer64k"] = plummer64k_leg(nb, torch, np, inputs, dev)
         out["adjoint"] = adjoint_leg(nb, torch, np, inputs, dev)
@@ -336,6 +339,31 @@ def round_schedule_leg(nb, torch, np, pos0, mass, eps, prec, n, warm=1, reps=5):
             "pct_fp32_peak": 100.0 * FLOP_PER_INTERACTION * float(n) * float(n) / (med * 1e-3) / PEAK_FP32,
             "max_e_all_particles": float(e.max()), "workspace_bytes_step": ws(F),
             "workspace_bytes_step_slot_schedule": ws(0)}
+
+
+def ring_share_leg(nb, torch, np, pos0, mass, eps, n, P=8, reps=3):
+    """One GPU's share of the paper's ring decomposition at its real shape: share 0 of P (its
+    n / P particles against all n, the j-range in P blocks) through nbody_forces_shard, timed
+    with HIP events, in the compensated and the double-float mode."""
+    log("ring share: 0 of %d" % P)
+    out = {"P": P, "share": 0}
+    acc = torch.zeros((3, n), dtype=torch.float64, device=pos0.device)
+    for prec in ("fp32c", "fp32ds"):
+        _, _, (i0, i1) = nb.forces_shard(pos0, mass, P, 0, eps=eps, precision=prec, out_acc=acc)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nb.forces_shard(pos0, mass, P, 0, eps=eps, precision=prec, out_acc=acc)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = float(np.median(ms))
+        inter = float(i1 - i0) * float(n)
+        out[prec] = {"rows": [i0, i1], "median_ms": med, "interactions_per_s": inter / (med * 1e-3),
+                     "pct_fp32_peak": 100.0 * FLOP_PER_INTERACTION * inter / (med * 1e-3) / PEAK_FP32}
+    return out
 
 
 def adjoint_1m_leg(nb, torch, np, pos0, mass, s, eps, prec):

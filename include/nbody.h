@@ -165,6 +165,25 @@ int nbody_workspace_size(const nbody_config *cfg, int64_t n, int64_t steps, int6
 int nbody_forces(const nbody_config *cfg, int64_t n, const double *pos, const double *mass,
                  double *acc, double *pot);
 
+/* One GPU's share of the paper's ring decomposition (Sec. V-B, Fig. 1), run on this GPU: with P
+ * GPUs each owning one block of the particles while the j-blocks travel around the ring, GPU g
+ * evaluates its own particles against all n, one j-block per hop. This call computes share g:
+ * the accelerations (and potentials) of block g's particles from all n particles, with the
+ * j-range taken in the same P blocks, one double partial sum per block, added in block order
+ * (what a ring implementation that keeps one partial per arriving block computes, whatever the
+ * order of arrival). Blocks hold s = 256 ceil(t / min(P, t)) particles, t = ceil(n / 256), so
+ * block g is [g s, min(n, (g + 1) s)) (empty when g s >= n). The rows equal, bitwise, those of
+ * nbody_forces on the one-sided tile "bs=256,i=1,tj=256" (tile variant 0) with P j-ranges.
+ * Gravity, single systems; FP32 modes and FP64 (the adaptive mode runs as the double-float
+ * mode).
+ *   P >= 1, 0 <= g < P (else NBODY_ERR_INVALID_ARG); n_systems == 1 (else UNSUPPORTED);
+ *   pos [3][n], mass [n]; acc [3][n], pot [n] (nullable): only block g's rows are written;
+ *   the workspace: nbody_forces_shard_workspace_size bytes (the j-array and, for P > 1,
+ *   P [4][n] double partial planes). */
+int nbody_forces_shard_workspace_size(const nbody_config *cfg, int64_t n, int32_t P, size_t *bytes);
+int nbody_forces_shard(const nbody_config *cfg, int64_t n, int32_t P, int32_t g, const double *pos,
+                       const double *mass, double *acc, double *pot);
+
 /* One kick-drift-kick step of size dt with force reuse (the Verlet
  * half-step update of Sec. II-A):
  *   v += dt/2 a;  x += dt v;  a = a(x);  v += dt/2 a

@@ -36,7 +36,7 @@ EXPORTED = ("nbody_abi_version", "nbody_last_error", "nbody_workspace_size", "nb
             "nbody_rollout", "nbody_energy_momentum", "nbody_rollout_backward", "nbody_set_tile_table",
             "nbody_tile_variants", "nbody_tile_lookup", "nbody_lj_forces", "nbody_lj_rollout",
             "nbody_rollout_backward_reversible", "nbody_diagnostics", "nbody_set_wait_limit",
-            "nbody_step_noalloc")
+            "nbody_step_noalloc", "nbody_forces_shard_workspace_size", "nbody_forces_shard")
 
 
 class NBodyError(RuntimeError):
@@ -104,6 +104,8 @@ def lib():
         "nbody_last_error": ([], ctypes.c_char_p),
         "nbody_workspace_size": ([C, I64, I64, I64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "nbody_forces": ([C, I64, P, P, P, P], ctypes.c_int),
+        "nbody_forces_shard_workspace_size": ([C, I64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "nbody_forces_shard": ([C, I64, ctypes.c_int32, ctypes.c_int32, P, P, P, P], ctypes.c_int),
         "nbody_step": ([C, I64, D, P, P, P, P, P], ctypes.c_int),
         "nbody_step_noalloc": ([C, I64, D, P, P, P, P, P], ctypes.c_int),
         "nbody_rollout": ([C, I64, D, I64, I64, P, P, P, P, P, P], ctypes.c_int),
@@ -237,9 +239,12 @@ class _Cfg:
         self.cfg.workspace = None
         self.cfg.workspace_bytes = 0
 
-    def workspace(self, n, steps=0, ckpt_every=0, device=None):
+    def workspace(self, n, steps=0, ckpt_every=0, device=None, shard_P=0):
         need = ctypes.c_size_t()
-        _check(lib().nbody_workspace_size(ctypes.byref(self.cfg), n, steps, ckpt_every, ctypes.byref(need)))
+        if shard_P:
+            _check(lib().nbody_forces_shard_workspace_size(ctypes.byref(self.cfg), n, shard_P, ctypes.byref(need)))
+        else:
+            _check(lib().nbody_workspace_size(ctypes.byref(self.cfg), n, steps, ckpt_every, ctypes.byref(need)))
         nbytes = int(need.value)
         torch = _torch()
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -294,6 +299,31 @@ def forces(pos, mass, *, G=1.0, eps=1e-2, precision="fp32c", want_pot=False, off
     _check(lib().nbody_forces(ctypes.byref(c.cfg), n, _dptr(pos, "pos", (3, n)), _dptr(mass, "mass"),
                               _dptr(acc, "acc", (3, n)), _dptr(pot, "pot", (n,))))
     return acc, pot
+
+
+def forces_shard(pos, mass, P, g, *, G=1.0, eps=1e-2, precision="fp32c", want_pot=False, out_acc=None,
+                 out_pot=None, stream=None):
+    """Share g of P of the ring decomposition: the rows of block g of (3, n) accelerations (and
+    (n,) potentials) from all n particles; the other rows of out_acc / out_pot are left as they
+    are (zeros when the arrays are allocated here). Returns (acc, pot, (i0, i1))."""
+    torch = _torch()
+    n = _n_of(mass)
+    c = _Cfg(precision, G, eps, None, 0, stream)
+    c.workspace(n, device=mass.device, shard_P=P)
+    acc = out_acc if out_acc is not None else torch.zeros((3, n), dtype=torch.float64, device=mass.device)
+    pot = (out_pot if out_pot is not None else torch.zeros(n, dtype=torch.float64, device=mass.device)) \
+        if want_pot else None
+    _check(lib().nbody_forces_shard(ctypes.byref(c.cfg), n, int(P), int(g), _dptr(pos, "pos", (3, n)),
+                                    _dptr(mass, "mass"), _dptr(acc, "acc", (3, n)), _dptr(pot, "pot", (n,))))
+    return acc, pot, shard_range(n, P, g)
+
+
+def shard_range(n, P, g):
+    """Rows [i0, i1) of share g of P: blocks of s = 256 ceil(t / min(P, t)) particles, t = ceil(n / 256)."""
+    t = max(1, -(-n // 256))
+    s = 256 * -(-t // min(P, t))
+    i0 = min(n, g * s)
+    return i0, min(n, i0 + s)
 
 
 def step(pos, vel, mass, acc, dt, *, G=1.0, eps=1e-2, precision="fp32c", offsets=None, flags=0, out_pot=None,

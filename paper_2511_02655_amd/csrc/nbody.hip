@@ -1011,8 +1011,32 @@ struct Ctx {
 
 // lj: the Lennard-Jones law (nullptr: gravity); law_free: a call that uses no pair law
 // (its G and eps are not checked).
+// One GPU's share of the ring decomposition: the one-sided tile "bs=256,i=1,tj=256" (variant 0)
+// with P j-ranges of s particles each (S of them non-empty); the workspace holds the j-array and,
+// for S > 1, one double partial-sum plane set per j-range.
+int shard_plan(const nbody_config* cfg, int64_t n, int32_t P, Plan& p, Tile& t, int64_t& S, int64_t& s) {
+  if (P < 1) return fail(NBODY_ERR_INVALID_ARG, "P must be >= 1 (got %d)", (int)P);
+  t = Tile{};
+  t.variant = 0;
+  t.sym = -1;
+  variant_shape(NBODY_KERNEL_FORCE, cfg->precision, 0, t.bs, t.i, t.tj);
+  t.j_split = P;
+  split_geometry(t, n, S, s);
+  p = Plan{};
+  size_t off = 0;
+  p.off_jbuf = off;
+  p.sz_jbuf = (size_t)n * jvec_bytes(cfg->precision);
+  off += align_up(p.sz_jbuf);
+  p.off_part = off;
+  p.sz_part = S > 1 ? (size_t)S * 4 * (size_t)n * sizeof(double) : 0;
+  off += align_up(p.sz_part);
+  p.total = off;
+  return NBODY_OK;
+}
+
+// shard_P > 0: the plan of one ring share of P (nbody_forces_shard), single systems only.
 int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsigned need,
-            const nbody_lj_params* lj = nullptr, bool law_free = false) {
+            const nbody_lj_params* lj = nullptr, bool law_free = false, int32_t shard_P = 0) {
   TRY(check_cfg(cfg, n, c.sys, lj == nullptr && !law_free));
   if (lj) {
     TRY(check_lj(cfg, lj));
@@ -1039,8 +1063,14 @@ int prepare(Ctx& c, const nbody_config* cfg, int64_t n, int64_t ckpt_every, unsi
   c.st = (hipStream_t)cfg->stream;
   c.bat = c.sys.S > 1;
   c.loop = c.bat && (cfg->flags & NBODY_FLAG_LOOP_SYSTEMS);
-  TRY(make_plan(cfg, c.sys, n, ckpt_every, need, c.plan, &c.uf, &c.ua, c.law));
-  {
+  if (shard_P > 0) {
+    if (c.sys.S != 1) return fail(NBODY_ERR_UNSUPPORTED, "a ring share is of a single system (n_systems == 1)");
+    Tile t;
+    int64_t S, s;
+    TRY(shard_plan(cfg, n, shard_P, c.plan, t, S, s));
+    c.adapt = false;
+  } else {
+    TRY(make_plan(cfg, c.sys, n, ckpt_every, need, c.plan, &c.uf, &c.ua, c.law));
     const Tile t = single_force_tile(cfg, force_kernel_id(c.law, false), cfg->precision, n);
     c.adapt = c.plan.adapt && (t.sym >= 0 || t.rounds);
   }
@@ -1771,6 +1801,63 @@ __attribute__((visibility("default"))) int nbody_forces(const nbody_config* cfg,
   TRY(upload_meta(c));
   TRY(stage(c, pos, mass));
   return force_pass(c, acc, pot, nullptr, 0.0);
+}
+
+__attribute__((visibility("default"))) int nbody_forces_shard_workspace_size(const nbody_config* cfg, int64_t n,
+                                                                              int32_t P, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(NBODY_ERR_INVALID_ARG, "bytes is NULL");
+  Systems sys;
+  TRY(check_cfg(cfg, n, sys, true));
+  if (sys.S != 1) return fail(NBODY_ERR_UNSUPPORTED, "a ring share is of a single system (n_systems == 1)");
+  Plan p;
+  Tile t;
+  int64_t S, s;
+  TRY(shard_plan(cfg, n, P, p, t, S, s));
+  *bytes = p.total;
+  return NBODY_OK;
+}
+
+__attribute__((visibility("default"))) int nbody_forces_shard(const nbody_config* cfg, int64_t n, int32_t P, int32_t g,
+                                                              const double* pos, const double* mass, double* acc,
+                                                              double* pot) {
+  g_err.clear();
+  if (P < 1 || g < 0 || g >= P) return fail(NBODY_ERR_INVALID_ARG, "need P >= 1 and 0 <= g < P (got P = %d, g = %d)",
+                                           (int)P, (int)g);
+  Ctx c;
+  TRY(prepare(c, cfg, n, 1, NEED_FORCE, nullptr, false, P));
+  if (n == 0) return NBODY_OK;
+  if (!pos || !mass || !acc) return fail(NBODY_ERR_INVALID_ARG, "pos, mass and acc must be non-NULL");
+  Plan p;
+  Tile t;
+  int64_t S, s;
+  TRY(shard_plan(cfg, n, P, p, t, S, s));
+  const int64_t i0 = (int64_t)g * s, i1 = std::min<int64_t>(n, i0 + s);
+  if (i0 >= n) return NBODY_OK;  // a block past the particles (small n): nothing to write
+  TRY(stage(c, pos, mass));
+  const int prec = cfg->precision;
+  const ForceVariant& fv = is_fp64(prec) ? kForce64[0] : kForce32[0];
+  ForceOut o{};
+  o.ls = c.ls;  // direct stores index particles globally (i in [i0, i1))
+  o.n_plane = n;
+  double* part = (double*)(c.ws + c.plan.off_part);
+  if (S == 1) {
+    o.acc = acc;
+    o.pot = pot;
+  } else {
+    TRY(check_part(c, (size_t)S * 4 * n * sizeof(double), "force_kernel (ring share)"));
+    o.part = part;
+  }
+  const dim3 grid((unsigned)cdiv(i1 - i0, (int64_t)t.bs * t.i), (unsigned)S);
+  fv.fn[LAW_GRAV][pot != nullptr][force_mode(prec)](grid, c.st, c.ws + c.plan.off_jbuf, i0, i1, 0, n, s, c.eps2, o);
+  LAUNCH_CHECK("force_kernel (ring share)");
+  if (S > 1) {
+    hipLaunchKernelGGL(reduce_splits, grid1d(i1 - i0), dim3(kReduceBS), 0, c.st, i1 - i0, n, (int32_t)S, part + i0,
+                       c.ls_at(i0), acc + i0, pot ? pot + i0 : nullptr, (double*)nullptr, 0.0, (int64_t)0,
+                       (const int64_t*)nullptr, (const int32_t*)nullptr, NextStep{}, EnergyFuse{});
+    LAUNCH_CHECK("reduce_splits (ring share)");
+  }
+  return NBODY_OK;
 }
 
 __attribute__((visibility("default"))) int nbody_step(const nbody_config* cfg, int64_t n, double dt, double* pos,

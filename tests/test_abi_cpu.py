@@ -348,3 +348,28 @@ def test_round_schedule_flag_workspace(nb):
     rc, w64 = _ws_size(nb, _cfg(nb, precision=0, flags=8), n)  # FP64 has no symmetric tiles
     rc2, w64b = _ws_size(nb, _cfg(nb, precision=0), n)
     assert rc == 0 and rc2 == 0 and w64 == w64b
+
+
+def test_forces_shard_arguments(nb):
+    """nbody_forces_shard (one GPU's share of the ring decomposition): its workspace is the
+    j-array plus one [4][n] double plane set per j-block (none for P = 1); P < 1, g outside
+    [0, P) and batches are rejected before any device work."""
+    L = nb.lib()
+    n = 1 << 20
+    b = ctypes.c_size_t()
+    for prec, jb in ((2, 16), (3, 32), (0, 32)):
+        assert L.nbody_forces_shard_workspace_size(ctypes.byref(_cfg(nb, precision=prec)), n, 8, ctypes.byref(b)) == 0
+        assert jb * n + 8 * 32 * n <= b.value < jb * n + 8 * 32 * n + 1024, (prec, b.value)
+        assert L.nbody_forces_shard_workspace_size(ctypes.byref(_cfg(nb, precision=prec)), n, 1, ctypes.byref(b)) == 0
+        assert jb * n <= b.value < jb * n + 512, (prec, b.value)
+    # 1000 particles are four 256-particle j-tiles: at most four blocks carry partial planes
+    assert L.nbody_forces_shard_workspace_size(ctypes.byref(_cfg(nb)), 1000, 8, ctypes.byref(b)) == 0
+    assert b.value < 16 * 1000 + 4 * 32 * 1000 + 1024
+    assert L.nbody_forces_shard_workspace_size(ctypes.byref(_cfg(nb)), n, 0, ctypes.byref(b)) == 1
+    z = np.zeros(3)
+    zp = z.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for P, g in ((0, 0), (8, 8), (8, -1)):
+        assert L.nbody_forces_shard(ctypes.byref(_cfg(nb)), 10, P, g, zp, zp, zp, None) == 1, (P, g)
+    batched = _cfg(nb, offsets=[0, 5, 10])
+    assert L.nbody_forces_shard_workspace_size(ctypes.byref(batched), 10, 2, ctypes.byref(b)) == 3
+    assert L.nbody_forces_shard(ctypes.byref(batched), 10, 2, 0, zp, zp, zp, None) == 3
