@@ -27,6 +27,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extr
        python bench.py --lj-only     (only the Lennard-Jones leg, printed as one JSON line)
        python bench.py --adjoint-1m-only  (only the adjoint pass at the headline size)
        python bench.py --round-schedule-only  (only the headline pass on the round schedule)
+       python bench.py --merger-only  (only the two-sphere merger forward and backward, no oracle)
 """
 import argparse
 import hashlib
@@ -94,6 +95,7 @@ def main():
     ap.add_argument("--lj-only", action="store_true")
     ap.add_argument("--adjoint-1m-only", action="store_true")
     ap.add_argument("--round-schedule-only", action="store_true")
+    ap.add_argument("--merger-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole system on a single MI355X "
@@ -114,6 +116,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.lj_only:
         print(json.dumps({"lj10k": lj_leg(nb, torch, np, inputs, dev)}), flush=True)
+        return
+    if args.merger_only:
+        print(json.dumps({"adjoint": adjoint_leg(nb, torch, np, inputs, dev, with_oracle=False)}), flush=True)
         return
 
     W = inputs.WORKLOADS["plummer1m"]
@@ -549,7 +554,7 @@ def plummer64k_leg(nb, torch, np, inputs, dev):
     return res
 
 
-def adjoint_leg(nb, torch, np, inputs, dev):
+def adjoint_leg(nb, torch, np, inputs, dev, with_oracle=True):
     """Two-sphere merger N = 2 x 8192, eps = 1e-2, 200 KDK steps dt = 1e-3, checkpoints
     every 20; loss = mean squared distance of the final positions to a Gaussian target
     set; gradient w.r.t. initial positions, velocities and masses (FP32 compensated)."""
@@ -639,22 +644,9 @@ def adjoint_leg(nb, torch, np, inputs, dev):
                     "rel_err_fp64": abs(float((g64[k] * d).sum()) - fdv) / abs(fdv)}
     # the CPU oracle's discrete adjoint at the full configuration (its own FP64 forward
     # trajectory and loss seed): rel-L2 and per particle
-    import oracle
-    log("adjoint leg: oracle gradient (full configuration)")
-    t0 = time.perf_counter()
-    xr, _, _, _ = oracle.kdk(s.pos, s.vel, s.mass, W["dt"], W["steps"], eps=W["eps"])
-    _, gxr = oracle.loss_msd(xr, inputs.gaussian_targets(s.n, W["target_seed"]))
-    ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, W["dt"], W["steps"], gxr, np.zeros_like(gxr), eps=W["eps"])
-    oracle_s = time.perf_counter() - t0
-    vs_oracle = {}
-    for pname, gg in (("fp32c", g32), ("fp64", g64)):
-        vs_oracle[pname] = {k: grad_errors(np, t.cpu().numpy(), r) for k, t, r in zip(("x0", "v0", "m"), gg, ref)}
-    return {
+    out = {
         "workload": "merger2x8k: two Plummer spheres N=2x8192, eps=1e-2, 200 KDK steps dt=1e-3, ckpt every 20, "
                     "MSD loss to Gaussian targets; FP32 compensated",
-        "grad_vs_oracle": vs_oracle,
-        "oracle_seconds": oracle_s,
-        "oracle_threads": oracle.num_threads(),
         "forward_ms": fwd_ms,
         "backward_ms": bwd_ms,
         "adjoint_passes": adj_passes,
@@ -667,6 +659,20 @@ def adjoint_leg(nb, torch, np, inputs, dev):
         "checkpoint_bytes": int(ckpt.numel() * 8),
         "directional_vs_fp64_finite_differences": fd,
     }
+    if not with_oracle:
+        return out
+    import oracle
+    log("adjoint leg: oracle gradient (full configuration)")
+    t0 = time.perf_counter()
+    xr, _, _, _ = oracle.kdk(s.pos, s.vel, s.mass, W["dt"], W["steps"], eps=W["eps"])
+    _, gxr = oracle.loss_msd(xr, inputs.gaussian_targets(s.n, W["target_seed"]))
+    ref = oracle.rollout_adjoint(s.pos, s.vel, s.mass, W["dt"], W["steps"], gxr, np.zeros_like(gxr), eps=W["eps"])
+    out["oracle_seconds"] = time.perf_counter() - t0
+    out["oracle_threads"] = oracle.num_threads()
+    out["grad_vs_oracle"] = {
+        pname: {k: grad_errors(np, t.cpu().numpy(), r) for k, t, r in zip(("x0", "v0", "m"), gg, ref)}
+        for pname, gg in (("fp32c", g32), ("fp64", g64))}
+    return out
 
 
 def grad_errors(np, a, b):
