@@ -1,7 +1,7 @@
 """Worst-case rounding-error bounds of the FP32 pair paths (test infrastructure).
 
 TEST INFRASTRUCTURE ONLY, like the rest of this package: the tests, the smoke check and
-the benchmark's error legs use these bounds to judge a GPU result against the FP64 oracle.
+the benchmark's error legs use these bounds to check a GPU result against the FP64 oracle.
 Nothing here is called by the GPU product path.
 
 Softened gravity, d = x_j - x_i, s = |d|^2 + eps^2, pair term m_j d s^{-3/2}:
