@@ -282,3 +282,45 @@ def test_adjoint_rounds_beyond_the_slot_cap(nb):
     for a, b in zip(outs[("fp32c", 0)], outs[("fp64", 0)]):
         rel = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
         assert rel <= 1e-4, rel
+
+
+def test_rounds_per_system_loop(nb, oracle):
+    """Batches whose systems are looped one by one (NBODY_FLAG_LOOP_SYSTEMS) run each system on
+    the round schedule with the flag: forces of every system against the oracle within its
+    bound, and a 3-step rollout plus its backward equal, system by system, the same calls on the
+    systems alone, bitwise. Without the loop flag the batched kernels ignore it (bitwise equal)."""
+    import torch
+    b = inputs.batched_mix(4, 1214, nmin=300, nmax=3000)
+    off = b.offsets
+    F = nb.FLAG_SYM_ROUNDS
+    L = nb.FLAG_LOOP_SYSTEMS
+    x, v, m = dev(b.pos), dev(b.vel), dev(b.mass)
+    a, _ = nb.forces(x, m, precision="fp32c", offsets=off, flags=F | L)
+    a_b, _ = nb.forces(x, m, precision="fp32c", offsets=off, flags=F)
+    a_n, _ = nb.forces(x, m, precision="fp32c", offsets=off)
+    assert torch.equal(a_b, a_n)
+    g = np.random.Generator(np.random.PCG64(1215))
+    gxK = g.normal(size=b.pos.shape)
+    for k in range(len(off) - 1):
+        lo, hi = int(off[k]), int(off[k + 1])
+        a_r, _ = oracle.forces(b.pos[:, lo:hi], b.mass[lo:hi], eps=1e-2)
+        B = _bound(b.pos[:, lo:hi], b.mass[lo:hi], 1e-2, "fp32c")
+        d = np.sqrt(np.sum((host(a)[:, lo:hi] - a_r) ** 2, axis=0))
+        assert np.max(d / B) <= 1.0, (k, float(np.max(d / B)))
+    p, vv = x.clone(), v.clone()
+    ckpt, _ = nb.rollout(p, vv, m, a.clone(), 1e-3, 3, ckpt_every=1, precision="fp32c", offsets=off, flags=F | L)
+    grads = nb.rollout_backward(m, ckpt, dev(gxK), torch.zeros_like(x), 1e-3, 3, 1, precision="fp32c", offsets=off,
+                                flags=F | L)
+    for k in range(len(off) - 1):
+        lo, hi = int(off[k]), int(off[k + 1])
+        xs, vs, ms = x[:, lo:hi].contiguous(), v[:, lo:hi].contiguous(), m[lo:hi].contiguous()
+        a1, _ = nb.forces(xs, ms, precision="fp32c", flags=F)
+        assert torch.equal(a1, a[:, lo:hi].contiguous()), k
+        ps, vs2 = xs.clone(), vs.clone()
+        ck1, _ = nb.rollout(ps, vs2, ms, a1.clone(), 1e-3, 3, ckpt_every=1, precision="fp32c", flags=F)
+        assert torch.equal(ps, p[:, lo:hi].contiguous()) and torch.equal(vs2, vv[:, lo:hi].contiguous()), k
+        g1 = nb.rollout_backward(ms, ck1, dev(gxK[:, lo:hi]), torch.zeros_like(xs), 1e-3, 3, 1, precision="fp32c",
+                                 flags=F)
+        for u, w in zip(g1, grads):
+            ww = w[..., lo:hi].contiguous()
+            assert torch.equal(u, ww), k
