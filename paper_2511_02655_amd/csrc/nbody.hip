@@ -932,11 +932,11 @@ int make_plan(const nbody_config* cfg, const Systems& sys, int64_t n, int64_t ck
     p.off_bbpart = take((size_t)p.adapt_bblocks * 6 * sizeof(double));
     p.off_bbox = take(8 * sizeof(double));
   }
-  // energy partials: chunks of 256 threads per system, about one particle per thread (the
-  // energy can ride on a per-particle reduction, which needs that parallelism), with at most
-  // max(16 S, 32768) chunks in all
+  // energy partials: chunks of kEnergyBS threads per system, about one particle per thread
+  // (the energy can ride on a per-particle reduction, which needs that parallelism), with at
+  // most max(16 S, 32768) chunks in all
   const int64_t chunk_cap = std::max<int64_t>(16, 32768 / std::max<int64_t>(1, sys.S));
-  int64_t chunks = std::min<int64_t>(std::max<int64_t>(1, cdiv(sys.max_n, 256)), chunk_cap);
+  int64_t chunks = std::min<int64_t>(std::max<int64_t>(1, cdiv(sys.max_n, kEnergyBS)), chunk_cap);
   p.e_chunks = (int32_t)chunks;
   // a rollout with an energy trace keeps the partials of up to kEnergySteps steps (at most
   // kEnergyBytes) and sums them in one launch
@@ -1444,6 +1444,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
   }
   // the reduction's launch geometry: one thread per particle, or the energy chunk grid
   auto rgrid = [&](int64_t count) { return ef.part ? dim3((unsigned)ef.chunks, (unsigned)c.sys.S) : grid1d(count); };
+  const dim3 rblock(ef.part ? kEnergyBS : kReduceBS);
   // after a reduction that carried the fused work, finish the energy sum
   auto fused_tail = [&]() -> int {
     if (!fz) return NBODY_OK;
@@ -1473,7 +1474,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
       // round schedule, then the per-particle end (copies added, scale, kick, next step, energy)
       int K = 1;
       TRY(round_tiles(c, ns, (const float4*)jarr + (is_ds(prec) ? 2 : 1) * b, law, pot_on, mode, AdaptIn{}, K));
-      hipLaunchKernelGGL(reduce_rounds, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n,
+      hipLaunchKernelGGL(reduce_rounds, rgrid(ns), rblock, 0, c.st, ns, n,
                          (const double*)(c.ws + c.plan.off_part), (int32_t)K, c.ls_at(b), acc + b,
                          pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, next_step_at(c, nx, b), ef,
                          (const uint32_t*)nullptr);
@@ -1491,7 +1492,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
                                (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("force_sym_kernel");
       // reduce_sym: the energy's chunk grid, else blocks of four waves for 64 particles
-      hipLaunchKernelGGL(reduce_sym, ef.part ? rgrid(ns) : grid1d(ns, 64), dim3(kReduceBS), 0, c.st, ns,
+      hipLaunchKernelGGL(reduce_sym, ef.part ? rgrid(ns) : grid1d(ns, 64), rblock, 0, c.st, ns,
                          n, (int32_t)nb, (const float*)pf,
                          c.ls_at(b), acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh,
                          next_step_at(c, nx, b), ef, (const uint32_t*)nullptr);
@@ -1515,7 +1516,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
     LAUNCH_CHECK("force_kernel");
     if (S > 1) {
       // reduce only this system's particle range: offset pointers into the planes
-      hipLaunchKernelGGL(reduce_splits, rgrid(ns), dim3(kReduceBS), 0, c.st, ns, n, (int32_t)S, part + b,
+      hipLaunchKernelGGL(reduce_splits, rgrid(ns), rblock, 0, c.st, ns, n, (int32_t)S, part + b,
                          c.ls_at(b), acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh, (int64_t)0,
                          (const int64_t*)nullptr, (const int32_t*)nullptr, next_step_at(c, nx, b), ef);
       LAUNCH_CHECK("reduce_splits");
@@ -1541,7 +1542,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
     sv.bfn[law][pot_on][mode](ugrid, c.st, (const float4*)jarr, (const SymUnit*)(c.ws + c.plan.off_units),
                               (int32_t)c.plan.n_units_force, (float)eps2, pf);
     LAUNCH_CHECK("force_sym_batched_kernel");
-    hipLaunchKernelGGL(reduce_sym_batched, rgrid(n), dim3(kReduceBS), 0, c.st, n, c.sys.S,
+    hipLaunchKernelGGL(reduce_sym_batched, rgrid(n), rblock, 0, c.st, n, c.sys.S,
                        (const int64_t*)(c.ws + c.plan.off_sysoff), (const int32_t*)(c.ws + c.plan.off_nsplit),
                        (const int64_t*)(c.ws + c.plan.off_partoff), (const float*)pf, c.ls, acc, pot, vel, hh,
                        next_step_at(c, nx, 0), ef);
@@ -1558,7 +1559,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
   fv.bfn[law][pot_on][mode](ugrid, c.st, jarr, (const WorkUnit*)(c.ws + c.plan.off_units),
                             (int32_t)c.plan.n_units_force, eps2, o);
   LAUNCH_CHECK("force_batched_kernel");
-  hipLaunchKernelGGL(reduce_splits, rgrid(n), dim3(kReduceBS), 0, c.st, n, n, (int32_t)0, part, c.ls, acc, pot, vel,
+  hipLaunchKernelGGL(reduce_splits, rgrid(n), rblock, 0, c.st, n, n, (int32_t)0, part, c.ls, acc, pot, vel,
                      hh, c.sys.S, (const int64_t*)(c.ws + c.plan.off_sysoff),
                      (const int32_t*)(c.ws + c.plan.off_nsplit), next_step_at(c, nx, 0), ef);
   LAUNCH_CHECK("reduce_splits");
@@ -1574,12 +1575,14 @@ int energy_pass(Ctx& c, const double* vel, const double* mass, const double* pot
     for (int64_t s = 0; s < c.sys.S; ++s) {
       const int64_t b = c.sys.off[s], ns = c.sys.off[s + 1] - b;
       // offset pointers; vel planes keep stride n, so pass a shifted view per plane
-      hipLaunchKernelGGL(energy_partial<256>, dim3(chunks, 1), dim3(256), 0, c.st, c.n, vel + b, mass + b, pot + b,
+      hipLaunchKernelGGL(energy_partial<kEnergyBS>, dim3(chunks, 1), dim3(kEnergyBS), 0, c.st, c.n, vel + b, mass + b,
+                         pot + b,
                          (const int64_t*)nullptr, ns, chunks, ep + s * chunks * 5);
       LAUNCH_CHECK("energy_partial");
     }
   } else {
-    hipLaunchKernelGGL(energy_partial<256>, dim3(chunks, (unsigned)c.sys.S), dim3(256), 0, c.st, c.n, vel, mass, pot,
+    hipLaunchKernelGGL(energy_partial<kEnergyBS>, dim3(chunks, (unsigned)c.sys.S), dim3(kEnergyBS), 0, c.st, c.n, vel,
+                       mass, pot,
                        dev_off, c.n, chunks, ep);
     LAUNCH_CHECK("energy_partial");
   }

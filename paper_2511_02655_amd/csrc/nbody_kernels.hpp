@@ -341,11 +341,14 @@ __device__ __forceinline__ void energy_terms(double m, double vx, double vy, dou
 }
 
 // Energy of the state a per-particle reduction has just finished, fused into it: the
-// reduction then runs on the (chunk, system) grid of energy_partial, each thread taking
-// the same particles in the same order, and block (chunk, s) writes part[s][chunk][5]
-// exactly as energy_partial would (energy_final completes the sum). part == nullptr:
-// nothing fused, one thread per particle.
-constexpr int kReduceBS = 256;  // block size of every per-particle reduction
+// reduction then runs on the (chunk, system) grid of energy_partial, blocks of kEnergyBS
+// threads, each thread taking the same particles in the same order, and block (chunk, s)
+// writes part[s][chunk][5] exactly as energy_partial would (energy_final completes the sum).
+// part == nullptr: nothing fused, one thread per particle.
+constexpr int kReduceBS = 256;  // block size of the per-particle reductions without the energy
+// Threads of an energy chunk: one wave, so that a system of n particles spreads its fused
+// reduction over n / 64 workgroups (at n = 10^4, 157 rather than 40 CUs).
+constexpr int kEnergyBS = 64;
 
 struct EnergyFuse {
   double* part;
@@ -358,11 +361,11 @@ struct EnergyFuse {
 // adding particle i's energy terms to en, then the chunk's block sum.
 template <typename F>
 __device__ __forceinline__ void energy_chunk(int64_t b, int64_t e, int64_t s, const EnergyFuse& ef, F&& body) {
-  __shared__ double sh[5 * (kReduceBS / 64)];
+  __shared__ double sh[5 * (kEnergyBS / 64)];
   double en[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = b + (int64_t)blockIdx.x * kReduceBS + threadIdx.x; i < e; i += (int64_t)ef.chunks * kReduceBS)
+  for (int64_t i = b + (int64_t)blockIdx.x * kEnergyBS + threadIdx.x; i < e; i += (int64_t)ef.chunks * kEnergyBS)
     body(i, en);
-  block_sum<kReduceBS, 5>(en, sh);
+  block_sum<kEnergyBS, 5>(en, sh);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int c = 0; c < 5; ++c) ef.part[(s * ef.chunks + blockIdx.x) * 5 + c] = en[c];
