@@ -1492,7 +1492,7 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
                                (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("force_sym_kernel");
       // reduce_sym: the energy's chunk grid, else blocks of four waves for 64 particles
-      hipLaunchKernelGGL(reduce_sym, ef.part ? rgrid(ns) : grid1d(ns, 64), rblock, 0, c.st, ns,
+      hipLaunchKernelGGL(reduce_sym, ef.part ? rgrid(ns) : grid1d(ns, 64), dim3(kReduceBS), 0, c.st, ns,
                          n, (int32_t)nb, (const float*)pf,
                          c.ls_at(b), acc + b, pot ? pot + b : nullptr, vel ? vel + b : nullptr, hh,
                          next_step_at(c, nx, b), ef, (const uint32_t*)nullptr);

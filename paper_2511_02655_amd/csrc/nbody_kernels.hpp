@@ -1342,60 +1342,60 @@ __device__ __forceinline__ void sum_slot_group(const float* __restrict__ part, i
   }
 }
 
-// All four groups in one thread: the slots in order, K at a time (K a multiple of 4), slot s
-// added to group s mod 4 - the same four sums as sum_slot_group, with the loads of K slots in
-// flight together.
-template <int NC, int K = 32>
-__device__ __forceinline__ void sum_slot_groups(const float* __restrict__ part, int64_t n, int64_t i, int32_t nb,
-                                                double p[4][4]) {
-  static_assert(K % 4 == 0, "whole groups per round");
-  for (int32_t s0 = 0; s0 < nb; s0 += K) {
-    float v[K][NC];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int32_t s = s0 + k;
-        const float x = part[((int64_t)(s < nb ? s : s0) * 4 + c) * n + i];
-        v[k][c] = s < nb ? x : 0.f;
-      }
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int c = 0; c < NC; ++c) p[k & 3][c] += (double)v[k][c];
-  }
-}
-
 // perm (nullable): the slot planes are in sorted order (the adaptive mode) and position p
 // holds particle perm[p], whose outputs are written at its own index.
 // Without the energy: blocks of four waves for 64 positions, wave g summing slot group g; wave 0
 // adds the four groups and finishes the particle (a grid of ceil(n / 64) blocks: four times the
 // waves of one thread per particle, a quarter of the dependent loads each, which at small n,
 // where the sum is bound by memory round trips, takes most of its time away).
-// With the energy fused: one thread per particle sums the four groups together, the same sums
-// in the same order (so trajectories do not depend on whether the energy is traced).
+// With the energy fused: the same four waves over each turn of an energy chunk (grid: the
+// chunks), wave 0 also adding the particle's energy terms with the thread map and block sum of
+// energy_partial; the same sums in the same order (so trajectories do not depend on whether the
+// energy is traced, and the energy is bitwise the separate pass's).
 __global__ __launch_bounds__(kReduceBS) void reduce_sym(int64_t n, int64_t stride, int32_t nb,
                                                        const float* __restrict__ part, LawScale ls,
                                                        double* __restrict__ acc, double* __restrict__ pot,
                                                        double* __restrict__ vel, double hh, NextStep nx,
                                                        EnergyFuse ef, const uint32_t* __restrict__ perm) {
   static_assert(kReduceBS == 256, "four waves of 64 positions");
-  if (ef.part) {  // grid (chunks, 1)
-    energy_chunk(0, n, 0, ef, [&](int64_t p, double* en) {
-      const int64_t i = perm ? (int64_t)perm[p] : p;
-      const PState ps = load_state(i, stride, ls, vel, nx, ef.mass, en != nullptr);
-      double q[4][4] = {};
-      if (pot) sum_slot_groups<4>(part, n, p, nb, q);
-      else sum_slot_groups<3>(part, n, p, nb, q);
-      double a[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a[c] = (q[0][c] + q[1][c]) + (q[2][c] + q[3][c]);
-      finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, en, ps);
-    });
-    return;
-  }
+  static_assert(kEnergyBS == 64, "one wave of positions per energy chunk");
   __shared__ double sh[3][4][64];
   const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (ef.part) {  // grid (chunks, 1): each turn the chunk's 64 positions, in four slot groups
+    double en[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t base = (int64_t)blockIdx.x * kEnergyBS; base < n; base += (int64_t)ef.chunks * kEnergyBS) {
+      const int64_t p = base + lane;  // the particle energy_partial's thread `lane` takes in this turn
+      const bool live = p < n;
+      double q[4] = {0.0, 0.0, 0.0, 0.0};
+      if (live) {
+        if (pot) sum_slot_group<4>(part, n, p, nb, g, q);
+        else sum_slot_group<3>(part, n, p, nb, g, q);
+      }
+      if (g > 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[g - 1][c][lane] = q[c];
+      __syncthreads();
+      if (g == 0 && live) {
+        const int64_t i = perm ? (int64_t)perm[p] : p;
+        const PState ps = load_state(i, stride, ls, vel, nx, ef.mass, true);
+        double a[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[c] = (q[c] + sh[0][c][lane]) + (sh[1][c][lane] + sh[2][c][lane]);
+        finish_particle(i, stride, a, ls, acc, pot, vel, hh, nx, en, ps);
+      }
+      __syncthreads();  // sh is rewritten by the next turn
+    }
+    if (g == 0) {  // the chunk's sum as block_sum<kEnergyBS, 5>: the wave by shuffles, then 0 + it
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        double x = en[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) ef.part[(int64_t)blockIdx.x * 5 + c] = 0.0 + x;
+      }
+    }
+    return;
+  }
   const int64_t p = (int64_t)blockIdx.x * 64 + lane;
   const bool live = p < n;
   int64_t i = 0;
