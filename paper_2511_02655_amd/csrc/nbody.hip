@@ -1442,9 +1442,13 @@ int force_pass(Ctx& c, double* acc, double* pot, double* vel, double hh, Fuse* f
       ef.chunks = c.plan.e_chunks;
     }
   }
-  // the reduction's launch geometry: one thread per particle, or the energy chunk grid
-  auto rgrid = [&](int64_t count) { return ef.part ? dim3((unsigned)ef.chunks, (unsigned)c.sys.S) : grid1d(count); };
-  const dim3 rblock(ef.part ? kEnergyBS : kReduceBS);
+  // the reduction's launch geometry: one thread per particle in one-wave workgroups (a small
+  // system's reduction then spreads over n / 64 CUs; each thread's sum is a chain of dependent
+  // loads, so the latency, not the bandwidth, sets its time), or the energy chunk grid
+  auto rgrid = [&](int64_t count) {
+    return ef.part ? dim3((unsigned)ef.chunks, (unsigned)c.sys.S) : grid1d(count, kEnergyBS);
+  };
+  const dim3 rblock(kEnergyBS);
   // after a reduction that carried the fused work, finish the energy sum
   auto fused_tail = [&]() -> int {
     if (!fz) return NBODY_OK;
