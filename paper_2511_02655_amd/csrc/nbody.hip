@@ -1296,6 +1296,7 @@ NextStep next_step_at(const Ctx& c, const NextStep* nx, int64_t b) {
   r = *nx;
   r.pos += b;
   r.mass += b;
+  if (r.pos_copy) r.pos_copy += b;
   r.jarr = (char*)r.jarr + (size_t)b * jvec_bytes(c.cfg->precision);
   return r;
 }
@@ -2193,10 +2194,21 @@ __attribute__((visibility("default"))) int nbody_rollout_backward(const nbody_co
     if (t_end > t0) {
       TRY(stage(c, xw, mass));
       TRY(force_pass(c, aw, nullptr, nullptr, 0.0));
-      for (int64_t t = t0; t < t_end; ++t) {
-        TRY(kick_drift(c, h, xw, vw, aw, mass));
-        TRY(copy_d2d(c, seg + (size_t)(t + 1 - t0) * 3 * n, xw, plane3));
-        if (t + 1 < t_end) TRY(force_pass(c, aw, nullptr, vw, 0.5 * h));
+      TRY(kick_drift(c, h, xw, vw, aw, mass));
+      TRY(copy_d2d(c, seg + (size_t)3 * n, xw, plane3));
+      NextStep nx = next_step(c, h, xw, mass);
+      for (int64_t t = t0 + 1; t < t_end; ++t) {
+        // the pass at x_t closes step t - 1; its reduction also runs the first half of step t,
+        // writing x_{t+1} to xw and to the segment (as a rollout's fused steps do)
+        double* dst = seg + (size_t)(t + 1 - t0) * 3 * n;
+        nx.pos_copy = dst;
+        Fuse fz;
+        fz.nx = &nx;
+        TRY(force_pass(c, aw, nullptr, vw, 0.5 * h, &fz));
+        if (!fz.done) {  // a pass without such a reduction: the first half and the copy here
+          TRY(kick_drift(c, h, xw, vw, aw, mass));
+          TRY(copy_d2d(c, dst, xw, plane3));
+        }
       }
     }
     // reverse sweep over this segment

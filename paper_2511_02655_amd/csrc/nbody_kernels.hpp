@@ -247,6 +247,7 @@ struct NextStep {
   double hh, h, xs;
   Walls wl;
   void* jarr;
+  double* pos_copy;  // nullable: the drifted positions are also written here ([3][n] like pos)
 };
 
 // The state a per-particle reduction needs besides the particle's sums, loaded before the sums'
@@ -296,6 +297,7 @@ __device__ __forceinline__ void next_step_tail(const NextStep& ns, int64_t i, in
     }
     vel[c * n + i] = v;
     ns.pos[c * n + i] = xc;
+    if (ns.pos_copy) ns.pos_copy[c * n + i] = xc;
     x[c] = xc;
   }
   if (ns.kind == 1) put_j<float, false>((float4*)ns.jarr, i, x, m, ns.xs);
