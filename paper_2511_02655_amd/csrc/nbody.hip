@@ -1621,8 +1621,19 @@ int diag_pass(Ctx& c, const double* pos, const double* vel, const double* mass, 
 
 // Adjoint pass at positions pos with l = w * gvel (after gvel += h_drift * gpos):
 // gpos += G(...), gmass += -G M.
+// The next adjoint pass's staging arguments, for a pass that can fuse them into its reduction.
+struct AdjNextArgs {
+  const double* pos;
+  double h_drift, w;
+};
+
+// One adjoint pass at positions pos. staged: the j-array already holds this pass's staging (a
+// previous pass fused it). next (nullable): the next pass's staging to fuse into this pass's
+// reduction where it has one (a single system on symmetric tiles); *fused (nullable) says
+// whether it did.
 int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, const double* gpos_in,
-                 double h_drift, double w, double* gpos, double* gmass) {
+                 double h_drift, double w, double* gpos, double* gmass, const AdjNextArgs* next = nullptr,
+                 bool staged = false, bool* fused = nullptr) {
   const int prec = c.cfg->precision;
   const int comp = adj_comp(prec);  // the double-float mode's adjoint runs compensated
   const double eps2 = c.cfg->eps * c.cfg->eps;
@@ -1630,13 +1641,16 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
   void* jadj = c.ws + c.plan.off_jbuf;
   double* part = (double*)(c.ws + c.plan.off_part);
   const int64_t n = c.n;
-  if (is_fp64(prec))
-    hipLaunchKernelGGL(adjoint_stage<double>, grid1d(n), dim3(256), 0, c.st, n, pos, mass, gvel, gpos_in, h_drift, w,
-                       (D4*)jadj);
-  else
-    hipLaunchKernelGGL(adjoint_stage<float>, grid1d(n), dim3(256), 0, c.st, n, pos, mass, gvel, gpos_in, h_drift, w,
-                       (float4*)jadj);
-  LAUNCH_CHECK("adjoint_stage");
+  if (fused) *fused = false;
+  if (!staged) {
+    if (is_fp64(prec))
+      hipLaunchKernelGGL(adjoint_stage<double>, grid1d(n), dim3(256), 0, c.st, n, pos, mass, gvel, gpos_in, h_drift,
+                         w, (D4*)jadj);
+    else
+      hipLaunchKernelGGL(adjoint_stage<float>, grid1d(n), dim3(256), 0, c.st, n, pos, mass, gvel, gpos_in, h_drift,
+                         w, (float4*)jadj);
+    LAUNCH_CHECK("adjoint_stage");
+  }
 
   auto single = [&](int64_t b, int64_t e) -> int {
     const int64_t ns = e - b;
@@ -1676,8 +1690,19 @@ int adjoint_pass(Ctx& c, const double* pos, const double* mass, double* gvel, co
       const float4* ja = (const float4*)jadj + 2 * b;
       sv.fn[comp](dim3((unsigned)tiles), c.st, ja, ns, (int32_t)nb, (float)eps2, pf);
       LAUNCH_CHECK("adjoint_sym_kernel");
+      AdjNext an{};
+      if (next && !c.bat && b == 0 && !is_fp64(prec)) {  // one system: its staging covers every particle
+        an.kind = 1;
+        an.pos = next->pos;
+        an.mass = mass;
+        an.gvel = gvel;
+        an.h_drift = next->h_drift;
+        an.w = next->w;
+        an.jadj = (float4*)jadj;
+        if (fused) *fused = true;
+      }
       hipLaunchKernelGGL(adjoint_reduce_sym_groups, grid1d(ns, 64), dim3(256), 0, c.st, ns, n, (int32_t)nb,
-                         (const float*)pf, c.cfg->G, gpos + b, gmass + b);
+                         (const float*)pf, c.cfg->G, gpos + b, gmass + b, an);
       LAUNCH_CHECK("adjoint_reduce_sym_groups");
       return NBODY_OK;
     }
@@ -2211,15 +2236,28 @@ __attribute__((visibility("default"))) int nbody_rollout_backward(const nbody_co
         }
       }
     }
-    // reverse sweep over this segment
+    // reverse sweep over this segment; a pass whose reduction can stage the next pass of the
+    // segment does so (the next segment's recomputation reuses the j-array first)
+    auto next_of = [&](int64_t t) {  // the staging of the pass at x_t
+      return AdjNextArgs{seg + (size_t)(t - t0) * 3 * n, h, t > 0 ? h : 0.5 * h};
+    };
+    bool staged = false;
     if (last) {
       const double* xK = seg + (size_t)(steps - t0) * 3 * n;
-      TRY(adjoint_pass(c, xK, mass, gvel0, gpos0, 0.0, 0.5 * h, gpos0, gmass));
+      const AdjNextArgs nxt = next_of(t1 - 1);
+      TRY(adjoint_pass(c, xK, mass, gvel0, gpos0, 0.0, 0.5 * h, gpos0, gmass, &nxt, false, &staged));
     }
     for (int64_t t = t1 - 1; t >= t0; --t) {
       const double* xt = seg + (size_t)(t - t0) * 3 * n;
       const double w = t > 0 ? h : 0.5 * h;
-      TRY(adjoint_pass(c, xt, mass, gvel0, gpos0, h, w, gpos0, gmass));
+      bool fused = false;
+      if (t > t0) {
+        const AdjNextArgs nxt = next_of(t - 1);
+        TRY(adjoint_pass(c, xt, mass, gvel0, gpos0, h, w, gpos0, gmass, &nxt, staged, &fused));
+      } else {
+        TRY(adjoint_pass(c, xt, mass, gvel0, gpos0, h, w, gpos0, gmass, nullptr, staged, &fused));
+      }
+      staged = fused;
     }
   }
   return NBODY_OK;

@@ -2311,12 +2311,25 @@ __global__ __launch_bounds__(256) void adjoint_reduce_rounds(int64_t n, int64_t 
   gmass[i] = g0[3] + -G * r[3];
 }
 
+// The next adjoint pass's staging (adjoint_stage<float>), fused into a reduction that has just
+// updated the particle's position gradient: kind 0 nothing, 1 the FP32 adjoint j-array.
+struct AdjNext {
+  int32_t kind;
+  int32_t pad;
+  const double* pos;   // the next pass's positions [3][stride]
+  const double* mass;
+  double* gvel;
+  double h_drift, w;
+  float4* jadj;
+};
+
 // The single-system form: four waves per 64 particles, wave g summing slot group g (as in
-// reduce_sym); wave 0 adds the groups, (p0 + p1) + (p2 + p3), and updates the gradients.
+// reduce_sym); wave 0 adds the groups, (p0 + p1) + (p2 + p3), updates the gradients and, with
+// an.kind, stages the particle for the next pass with adjoint_stage's arithmetic.
 __global__ __launch_bounds__(256) void adjoint_reduce_sym_groups(int64_t n, int64_t stride, int32_t nb,
                                                                 const float* __restrict__ part, double G,
                                                                 double* __restrict__ gpos,
-                                                                double* __restrict__ gmass) {
+                                                                double* __restrict__ gmass, AdjNext an) {
   __shared__ double sh[3][4][64];
   const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
@@ -2337,9 +2350,36 @@ __global__ __launch_bounds__(256) void adjoint_reduce_sym_groups(int64_t n, int6
     double r[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) r[c] = (q[c] + sh[0][c][lane]) + (sh[1][c][lane] + sh[2][c][lane]);
+    double gp[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gpos[c * stride + i] = g0[c] + G * r[c];
+    for (int c = 0; c < 3; ++c) {
+      gp[c] = g0[c] + G * r[c];
+      gpos[c * stride + i] = gp[c];
+    }
     gmass[i] = g0[3] + -G * r[3];
+    if (an.kind) {
+      float l[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double gv = an.gvel[c * stride + i];
+        if (an.h_drift != 0.0) {
+          gv += an.h_drift * gp[c];
+          an.gvel[c * stride + i] = gv;
+        }
+        l[c] = (float)(an.w * gv);
+      }
+      float4 a, b;
+      a.x = (float)an.pos[i];
+      a.y = (float)an.pos[stride + i];
+      a.z = (float)an.pos[2 * stride + i];
+      a.w = (float)an.mass[i];
+      b.x = l[0];
+      b.y = l[1];
+      b.z = l[2];
+      b.w = 0.f;
+      an.jadj[2 * i] = a;
+      an.jadj[2 * i + 1] = b;
+    }
   }
 }
 
