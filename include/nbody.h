@@ -213,9 +213,9 @@ int nbody_step(const nbody_config *cfg, int64_t n, double dt, double *pos, doubl
  *   1.2-1.6 million, by mode) returns NBODY_ERR_WORKSPACE before any device work.
  * Every call on one GPU shares that GPU's array (nothing in it needs to start at zero): calls
  * that overlap on one GPU (other host threads, other streams without ordering) race.
- * Under stream capture the step records only kernel launches on the caller's stream (the round
- * schedule's launches, which otherwise alternate between two library streams, go in order on
- * it, with the same results). */
+ * The step creates no stream or event and records only kernel launches on the caller's stream
+ * (the round schedule's launches, which nbody_step alternates between two library streams, go in
+ * order on it, with the same results), also under stream capture. */
 #define NBODY_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 int nbody_step_noalloc(const nbody_config *cfg, int64_t n, double dt, double *pos, double *vel,
                        const double *mass, double *acc, double *pot);

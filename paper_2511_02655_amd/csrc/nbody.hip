@@ -237,15 +237,18 @@ int round_streams(hipStream_t (&out)[2]) {
 // launch L runs the K/2 rounds from L K/2 into copies (L mod 2) K/2 .. (L mod 2) K/2 + K/2 - 1,
 // on round stream L mod 2; the round streams start after st's work so far and st waits for both
 // at the end, also when a launch failed (the workspace must not be reused under running tiles).
-// Under stream capture the same launches go in order on st (the same sums in the same order, so
-// the same results), with no other stream or event involved.
+// Under stream capture, and in the allocation-free step (g_rounds_one_stream: no stream or event
+// is created), the same launches go in order on st (the same sums in the same order, so the same
+// results).
+thread_local bool g_rounds_one_stream = false;
+
 template <typename Launch>
 int run_rounds(hipStream_t st, int64_t ns, int64_t nbr, double* a64, int K, const char* what, Launch&& launch) {
   const int64_t KH = K >= 2 ? K / 2 : 1;
   const int sets = K >= 2 ? 2 : 1;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(st, &cap));
-  if (sets == 1 || cap != hipStreamCaptureStatusNone) {
+  if (sets == 1 || cap != hipStreamCaptureStatusNone || g_rounds_one_stream) {
     int64_t L = 0;
     for (int64_t r = 0; r + 1 < nbr; r += KH, ++L) {
       const unsigned ky = (unsigned)std::min<int64_t>(KH, nbr - 1 - r);
@@ -1958,11 +1961,14 @@ __attribute__((visibility("default"))) int nbody_step_noalloc(const nbody_config
   struct CapGuard {
     double cap = g_sym_cap;
     int level = g_sym_level;
+    bool one_stream = g_rounds_one_stream;
     ~CapGuard() {
       g_sym_cap = cap;
       g_sym_level = level;
+      g_rounds_one_stream = one_stream;
     }
   } cap_guard;
+  g_rounds_one_stream = true;  // the round schedule's launches on the caller's stream only
   const double total = (double)NBODY_NOALLOC_SCRATCH_BYTES;
   size_t need = 0;
   for (int level = 0; level < 4; ++level) {
