@@ -24,10 +24,13 @@
  *     SoA planes of doubles, [3][n] (all x, then all y, then all z).
  *   - The library allocates no device memory. Scratch space comes from the
  *     caller's workspace (nbody_config.workspace), whose size
- *     nbody_workspace_size() returns.
+ *     nbody_workspace_size() returns (nbody_step_noalloc: a static device array
+ *     of the library instead).
  *   - Calls are asynchronous on nbody_config.stream (a hipStream_t; NULL = the
- *     null stream). Host arguments (offsets, the config itself) may be reused
- *     as soon as the call returns.
+ *     null stream). The round schedule (NBODY_FLAG_SYM_ROUNDS) also runs work
+ *     on two streams of the library, ordered before and after the call's other
+ *     work on nbody_config.stream by events. Host arguments (offsets, the
+ *     config itself) may be reused as soon as the call returns.
  *   - Every call returns an nbody_status. Argument errors are detected on the
  *     host before any HIP call and leave device memory untouched; a failed
  *     launch returns NBODY_ERR_DEVICE. nbody_last_error() describes the last
@@ -35,8 +38,9 @@
  *     next synchronisation.
  *   - n == 0 is valid and does nothing.
  *   - Results are deterministic: the same inputs, configuration and tile
- *     table give bitwise-equal outputs (fixed summation orders, no atomics in
- *     any arithmetic).
+ *     table give bitwise-equal outputs (fixed summation orders; the round
+ *     schedule's atomic adds reach each accumulator word once per launch, so
+ *     their order is fixed as well).
  *   - Outputs must not alias inputs except where a parameter is documented as
  *     in/out.
  */
